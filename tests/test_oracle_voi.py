@@ -125,3 +125,25 @@ def test_table1_case1_voi_count_bracket(oracle_lib):
     n = plan.counts().sum()
     ratio = n / (row["n_prime_voxel_1e7"] * 1e7)
     assert 0.4 < ratio <= 1.0
+
+
+def test_default_voi_is_six_beamlet_widths(oracle_lib):
+    """Sec. 2.1: the VOI is a co-axial beamlet whose side is six times the beamlet's.
+
+    With a parallel beam and no explicit cutoff the VOI is a prism of
+    half-widths 3a by 3b around the axis.
+    """
+    g = fi.water_phantom((41, 5, 37), (0.25, 0.5, 0.25))
+    k = fi.default_kernel(0)
+    k.cutoff_u = k.cutoff_v = 0.0
+    a, b = 0.6, 0.35
+    xc, zc = 0.1, -0.32           # no voxel centre exactly on the 3a, 3b boundary
+    beams = [fi.Beam(0.0, (0.0, 0.0, 0.0), 1e6, a, b, 1, 1, xc, zc)]
+    plan = oracle_lib.OraclePlan(fi.Problem("def", g, beams, k))
+    idx, _ = plan.row(0)
+    nx, ny, nz = g.shape_xyz
+    x = g.origin[0] + 0.25 * np.arange(nx)
+    z = g.origin[2] + 0.25 * np.arange(nz)
+    mx = np.abs(x - xc) <= 3 * a + 1e-9
+    mz = np.abs(z - zc) <= 3 * b + 1e-9
+    assert len(idx) == mx.sum() * mz.sum() * ny
