@@ -177,9 +177,11 @@ int32_t ofs_geometry(const ofs_grid *g, const ofs_beam *beams, int32_t n_beams,
                 if (!clip_to_grid(g, bl->S, bl->e, &tA, &tB)) { bl->n = 0; continue; }
                 bl->tA = tA; bl->tB = tB;
                 /* n equally spaced points on AB, both ends included, no further
-                 * apart than the nominal element length */
+                 * apart than the nominal element length (a ratio within 1e-9 of
+                 * an integer counts as that integer, so |AB| = k * nominal gives
+                 * exactly k elements despite rounding in tA and tB) */
                 double L = tB - tA;
-                int32_t segs = (int32_t)ceil(L / nominal);
+                int32_t segs = (int32_t)ceil(L / nominal - 1e-9);
                 if (segs < 1) segs = 1;
                 bl->n = segs + 1;
                 bl->step = L / segs;

@@ -36,7 +36,7 @@ def test_water_depth_is_geometric(oracle_lib, gantries):
         t = tab[off[j]:off[j + 1]]
         L = bl.tB - bl.tA
         assert bl.n >= 2 and abs(bl.step * (bl.n - 1) - L) < 1e-12
-        assert bl.step <= 0.25 + 1e-12
+        assert bl.step <= 0.25 * (1 + 1e-9)
         np.testing.assert_allclose(t, np.minimum(np.arange(bl.n) * bl.step, L), rtol=0, atol=1e-12)
         for tp in np.linspace(bl.tA - 3.0, bl.tB + 3.0, 17):
             d = plan.table_depth(j, t, tp)
