@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark: D_ij nonzeros/s and ms per 9-field plan on one MI355X.
+
+One step = the whole plain path for one plan of the 128^3 slab workload
+(9 coplanar beams 40 deg apart, 30 x 30 beamlets of 0.5 cm, 8100 rows):
+  fspb_plan_create  (FP64 beamlet geometry, VOI row bounds, record upload)
+  fspb_raytrace     (density mask + radiological-depth tables)
+  fspb_dose_coeffs  (count, scan, 8-byte nnz read, fill)
+  fspb_plan_destroy
+The density grid, the output buffers and the workspace are resident in HBM
+before the timed region.  `value` = nonzeros produced per second of
+wall-clock over the K timed steps.
+
+Printed as one JSON line.  Besides the contract fields it carries
+`roofline` (the fill kernel: 8 bytes written per nonzero over its
+HIP-event duration, against 8 TB/s), `cpu_baseline` (the FP64 oracle on a
+bounded sample of the same workload, on this host's cores) and per-kernel
+times.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "D_ij nonzeros/s + ms per 9-field plan; surrogate vs analytic at <=0.5% error"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=1, choices=[1, 2],
+                    help="1: 128^3 slab (default); 2: 256x256x100 pelvis")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target duration of the oracle sample (0 disables)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def traffic_from_profile(kernel_name, workload):
+    """HBM bytes per fill launch from committed rocprofv3 counter summaries, if current."""
+    path = os.path.join(ROOT, "profiles", "fill_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    from paper_0908_4417_amd import build as b
+    if d.get("kernel_source_sha") != b.kernel_source_sha() or d.get("workload") != workload:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, target_s, n_beamlets):
+    """Oracle on a seeded sample of beamlet rows, scaled to nonzeros per second.
+
+    Rows are taken in a seeded random order, 64 at a time (count, then rows,
+    both timed), until about ``target_s`` seconds have passed; memory stays
+    bounded by one chunk.
+    """
+    import oracle
+    ora = oracle.OraclePlan(prob)
+    order = np.random.default_rng(12345).permutation(n_beamlets)
+    nz = 0
+    done = 0
+    t0 = time.perf_counter()
+    while done < n_beamlets and time.perf_counter() - t0 < target_s:
+        sel = np.sort(order[done:done + 64])
+        off, idx, val = ora.rows(sel, ora.counts_of(sel))
+        nz += int(off[-1])
+        done += len(sel)
+    dt = time.perf_counter() - t0
+    return {"value": round(nz / dt, 1), "unit": "D_ij nonzeros/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{done} of {n_beamlets} beamlet rows (seeded order), {nz} nonzeros in {dt:.1f} s; "
+                      f"FP64 C oracle, OpenMP over rows"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the dose-coefficient path "
+              f"shards by beamlet rows across GPUs but this build measures a single MI355X.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import fspb_inputs as fi
+    import paper_0908_4417_amd as m
+    from paper_0908_4417_amd.plan import _structs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    prob = fi.make_config(args.workload)
+    density = torch.from_numpy(prob.grid.density).to(dev)
+    grid, beams, kern, _pdd = _structs(prob, density.data_ptr())
+    nb = len(prob.beams)
+    stream = torch.cuda.current_stream(dev)
+    s = C.c_void_p(stream.cuda_stream)
+
+    # sizes (outside the timed region)
+    st, _, need = m.fspb_plan_create(grid, beams, nb, kern, None, 0)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    wsp = (ws.data_ptr() + 255) // 256 * 256
+    st, h, _ = m.fspb_plan_create(grid, beams, nb, kern, wsp, need)
+    desc = m.fspb_plan_info(h)
+    indptr = torch.empty(desc.n_beamlets + 1, dtype=torch.int64, device=dev)
+    m.fspb_raytrace(h, s)
+    st, nnz = m.fspb_dose_coeffs(h, indptr.data_ptr(), None, None, 0, s)
+    m.fspb_plan_destroy(h)
+    indices = torch.empty(nnz, dtype=torch.int32, device=dev)
+    values = torch.empty(nnz, dtype=torch.float32, device=dev)
+
+    def step(timed):
+        st_, hh, _ = m.fspb_plan_create(grid, beams, nb, kern, wsp, need)
+        if timed:
+            m.fspb_plan_set_timing(hh, 1)
+        m.fspb_raytrace(hh, s)
+        st_, n_ = m.fspb_dose_coeffs(hh, indptr.data_ptr(), indices.data_ptr(), values.data_ptr(), nnz, s)
+        assert st_ == m.FSPB_OK and n_ == nnz
+        t = m.fspb_plan_get_timing(hh) if timed else None
+        m.fspb_plan_destroy(hh)
+        return t
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+
+    # per-kernel device times (HIP events on the launch stream), separate pass
+    times = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    kt = {k: float(np.mean([getattr(t, k) for t in times]))
+          for k in ("prep_ms", "raytrace_ms", "count_ms", "scan_ms", "fill_ms")}
+    fill_s = kt["fill_ms"] * 1e-3
+    alg_bytes = 8.0 * nnz                     # FP32 value + int32 column per nonzero
+    achieved = alg_bytes / fill_s / 1e9
+    workload = fi.CONFIG_NAMES[args.workload]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profile("k_fill", workload),
+                "kernel": "k_fill", "bytes_per_launch": alg_bytes}
+
+    out = {
+        "metric": METRIC,
+        "value": round(nnz * args.steps / wall, 1),
+        "unit": "D_ij nonzeros/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "grid": list(prob.grid.shape_xyz), "beams": nb,
+                   "beamlets": desc.n_beamlets, "nnz": nnz},
+        "roofline": roofline,
+        "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
+        "device_ms_per_plan": round(sum(kt.values()), 4),
+    }
+    if not args.no_cpu_baseline and args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, desc.n_beamlets)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * fspb.h -- dose-deposition coefficients D_ij of a finite-size pencil-beam
+ * (FSPB) model on an AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for every beamlet j of a set of coplanar IMRT beams
+ * and every voxel i inside that beamlet's volume of interest, the coefficient
+ *
+ *     D_ij = A(d) F(u, v, d)                      (Eq. 2 of Gu et al. 2009,
+ *                                                   arXiv:0908.4417)
+ *     A(d) = PDD(d) (SAD / t')^2                   depth dose x inverse square
+ *     F    = sum_k c1_k / 4 [erf((c2_k a/2 - u)/(sqrt2 c3_k(d)))
+ *                            + erf((c2_k a/2 + u)/(sqrt2 c3_k(d)))]
+ *                          [same in v with b]       (Eq. 3, K <= 4 terms)
+ *
+ * and returns them as an FP32 CSR matrix, one row per beamlet, columns =
+ * voxel linear index (iz * ny + iy) * nx + ix in strictly ascending order.
+ *
+ * Geometry (Fig. 1 of the paper; Sec. 2.1 and 2.2):
+ *   - gantry angle g rotates about the patient z axis; the source is at
+ *     S = iso + SAD (sin g, -cos g, 0); the beam's lateral axes are
+ *     eu = (cos g, sin g, 0) and ev = (0, 0, 1);
+ *   - beamlet (iu, iv) of a beam is centred at iso + (u0 + iu a) eu +
+ *     (v0 + iv b) ev on the iso plane; its central axis runs from S through
+ *     that point; row j = (sum of nu*nv over earlier beams) + iv * nu + iu;
+ *   - for a voxel centre P: t' = (P - S).e (distance from S to O', the
+ *     projection of P on the axis), u = (P - S).eu' SAD / t',
+ *     v = (P - S).ev' SAD / t' (iso-plane lateral offsets), where eu' is eu
+ *     made perpendicular to the axis e and ev' = eu' x e;
+ *   - the VOI (Sec. 2.1, last paragraph) is |u| <= cutoff_u, |v| <= cutoff_v
+ *     (default 3a, 3b: a co-axial beamlet six times wider) and density >
+ *     rho_min;
+ *   - the radiological depth d at O' is read by linear interpolation from a
+ *     per-beamlet table of n equally spaced points on AB (A, B = entry and
+ *     exit of the axis through the grid's bounding box; Sec. 2.2), each
+ *     point's depth being the Siddon (1985) path integral of density from A;
+ *     d = 0 before A and d = depth(B) beyond B.
+ *
+ * Units: cm, g/cc relative to water, degrees.
+ *
+ * Conventions for every entry point:
+ *   - all functions return an fspb_status; nothing aborts or throws;
+ *   - arguments are validated before any device work; on error nothing is
+ *     written to caller memory and fspb_last_error() describes the problem;
+ *   - device work is ordered on the caller's stream (a hipStream_t passed as
+ *     void*, NULL = the null stream); the only host synchronisation in the
+ *     plain path is the 8-byte nonzero count read by fspb_dose_coeffs;
+ *   - a plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef FSPB_H
+#define FSPB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fspb_status;
+#define FSPB_OK             0
+#define FSPB_ERR_INVALID   (-1)   /* an argument failed validation */
+#define FSPB_ERR_STATE     (-2)   /* call out of order (e.g. dose before raytrace) */
+#define FSPB_ERR_CAPACITY  (-3)   /* caller buffer too small; the size needed was reported */
+#define FSPB_ERR_HIP       (-4)   /* a HIP runtime call failed */
+#define FSPB_ERR_NOMEM     (-5)   /* host allocation failed */
+#define FSPB_ERR_OVERFLOW  (-6)   /* a replayed batch produced more nonzeros than its buffers */
+
+typedef struct fspb_plan fspb_plan;
+
+/* CT-derived density grid (Sec. 2.2: the CT images and their bounding prism). */
+typedef struct {
+    int32_t nx, ny, nz;          /* voxels per axis, each >= 1, nx*ny*nz < 2^31 */
+    int32_t reserved;            /* must be 0 */
+    double spacing[3];           /* voxel size (cm), each > 0 */
+    double origin[3];            /* centre of voxel (0,0,0) (cm) */
+    const float *density;        /* DEVICE pointer, [nz][ny][nx] x fastest, finite and >= 0.
+                                    BORROWED: must stay valid while the plan lives; its
+                                    contents are read by every fspb_raytrace call. */
+} fspb_grid;
+
+/* One broad beam split into identical beamlets (Sec. 2.1, assumption 1). */
+typedef struct {
+    double gantry_deg;           /* gantry angle (degrees) */
+    double isocenter[3];         /* (cm) */
+    double sad;                  /* source-axis distance (cm), > 0; the source must lie
+                                    outside the grid's bounding box */
+    double beamlet_a, beamlet_b; /* beamlet side lengths at the iso plane along eu, ev (cm) */
+    double u0, v0;               /* iso-plane centre of beamlet (0,0) (cm) */
+    int32_t nu, nv;              /* beamlets along eu and ev, each >= 1 */
+} fspb_beam;
+
+/* FSPB kernel parameters (Eq. 2-3) and VOI / table settings. */
+typedef struct {
+    int32_t n_terms;             /* K, 1..4 (Eq. 3 uses 3) */
+    int32_t n_pdd;               /* entries of pdd, >= 2 */
+    double weight[4];            /* c1_k (finite) */
+    double sigma0[4];            /* c3_k(d) = sigma0_k + sigma_slope_k d; sigma0 > 0 */
+    double sigma_slope[4];       /* >= 0 */
+    double width_scale[4];       /* c2_k > 0 */
+    const float *pdd;            /* HOST pointer: depth dose at depths k * pdd_step; linear
+                                    interpolation, held at the last entry. COPIED at create. */
+    double pdd_step;             /* > 0 (cm) */
+    double cutoff_u, cutoff_v;   /* VOI half-widths at the iso plane; <= 0 selects 3a, 3b */
+    double table_step;           /* nominal depth-table element; <= 0 selects half the
+                                    smallest voxel spacing (Sec. 3.2) */
+    float rho_min;               /* voxels with density <= rho_min are in no VOI */
+    uint32_t flags;              /* must be 0 */
+} fspb_kernel;
+
+/* Static description of a created plan. */
+typedef struct {
+    int32_t n_beamlets;          /* rows of D */
+    int32_t n_voxels;            /* columns of D (nx*ny*nz) */
+    int64_t table_entries;       /* sum of depth-table lengths */
+    int64_t n_tiles;             /* units of work of the count and fill kernels */
+    int32_t max_table;           /* longest depth table */
+    int32_t reserved;
+} fspb_plan_desc;
+
+/*
+ * Create a plan: validate, compute the FP64 beamlet geometry (Fig. 1) on the
+ * host, carve the caller's device workspace and upload the beamlet records
+ * and the depth-dose table.
+ *
+ * workspace        DEVICE pointer of workspace_bytes bytes (256-byte aligned), owned by
+ *                  the caller, kept for the plan's life.  NULL: only *workspace_needed is
+ *                  set and FSPB_ERR_CAPACITY is returned (no plan is created).
+ * workspace_needed HOST out, may be NULL when workspace is given.
+ * out              HOST out: the plan (owns host metadata only).
+ * Errors: INVALID (bad argument), CAPACITY (workspace missing or too small, size
+ * reported), HIP (upload failed), NOMEM.
+ */
+fspb_status fspb_plan_create(const fspb_grid *grid, const fspb_beam *beams, int32_t n_beams,
+                             const fspb_kernel *kernel, void *workspace, size_t workspace_bytes,
+                             size_t *workspace_needed, fspb_plan **out);
+
+/*
+ * Radiological-depth tables (Sec. 2.2): for every beamlet, trace its central
+ * axis from A to B through the density grid (Siddon; crossing parameters in
+ * FP64, path sums in FP32 with compensation) and tabulate the depth at the
+ * table points.  Also derives the density mask (density > rho_min) used by
+ * the VOI test.  Reads the borrowed density; enqueues work on `stream`.
+ */
+fspb_status fspb_raytrace(fspb_plan *plan, void *stream);
+
+/*
+ * D_ij as FP32 CSR (Eq. 2-3 over every beamlet's VOI).  Requires a prior
+ * fspb_raytrace on the plan.
+ *
+ * indptr   DEVICE, n_beamlets + 1 int64 (always written on OK or CAPACITY).
+ * indices  DEVICE, capacity int32 voxel indices; NULL = size query.
+ * values   DEVICE, capacity floats.
+ * nnz_out  HOST out: number of nonzeros.
+ * Returns CAPACITY (after writing indptr and *nnz_out, no values) when indices
+ * or values is NULL or capacity < nnz.  The call synchronises `stream` once to
+ * read the count; the fill is then enqueued without waiting.
+ */
+fspb_status fspb_dose_coeffs(fspb_plan *plan, int64_t *indptr, int32_t *indices, float *values,
+                             int64_t capacity, int64_t *nnz_out, void *stream);
+
+/* Release the plan's host metadata (the workspace stays the caller's). NULL is a no-op. */
+void fspb_plan_destroy(fspb_plan *plan);
+
+/* Static sizes of a plan. */
+fspb_status fspb_plan_info(const fspb_plan *plan, fspb_plan_desc *desc);
+
+/*
+ * Copy the depth tables to HOST memory for inspection: tables gets
+ * desc.table_entries floats, offsets n_beamlets + 1 int64 (row j's table is
+ * tables[offsets[j] .. offsets[j+1])); synchronises `stream`.  Requires a prior
+ * fspb_raytrace.  Either pointer may be NULL.
+ */
+fspb_status fspb_plan_get_tables(fspb_plan *plan, float *tables, int64_t *offsets, void *stream);
+
+/* Device time of the kernels of the most recent fspb_raytrace / fspb_dose_coeffs calls. */
+typedef struct {
+    float prep_ms;               /* density mask and row extents */
+    float raytrace_ms;           /* depth tables */
+    float count_ms;              /* VOI members per tile */
+    float scan_ms;               /* row sums and row pointers */
+    float fill_ms;               /* dose values and CSR columns */
+    int32_t valid;               /* 1 if every interval above was recorded */
+} fspb_timing;
+
+/*
+ * Enable (1) or disable (0) HIP-event timing of the plan's kernels.  When on,
+ * every launch is bracketed by events recorded on the caller's stream.
+ */
+fspb_status fspb_plan_set_timing(fspb_plan *plan, int32_t enable);
+
+/* Wait for the last recorded events and report the intervals (HOST out). */
+fspb_status fspb_plan_get_timing(fspb_plan *plan, fspb_timing *out);
+
+/* Human-readable name of a status code (static storage). */
+const char *fspb_status_string(fspb_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *fspb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSPB_H */

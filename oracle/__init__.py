@@ -102,6 +102,7 @@ def lib():
             "ofs_max_threads": (i32, []),
             "ofs_plan_tables": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(d), P(i64)]),
             "ofs_plan_counts": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(i64)]),
+            "ofs_plan_counts_sel": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(i32), i32, P(i64)]),
             "ofs_plan_rows": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(i32), i32, P(i64),
                                     P(i32), P(d)]),
             "ofs_mlp_nparams": (i32, []),
@@ -176,11 +177,18 @@ class OraclePlan:
                               _ptr(c, C.c_int64))
         return c
 
+    def counts_of(self, sel):
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+        c = np.zeros(len(sel), dtype=np.int64)
+        lib().ofs_plan_counts_sel(C.byref(self.grid), self.beams, self.n_beams, C.byref(self.kernel),
+                                  _ptr(sel, C.c_int32), len(sel), _ptr(c, C.c_int64))
+        return c
+
     def rows(self, sel, counts=None):
         """CSR (indptr, indices int32, values float64) of the selected beamlet rows."""
         sel = np.ascontiguousarray(sel, dtype=np.int32)
         if counts is None:
-            counts = np.array([self.row_count(int(j)) for j in sel], dtype=np.int64)
+            counts = self.counts_of(sel)
         off = np.zeros(len(sel) + 1, dtype=np.int64)
         off[1:] = np.cumsum(counts)
         idx = np.zeros(max(int(off[-1]), 1), dtype=np.int32)

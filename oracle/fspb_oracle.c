@@ -521,6 +521,19 @@ int32_t ofs_plan_counts(const ofs_grid *g, const ofs_beam *beams, int32_t n_beam
     return nb;
 }
 
+/* Nonzeros of the selected beamlet rows sel[0..nsel). */
+int32_t ofs_plan_counts_sel(const ofs_grid *g, const ofs_beam *beams, int32_t n_beams, const ofs_kernel *K,
+                            const int32_t *sel, int32_t nsel, int64_t *counts)
+{
+    int32_t nb = ofs_count_beamlets(beams, n_beams);
+    ofs_beamlet *bl = (ofs_beamlet *)malloc(sizeof(ofs_beamlet) * (size_t)nb);
+    ofs_geometry(g, beams, n_beams, K, bl);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t s = 0; s < nsel; ++s) counts[s] = ofs_beamlet_row(g, K, &bl[sel[s]], NULL, NULL, NULL, 0);
+    free(bl);
+    return nsel;
+}
+
 /*
  * Rows of the selected beamlets (sel[0..nsel)), row sel[s] written at
  * idx/val + off[s]; off has nsel + 1 entries and must come from the counts.

@@ -1,0 +1,36 @@
+"""MI355X-native FSPB dose-deposition coefficients (Gu et al., arXiv:0908.4417).
+
+Thin Python binding over ``libfspb.so`` (C ABI declared in ``include/fspb.h``).
+Every step of the path runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory and streams.
+
+Low level: ``fspb_plan_create``, ``fspb_raytrace``, ``fspb_dose_coeffs``,
+``fspb_plan_destroy``, ``fspb_plan_info``, ``fspb_plan_get_tables`` mirror the
+C functions of the same names.
+
+High level: ``Plan(problem, device)`` owns a torch workspace and returns CSR
+tensors from ``Plan.compute()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._lib import (FSPB_OK, FSPB_ERR_INVALID, FSPB_ERR_STATE, FSPB_ERR_CAPACITY, FSPB_ERR_HIP,
+                   FSPB_ERR_NOMEM, FSPB_ERR_OVERFLOW, FspbError, FspbGrid, FspbBeam, FspbKernel,
+                   FspbPlanDesc, FspbTiming, lib, library_path, EXPORTED,
+                   fspb_plan_create, fspb_raytrace, fspb_dose_coeffs, fspb_plan_destroy,
+                   fspb_plan_info, fspb_plan_get_tables, fspb_plan_set_timing, fspb_plan_get_timing,
+                   fspb_status_string, fspb_last_error)
+from .plan import Plan, CSR
+
+__all__ = [
+    "Plan", "CSR", "FspbError", "lib", "library_path", "EXPORTED",
+    "fspb_plan_create", "fspb_raytrace", "fspb_dose_coeffs", "fspb_plan_destroy",
+    "fspb_plan_info", "fspb_plan_get_tables", "fspb_plan_set_timing", "fspb_plan_get_timing",
+    "fspb_status_string", "fspb_last_error", "FspbTiming",
+    "FSPB_OK", "FSPB_ERR_INVALID", "FSPB_ERR_STATE", "FSPB_ERR_CAPACITY", "FSPB_ERR_HIP",
+    "FSPB_ERR_NOMEM", "FSPB_ERR_OVERFLOW",
+]

@@ -1,0 +1,165 @@
+"""ctypes declarations of the C ABI in ``include/fspb.h``.
+
+Loading fails loudly if ``libfspb.so`` has not been built: there is no other
+implementation behind these names.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libfspb.so")
+
+FSPB_OK = 0
+FSPB_ERR_INVALID = -1
+FSPB_ERR_STATE = -2
+FSPB_ERR_CAPACITY = -3
+FSPB_ERR_HIP = -4
+FSPB_ERR_NOMEM = -5
+FSPB_ERR_OVERFLOW = -6
+
+
+class FspbError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_name(status)}: {message}")
+        self.status = status
+
+
+def status_name(s):
+    return {0: "FSPB_OK", -1: "FSPB_ERR_INVALID", -2: "FSPB_ERR_STATE", -3: "FSPB_ERR_CAPACITY",
+            -4: "FSPB_ERR_HIP", -5: "FSPB_ERR_NOMEM", -6: "FSPB_ERR_OVERFLOW"}.get(s, str(s))
+
+
+class FspbGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("reserved", C.c_int32),
+                ("spacing", C.c_double * 3), ("origin", C.c_double * 3),
+                ("density", C.c_void_p)]
+
+
+class FspbBeam(C.Structure):
+    _fields_ = [("gantry_deg", C.c_double), ("isocenter", C.c_double * 3), ("sad", C.c_double),
+                ("beamlet_a", C.c_double), ("beamlet_b", C.c_double),
+                ("u0", C.c_double), ("v0", C.c_double), ("nu", C.c_int32), ("nv", C.c_int32)]
+
+
+class FspbKernel(C.Structure):
+    _fields_ = [("n_terms", C.c_int32), ("n_pdd", C.c_int32),
+                ("weight", C.c_double * 4), ("sigma0", C.c_double * 4),
+                ("sigma_slope", C.c_double * 4), ("width_scale", C.c_double * 4),
+                ("pdd", C.POINTER(C.c_float)), ("pdd_step", C.c_double),
+                ("cutoff_u", C.c_double), ("cutoff_v", C.c_double), ("table_step", C.c_double),
+                ("rho_min", C.c_float), ("flags", C.c_uint32)]
+
+
+class FspbTiming(C.Structure):
+    _fields_ = [("prep_ms", C.c_float), ("raytrace_ms", C.c_float), ("count_ms", C.c_float),
+                ("scan_ms", C.c_float), ("fill_ms", C.c_float), ("valid", C.c_int32)]
+
+
+class FspbPlanDesc(C.Structure):
+    _fields_ = [("n_beamlets", C.c_int32), ("n_voxels", C.c_int32), ("table_entries", C.c_int64),
+                ("n_tiles", C.c_int64), ("max_table", C.c_int32), ("reserved", C.c_int32)]
+
+
+# name -> (restype, argtypes); every symbol include/fspb.h declares
+_SIGS = {
+    "fspb_plan_create": (C.c_int32, [C.POINTER(FspbGrid), C.POINTER(FspbBeam), C.c_int32,
+                                     C.POINTER(FspbKernel), C.c_void_p, C.c_size_t,
+                                     C.POINTER(C.c_size_t), C.POINTER(C.c_void_p)]),
+    "fspb_raytrace": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fspb_dose_coeffs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.POINTER(C.c_int64), C.c_void_p]),
+    "fspb_plan_destroy": (None, [C.c_void_p]),
+    "fspb_plan_info": (C.c_int32, [C.c_void_p, C.POINTER(FspbPlanDesc)]),
+    "fspb_plan_get_tables": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_plan_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "fspb_plan_get_timing": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fspb_status_string": (C.c_char_p, [C.c_int32]),
+    "fspb_last_error": (C.c_char_p, []),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def library_path():
+    return _LIB
+
+
+def lib():
+    """The loaded HIP library; raises if it was never built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            raise ImportError(f"{_LIB} is missing: build it with paper_0908_4417_amd.build.build() "
+                              "(the HIP library is the only implementation)")
+        L = C.CDLL(_LIB)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != FSPB_OK:
+        raise FspbError(status, lib().fspb_last_error().decode())
+    return status
+
+
+def fspb_status_string(s):
+    return lib().fspb_status_string(s).decode()
+
+
+def fspb_last_error():
+    return lib().fspb_last_error().decode()
+
+
+def fspb_plan_create(grid, beams, n_beams, kernel, workspace, workspace_bytes):
+    """Returns (status, plan handle or None, workspace bytes needed).  No exception on CAPACITY."""
+    need = C.c_size_t(0)
+    handle = C.c_void_p(None)
+    st = lib().fspb_plan_create(C.byref(grid), beams, n_beams, C.byref(kernel), workspace,
+                                workspace_bytes, C.byref(need), C.byref(handle))
+    if st not in (FSPB_OK, FSPB_ERR_CAPACITY):
+        _check(st)
+    return st, (handle.value if st == FSPB_OK else None), need.value
+
+
+def fspb_raytrace(plan, stream):
+    return _check(lib().fspb_raytrace(plan, stream))
+
+
+def fspb_dose_coeffs(plan, indptr, indices, values, capacity, stream):
+    """Returns (status, nnz).  CAPACITY is returned, not raised (size query)."""
+    nnz = C.c_int64(0)
+    st = lib().fspb_dose_coeffs(plan, indptr, indices, values, capacity, C.byref(nnz), stream)
+    if st not in (FSPB_OK, FSPB_ERR_CAPACITY):
+        _check(st)
+    return st, nnz.value
+
+
+def fspb_plan_destroy(plan):
+    lib().fspb_plan_destroy(plan)
+
+
+def fspb_plan_info(plan):
+    d = FspbPlanDesc()
+    _check(lib().fspb_plan_info(plan, C.byref(d)))
+    return d
+
+
+def fspb_plan_get_tables(plan, tables_ptr, offsets_ptr, stream):
+    return _check(lib().fspb_plan_get_tables(plan, tables_ptr, offsets_ptr, stream))
+
+
+def fspb_plan_set_timing(plan, enable):
+    return _check(lib().fspb_plan_set_timing(plan, int(enable)))
+
+
+def fspb_plan_get_timing(plan):
+    t = FspbTiming()
+    _check(lib().fspb_plan_get_timing(plan, C.byref(t)))
+    return t

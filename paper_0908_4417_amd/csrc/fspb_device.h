@@ -1,0 +1,84 @@
+/*
+ * Internal records shared by the host plan code and the gfx950 kernels.
+ * Not part of the public ABI.
+ */
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fspb {
+
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kRowsPerTile = 64;     // grid rows (iy, iz) per count/fill tile: one per lane
+constexpr int kMaxTerms = 4;
+
+/* Per-beamlet record, built in FP64 on the host (Fig. 1 geometry). */
+struct alignas(16) BeamletRec {
+    double S[3];          // source
+    double e[3];          // unit central axis
+    double eu[3], ev[3];  // unit lateral axes (x', z')
+    double tA, tB;        // entry / exit distances from S
+    double step;          // spacing of the table points on AB
+    double sad;
+    double cu_sad, cv_sad;  // cutoff / SAD: |U| <= cu_sad t', |V| <= cv_sad t'
+    float half_a, half_b;   // a/2, b/2 at the iso plane
+    float tA_f, inv_step_f;
+    int32_t n_table;      // table points (0: axis misses the grid)
+    int32_t table_off;    // first entry in the plan's table array
+    int32_t iy0, n_iy;    // bounding rows of the VOI
+    int32_t iz0, n_iz;
+    int32_t tile0;        // first tile (plan-local)
+    int32_t n_tiles;
+};
+
+/* Everything a kernel needs about one plan; lives in device memory. */
+struct alignas(16) PlanDev {
+    // grid
+    int32_t nx, ny, nz, wpr;     // wpr = 32-bit mask words per grid row
+    double org[3], sp[3];
+    double lo[3];                // lower corner of the bounding box
+    const float *density;
+    uint32_t *bits;              // [nz*ny][wpr] density > rho_min
+    int2 *ext;                   // [nz*ny] first / last member column of each grid row
+    float rho_min;
+    // kernel
+    int32_t n_terms, n_pdd;
+    float w4[kMaxTerms];         // c1 / 4
+    float sig0[kMaxTerms], sig1[kMaxTerms];
+    float c2[kMaxTerms];
+    float pdd_inv_step;
+    const float *pdd;
+    // beamlets and tables
+    int32_t n_beamlets, max_table;
+    int32_t ray_iters;           // bound on the per-interval Siddon loop
+    int32_t n_tiles;
+    int32_t max_tiles;           // most tiles of any beamlet
+    int32_t pad0;
+    const BeamletRec *rec;
+    float *tables;
+    const int32_t *tile_beamlet; // [n_tiles]
+    int32_t *tile_count;         // [n_tiles]
+    int64_t *row_nnz;            // [n_beamlets]
+    int64_t *nnz;                // [1]
+};
+
+/* Caller-owned CSR output of one plan (device pointers). */
+struct alignas(16) OutDev {
+    int64_t *indptr;             // n_beamlets + 1
+    int32_t *indices;            // capacity
+    float *values;               // capacity
+    int64_t capacity;
+    int32_t *overflow;           // set to 1 if a fill would exceed capacity
+    int64_t pad;
+};
+
+/* Launchers (fspb_kernels.hip).  Each returns the launch's hipError_t. */
+hipError_t launch_prep(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
+hipError_t launch_raytrace(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
+hipError_t launch_count(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
+hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h,
+                              hipStream_t s);
+hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s);
+
+}  // namespace fspb

@@ -1,0 +1,576 @@
+/*
+ * Host side of the fspb C ABI: argument validation, FP64 beamlet geometry
+ * (Fig. 1 of Gu et al. 2009), VOI row bounds, workspace layout and kernel
+ * launches.  See include/fspb.h for the contract of each entry point.
+ */
+#include "../../include/fspb.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fspb_device.h"
+
+using fspb::BeamletRec;
+using fspb::OutDev;
+using fspb::PlanDev;
+
+namespace fspb {
+size_t fill_shared_bytes(const PlanDev &h);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fspb_status fail(fspb_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+fspb_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(FSPB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define FSPB_HIP(call, what)                              \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, what);  \
+    } while (0)
+
+/* ------------------------------------------------------------ vec3 */
+struct V3 {
+    double x, y, z;
+};
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline V3 unit(V3 a) { return (1.0 / std::sqrt(dot(a, a))) * a; }
+inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+inline void store(V3 a, double *p) { p[0] = a.x; p[1] = a.y; p[2] = a.z; }
+
+bool finite(double v) { return std::isfinite(v); }
+
+constexpr double kPi = 3.14159265358979323846;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+/* Workspace carve: offsets of every device array. */
+struct Layout {
+    size_t plan, out, scal, rec, tile_beamlet, tile_count, row_nnz, tables, pdd, bits, ext, total;
+};
+
+}  // namespace
+
+struct fspb_plan {
+    PlanDev h{};                  // host image of the device record (device pointers inside)
+    OutDev out{};                 // host image of the output record
+    PlanDev *d_plan = nullptr;
+    OutDev *d_out = nullptr;
+    int64_t *d_nnz = nullptr;
+    int32_t *d_overflow = nullptr;
+    std::vector<BeamletRec> recs;
+    std::vector<int32_t> tile_beamlet;
+    int64_t table_entries = 0;
+    int32_t n_voxels = 0;
+    bool traced = false;
+    // optional kernel timing: events bracket prep, raytrace, count, scan, fill
+    bool timing = false;
+    hipEvent_t ev[8] = {};
+    bool have_trace_ev = false, have_dose_ev = false;
+    ~fspb_plan()
+    {
+        for (hipEvent_t &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams, const fspb_kernel *K)
+{
+    if (!g) return fail(FSPB_ERR_INVALID, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(FSPB_ERR_INVALID, "grid dimensions must be >= 1 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+    if ((int64_t)g->nx * g->ny * g->nz >= (int64_t)1 << 31)
+        return fail(FSPB_ERR_INVALID, "grid has 2^31 or more voxels");
+    if (g->reserved != 0) return fail(FSPB_ERR_INVALID, "grid.reserved must be 0");
+    for (int k = 0; k < 3; ++k) {
+        if (!(finite(g->spacing[k]) && g->spacing[k] > 0.0))
+            return fail(FSPB_ERR_INVALID, "grid.spacing[%d] must be finite and > 0", k);
+        if (!finite(g->origin[k])) return fail(FSPB_ERR_INVALID, "grid.origin[%d] is not finite", k);
+    }
+    if (!g->density) return fail(FSPB_ERR_INVALID, "grid.density is NULL");
+    if (!beams) return fail(FSPB_ERR_INVALID, "beams is NULL");
+    if (n_beams < 1) return fail(FSPB_ERR_INVALID, "n_beams must be >= 1");
+    int64_t nbl = 0;
+    const double lo[3] = {g->origin[0] - 0.5 * g->spacing[0], g->origin[1] - 0.5 * g->spacing[1],
+                          g->origin[2] - 0.5 * g->spacing[2]};
+    const int nn[3] = {g->nx, g->ny, g->nz};
+    for (int32_t b = 0; b < n_beams; ++b) {
+        const fspb_beam &B = beams[b];
+        if (!finite(B.gantry_deg) || !finite(B.isocenter[0]) || !finite(B.isocenter[1]) ||
+            !finite(B.isocenter[2]) || !finite(B.u0) || !finite(B.v0))
+            return fail(FSPB_ERR_INVALID, "beam %d: non-finite angle, isocentre or offset", b);
+        if (!(finite(B.sad) && B.sad > 0.0)) return fail(FSPB_ERR_INVALID, "beam %d: sad must be > 0", b);
+        if (!(finite(B.beamlet_a) && B.beamlet_a > 0.0 && finite(B.beamlet_b) && B.beamlet_b > 0.0))
+            return fail(FSPB_ERR_INVALID, "beam %d: beamlet sizes must be > 0", b);
+        if (B.nu < 1 || B.nv < 1) return fail(FSPB_ERR_INVALID, "beam %d: nu and nv must be >= 1", b);
+        nbl += (int64_t)B.nu * B.nv;
+        const double g_rad = B.gantry_deg * kPi / 180.0;
+        const double S[3] = {B.isocenter[0] + B.sad * std::sin(g_rad), B.isocenter[1] - B.sad * std::cos(g_rad),
+                             B.isocenter[2]};
+        bool inside = true;
+        for (int k = 0; k < 3; ++k) inside = inside && S[k] >= lo[k] && S[k] < lo[k] + nn[k] * g->spacing[k];
+        if (inside) return fail(FSPB_ERR_INVALID, "beam %d: the source lies inside the grid", b);
+    }
+    if (nbl >= (int64_t)1 << 28) return fail(FSPB_ERR_INVALID, "too many beamlets (%lld)", (long long)nbl);
+    if (!K) return fail(FSPB_ERR_INVALID, "kernel is NULL");
+    if (K->n_terms < 1 || K->n_terms > fspb::kMaxTerms)
+        return fail(FSPB_ERR_INVALID, "kernel.n_terms must be 1..4 (got %d)", K->n_terms);
+    for (int i = 0; i < K->n_terms; ++i) {
+        if (!finite(K->weight[i])) return fail(FSPB_ERR_INVALID, "kernel.weight[%d] is not finite", i);
+        if (!(finite(K->sigma0[i]) && K->sigma0[i] > 0.0))
+            return fail(FSPB_ERR_INVALID, "kernel.sigma0[%d] must be > 0", i);
+        if (!(finite(K->sigma_slope[i]) && K->sigma_slope[i] >= 0.0))
+            return fail(FSPB_ERR_INVALID, "kernel.sigma_slope[%d] must be >= 0", i);
+        if (!(finite(K->width_scale[i]) && K->width_scale[i] > 0.0))
+            return fail(FSPB_ERR_INVALID, "kernel.width_scale[%d] must be > 0", i);
+    }
+    if (!K->pdd) return fail(FSPB_ERR_INVALID, "kernel.pdd is NULL");
+    if (K->n_pdd < 2 || K->n_pdd > 4096) return fail(FSPB_ERR_INVALID, "kernel.n_pdd must be 2..4096");
+    for (int i = 0; i < K->n_pdd; ++i)
+        if (!std::isfinite(K->pdd[i])) return fail(FSPB_ERR_INVALID, "kernel.pdd[%d] is not finite", i);
+    if (!(finite(K->pdd_step) && K->pdd_step > 0.0)) return fail(FSPB_ERR_INVALID, "kernel.pdd_step must be > 0");
+    if (!finite(K->cutoff_u) || !finite(K->cutoff_v) || !finite(K->table_step))
+        return fail(FSPB_ERR_INVALID, "kernel cutoffs and table_step must be finite");
+    if (!std::isfinite(K->rho_min)) return fail(FSPB_ERR_INVALID, "kernel.rho_min must be finite");
+    if (K->flags != 0) return fail(FSPB_ERR_INVALID, "kernel.flags must be 0");
+    return FSPB_OK;
+}
+
+/* Entry and exit of S + t e through the box [lo, hi) (slab method). */
+bool clip_box(V3 S, V3 e, const double lo[3], const double hi[3], double &tA, double &tB)
+{
+    double t0 = 0.0, t1 = HUGE_VAL;
+    for (int k = 0; k < 3; ++k) {
+        const double s = comp(S, k), d = comp(e, k);
+        if (d == 0.0) {
+            if (s < lo[k] || s >= hi[k]) return false;
+            continue;
+        }
+        double a = (lo[k] - s) / d, b = (hi[k] - s) / d;
+        if (a > b) std::swap(a, b);
+        t0 = std::max(t0, a);
+        t1 = std::min(t1, b);
+    }
+    if (!(t1 > t0)) return false;
+    tA = t0;
+    tB = t1;
+    return true;
+}
+
+/*
+ * Conservative index bounds of the VOI along y and z.  The VOI inside the grid
+ * lies in the pyramid |U| <= cu t'/SAD, |V| <= cv t'/SAD between the smallest
+ * and largest t' of the grid's corners; its 8 corner points bound it.
+ */
+void voi_rows(const fspb_grid *g, V3 S, V3 e, V3 eu, V3 ev, double cu_sad, double cv_sad, int &iy0, int &n_iy,
+              int &iz0, int &n_iz)
+{
+    const double lo[3] = {g->origin[0] - 0.5 * g->spacing[0], g->origin[1] - 0.5 * g->spacing[1],
+                          g->origin[2] - 0.5 * g->spacing[2]};
+    const int nn[3] = {g->nx, g->ny, g->nz};
+    double tmin = HUGE_VAL, tmax = -HUGE_VAL;
+    for (int c = 0; c < 8; ++c) {
+        V3 P = {lo[0] + ((c & 1) ? nn[0] * g->spacing[0] : 0.0), lo[1] + ((c & 2) ? nn[1] * g->spacing[1] : 0.0),
+                lo[2] + ((c & 4) ? nn[2] * g->spacing[2] : 0.0)};
+        const double t = dot(P - S, e);
+        tmin = std::min(tmin, t);
+        tmax = std::max(tmax, t);
+    }
+    n_iy = n_iz = 0;
+    iy0 = iz0 = 0;
+    if (!(tmax > 0.0)) return;
+    tmin = std::max(tmin, 0.0);
+    double bmin[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, bmax[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    for (int c = 0; c < 8; ++c) {
+        const double t = (c & 1) ? tmax : tmin;
+        const double su = (c & 2) ? cu_sad : -cu_sad, sv = (c & 4) ? cv_sad : -cv_sad;
+        V3 P = S + t * (e + su * eu + sv * ev);
+        for (int k = 0; k < 3; ++k) {
+            bmin[k] = std::min(bmin[k], comp(P, k));
+            bmax[k] = std::max(bmax[k], comp(P, k));
+        }
+    }
+    int first[3], last[3];
+    for (int k = 1; k < 3; ++k) {
+        const double a = (bmin[k] - g->origin[k]) / g->spacing[k];
+        const double b = (bmax[k] - g->origin[k]) / g->spacing[k];
+        first[k] = (int)std::max(0.0, std::floor(a) - 1.0);
+        last[k] = (int)std::min((double)nn[k] - 1.0, std::ceil(b) + 1.0);
+    }
+    if (first[1] > last[1] || first[2] > last[2]) return;
+    iy0 = first[1];
+    n_iy = last[1] - first[1] + 1;
+    iz0 = first[2];
+    n_iz = last[2] - first[2] + 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fspb_status_string(fspb_status s)
+{
+    switch (s) {
+    case FSPB_OK: return "FSPB_OK";
+    case FSPB_ERR_INVALID: return "FSPB_ERR_INVALID";
+    case FSPB_ERR_STATE: return "FSPB_ERR_STATE";
+    case FSPB_ERR_CAPACITY: return "FSPB_ERR_CAPACITY";
+    case FSPB_ERR_HIP: return "FSPB_ERR_HIP";
+    case FSPB_ERR_NOMEM: return "FSPB_ERR_NOMEM";
+    case FSPB_ERR_OVERFLOW: return "FSPB_ERR_OVERFLOW";
+    default: return "FSPB_ERR_UNKNOWN";
+    }
+}
+
+const char *fspb_last_error(void) { return g_last_error.c_str(); }
+
+fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams, const fspb_kernel *K,
+                             void *workspace, size_t workspace_bytes, size_t *workspace_needed, fspb_plan **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(FSPB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    fspb_status st = validate(g, beams, n_beams, K);
+    if (st != FSPB_OK) return st;
+    if (!workspace && !workspace_needed)
+        return fail(FSPB_ERR_INVALID, "workspace and workspace_needed are both NULL");
+
+    fspb_plan *p = new (std::nothrow) fspb_plan;
+    if (!p) return fail(FSPB_ERR_NOMEM, "cannot allocate the plan");
+    struct Guard {
+        fspb_plan *p;
+        ~Guard() { delete p; }
+    } guard{p};
+
+    // ---- grid and kernel constants
+    PlanDev &h = p->h;
+    h.nx = g->nx;
+    h.ny = g->ny;
+    h.nz = g->nz;
+    h.wpr = (g->nx + 31) / 32;
+    for (int k = 0; k < 3; ++k) {
+        h.org[k] = g->origin[k];
+        h.sp[k] = g->spacing[k];
+        h.lo[k] = g->origin[k] - 0.5 * g->spacing[k];
+    }
+    double hi[3] = {h.lo[0] + g->nx * g->spacing[0], h.lo[1] + g->ny * g->spacing[1], h.lo[2] + g->nz * g->spacing[2]};
+    h.density = g->density;
+    h.rho_min = K->rho_min;
+    h.n_terms = K->n_terms;
+    h.n_pdd = K->n_pdd;
+    for (int i = 0; i < fspb::kMaxTerms; ++i) {
+        const bool on = i < K->n_terms;
+        h.w4[i] = on ? (float)(0.25 * K->weight[i]) : 0.0f;
+        h.sig0[i] = on ? (float)K->sigma0[i] : 1.0f;
+        h.sig1[i] = on ? (float)K->sigma_slope[i] : 0.0f;
+        h.c2[i] = on ? (float)K->width_scale[i] : 1.0f;
+    }
+    h.pdd_inv_step = (float)(1.0 / K->pdd_step);
+    p->n_voxels = g->nx * g->ny * g->nz;
+
+    // ---- beamlet geometry (FP64)
+    const double minsp = std::min(g->spacing[0], std::min(g->spacing[1], g->spacing[2]));
+    const double nominal = K->table_step > 0.0 ? K->table_step : 0.5 * minsp;
+    int64_t nbl = 0;
+    for (int32_t b = 0; b < n_beams; ++b) nbl += (int64_t)beams[b].nu * beams[b].nv;
+    try {
+        p->recs.resize((size_t)nbl);
+    } catch (...) {
+        return fail(FSPB_ERR_NOMEM, "cannot allocate %lld beamlet records", (long long)nbl);
+    }
+    int64_t table_off = 0, tile_off = 0;
+    int32_t max_table = 2, max_tiles = 0;
+    double max_step = nominal;
+    size_t j = 0;
+    for (int32_t b = 0; b < n_beams; ++b) {
+        const fspb_beam &B = beams[b];
+        const double gr = B.gantry_deg * kPi / 180.0;
+        const V3 iso = {B.isocenter[0], B.isocenter[1], B.isocenter[2]};
+        const V3 S = iso + B.sad * V3{std::sin(gr), -std::cos(gr), 0.0};
+        const V3 beu = {std::cos(gr), std::sin(gr), 0.0};
+        const V3 bev = {0.0, 0.0, 1.0};
+        const double cu = K->cutoff_u > 0.0 ? K->cutoff_u : 3.0 * B.beamlet_a;
+        const double cv = K->cutoff_v > 0.0 ? K->cutoff_v : 3.0 * B.beamlet_b;
+        for (int32_t iv = 0; iv < B.nv; ++iv) {
+            for (int32_t iu = 0; iu < B.nu; ++iu, ++j) {
+                BeamletRec &R = p->recs[j];
+                std::memset(&R, 0, sizeof R);
+                const V3 Q = iso + (B.u0 + iu * B.beamlet_a) * beu + (B.v0 + iv * B.beamlet_b) * bev;
+                const V3 e = unit(Q - S);
+                const V3 eu = unit(beu - dot(beu, e) * e);
+                const V3 ev = cross(eu, e);
+                store(S, R.S);
+                store(e, R.e);
+                store(eu, R.eu);
+                store(ev, R.ev);
+                R.sad = B.sad;
+                R.cu_sad = cu / B.sad;
+                R.cv_sad = cv / B.sad;
+                R.half_a = (float)(0.5 * B.beamlet_a);
+                R.half_b = (float)(0.5 * B.beamlet_b);
+                double tA, tB;
+                if (!clip_box(S, e, h.lo, hi, tA, tB)) continue;   // axis misses: empty row
+                const double L = tB - tA;
+                int32_t segs = (int32_t)std::ceil(L / nominal - 1e-9);
+                if (segs < 1) segs = 1;
+                R.tA = tA;
+                R.tB = tB;
+                R.step = L / segs;
+                R.n_table = segs + 1;
+                R.table_off = (int32_t)table_off;
+                R.tA_f = (float)tA;
+                R.inv_step_f = (float)(1.0 / R.step);
+                table_off += R.n_table;
+                max_table = std::max(max_table, R.n_table);
+                max_step = std::max(max_step, R.step);
+                voi_rows(g, S, e, eu, ev, R.cu_sad, R.cv_sad, R.iy0, R.n_iy, R.iz0, R.n_iz);
+                const int64_t rows = (int64_t)R.n_iy * R.n_iz;
+                R.n_tiles = (int32_t)((rows + fspb::kRowsPerTile - 1) / fspb::kRowsPerTile);
+                R.tile0 = (int32_t)tile_off;
+                tile_off += R.n_tiles;
+                max_tiles = std::max(max_tiles, R.n_tiles);
+            }
+        }
+    }
+    if (table_off >= (int64_t)1 << 31 || tile_off >= (int64_t)1 << 31)
+        return fail(FSPB_ERR_INVALID, "plan too large (%lld table entries, %lld tiles)", (long long)table_off,
+                    (long long)tile_off);
+    try {
+        p->tile_beamlet.resize((size_t)tile_off);
+    } catch (...) {
+        return fail(FSPB_ERR_NOMEM, "cannot allocate the tile map");
+    }
+    for (size_t k = 0; k < p->recs.size(); ++k)
+        for (int32_t t = 0; t < p->recs[k].n_tiles; ++t) p->tile_beamlet[(size_t)p->recs[k].tile0 + t] = (int32_t)k;
+    h.n_beamlets = (int32_t)nbl;
+    h.max_table = max_table;
+    h.n_tiles = (int32_t)tile_off;
+    h.max_tiles = max_tiles;
+    // Siddon steps inside one table interval: crossings per axis plus the final segment
+    h.ray_iters = 2;
+    for (int k = 0; k < 3; ++k) h.ray_iters += (int32_t)std::ceil(max_step / g->spacing[k]) + 1;
+    p->table_entries = table_off;
+    if (fspb::fill_shared_bytes(h) > 64 * 1024)
+        return fail(FSPB_ERR_INVALID, "depth tables too long for the fill kernel's LDS (%zu bytes)",
+                    fspb::fill_shared_bytes(h));
+
+    // ---- workspace layout
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const int64_t grow = (int64_t)g->ny * g->nz;
+    L.plan = take(sizeof(PlanDev));
+    L.out = take(sizeof(OutDev));
+    L.scal = take(64);
+    L.rec = take(sizeof(BeamletRec) * (size_t)nbl);
+    L.tile_beamlet = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
+    L.tile_count = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
+    L.row_nnz = take(sizeof(int64_t) * (size_t)nbl);
+    L.tables = take(sizeof(float) * (size_t)std::max<int64_t>(table_off, 1));
+    L.pdd = take(sizeof(float) * (size_t)K->n_pdd);
+    L.bits = take(sizeof(uint32_t) * (size_t)grow * h.wpr);
+    L.ext = take(sizeof(int2) * (size_t)grow);
+    L.total = off;
+    if (workspace_needed) *workspace_needed = L.total;
+    if (!workspace) return fail(FSPB_ERR_CAPACITY, "workspace query: %zu bytes needed", L.total);
+    if (workspace_bytes < L.total)
+        return fail(FSPB_ERR_CAPACITY, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes,
+                    L.total);
+    if ((uintptr_t)workspace % 256 != 0) return fail(FSPB_ERR_INVALID, "workspace must be 256-byte aligned");
+
+    // density and workspace must be device memory
+    hipPointerAttribute_t attr;
+    for (const void *ptr : {(const void *)g->density, (const void *)workspace}) {
+        hipError_t e = hipPointerGetAttributes(&attr, ptr);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FSPB_ERR_INVALID, "density and workspace must be device pointers (%s)", hipGetErrorString(e));
+        }
+        if (attr.type != hipMemoryTypeDevice)
+            return fail(FSPB_ERR_INVALID, "density and workspace must be device memory");
+    }
+
+    char *ws = static_cast<char *>(workspace);
+    p->d_plan = reinterpret_cast<PlanDev *>(ws + L.plan);
+    p->d_out = reinterpret_cast<OutDev *>(ws + L.out);
+    p->d_nnz = reinterpret_cast<int64_t *>(ws + L.scal);
+    p->d_overflow = reinterpret_cast<int32_t *>(ws + L.scal + 16);
+    h.rec = reinterpret_cast<BeamletRec *>(ws + L.rec);
+    h.tile_beamlet = reinterpret_cast<int32_t *>(ws + L.tile_beamlet);
+    h.tile_count = reinterpret_cast<int32_t *>(ws + L.tile_count);
+    h.row_nnz = reinterpret_cast<int64_t *>(ws + L.row_nnz);
+    h.tables = reinterpret_cast<float *>(ws + L.tables);
+    h.pdd = reinterpret_cast<float *>(ws + L.pdd);
+    h.bits = reinterpret_cast<uint32_t *>(ws + L.bits);
+    h.ext = reinterpret_cast<int2 *>(ws + L.ext);
+    h.nnz = p->d_nnz;
+
+    FSPB_HIP(hipMemcpy(p->d_plan, &h, sizeof(PlanDev), hipMemcpyHostToDevice), "upload plan record");
+    if (nbl > 0)
+        FSPB_HIP(hipMemcpy((void *)h.rec, p->recs.data(), sizeof(BeamletRec) * (size_t)nbl, hipMemcpyHostToDevice),
+                 "upload beamlet records");
+    if (tile_off > 0)
+        FSPB_HIP(hipMemcpy((void *)h.tile_beamlet, p->tile_beamlet.data(), sizeof(int32_t) * (size_t)tile_off,
+                           hipMemcpyHostToDevice),
+                 "upload tile map");
+    FSPB_HIP(hipMemcpy((void *)h.pdd, K->pdd, sizeof(float) * (size_t)K->n_pdd, hipMemcpyHostToDevice),
+             "upload depth dose");
+    FSPB_HIP(hipMemset(p->d_overflow, 0, sizeof(int32_t)), "clear overflow flag");
+    guard.p = nullptr;
+    *out = p;
+    return FSPB_OK;
+}
+
+fspb_status fspb_raytrace(fspb_plan *p, void *stream)
+{
+    g_last_error.clear();
+    if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[0], s), "record event");
+    FSPB_HIP(fspb::launch_prep(p->d_plan, p->h, s), "launch prep");
+    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[1], s), "record event");
+    FSPB_HIP(fspb::launch_raytrace(p->d_plan, p->h, s), "launch raytrace");
+    if (p->timing) {
+        FSPB_HIP(hipEventRecord(p->ev[2], s), "record event");
+        p->have_trace_ev = true;
+    }
+    p->traced = true;
+    return FSPB_OK;
+}
+
+fspb_status fspb_dose_coeffs(fspb_plan *p, int64_t *indptr, int32_t *indices, float *values, int64_t capacity,
+                             int64_t *nnz_out, void *stream)
+{
+    g_last_error.clear();
+    if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
+    if (!indptr) return fail(FSPB_ERR_INVALID, "indptr is NULL");
+    if (!nnz_out) return fail(FSPB_ERR_INVALID, "nnz_out is NULL");
+    if (capacity < 0) return fail(FSPB_ERR_INVALID, "capacity must be >= 0");
+    if (!p->traced) return fail(FSPB_ERR_STATE, "fspb_raytrace must run before fspb_dose_coeffs");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    p->out.indptr = indptr;
+    p->out.indices = indices;
+    p->out.values = values;
+    p->out.capacity = (indices && values) ? capacity : 0;
+    p->out.overflow = p->d_overflow;
+    FSPB_HIP(hipMemcpyAsync(p->d_out, &p->out, sizeof(OutDev), hipMemcpyHostToDevice, s), "upload output record");
+    p->have_dose_ev = false;
+    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[3], s), "record event");
+    FSPB_HIP(fspb::launch_count(p->d_plan, p->h, s), "launch count");
+    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[4], s), "record event");
+    FSPB_HIP(fspb::launch_rowsum_scan(p->d_plan, p->d_out, p->h, s), "launch scan");
+    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[5], s), "record event");
+    int64_t nnz = 0;
+    FSPB_HIP(hipMemcpyAsync(&nnz, p->d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read nnz");
+    FSPB_HIP(hipStreamSynchronize(s), "synchronise for nnz");
+    *nnz_out = nnz;
+    if (!indices || !values || capacity < nnz)
+        return fail(FSPB_ERR_CAPACITY, "%lld nonzeros do not fit a capacity of %lld", (long long)nnz,
+                    (long long)(indices && values ? capacity : 0));
+    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[6], s), "record event");
+    FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, s), "launch fill");
+    if (p->timing) {
+        FSPB_HIP(hipEventRecord(p->ev[7], s), "record event");
+        p->have_dose_ev = true;
+    }
+    return FSPB_OK;
+}
+
+fspb_status fspb_plan_set_timing(fspb_plan *p, int32_t enable)
+{
+    g_last_error.clear();
+    if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
+    if (enable && !p->ev[0])
+        for (hipEvent_t &e : p->ev) FSPB_HIP(hipEventCreate(&e), "create timing event");
+    p->timing = enable != 0;
+    p->have_trace_ev = p->have_dose_ev = false;
+    return FSPB_OK;
+}
+
+fspb_status fspb_plan_get_timing(fspb_plan *p, fspb_timing *t)
+{
+    g_last_error.clear();
+    if (!p || !t) return fail(FSPB_ERR_INVALID, "plan or timing is NULL");
+    std::memset(t, 0, sizeof *t);
+    if (!p->have_trace_ev || !p->have_dose_ev) return FSPB_OK;
+    FSPB_HIP(hipEventSynchronize(p->ev[7]), "wait for timing events");
+    FSPB_HIP(hipEventElapsedTime(&t->prep_ms, p->ev[0], p->ev[1]), "elapsed");
+    FSPB_HIP(hipEventElapsedTime(&t->raytrace_ms, p->ev[1], p->ev[2]), "elapsed");
+    FSPB_HIP(hipEventElapsedTime(&t->count_ms, p->ev[3], p->ev[4]), "elapsed");
+    FSPB_HIP(hipEventElapsedTime(&t->scan_ms, p->ev[4], p->ev[5]), "elapsed");
+    FSPB_HIP(hipEventElapsedTime(&t->fill_ms, p->ev[6], p->ev[7]), "elapsed");
+    t->valid = 1;
+    return FSPB_OK;
+}
+
+void fspb_plan_destroy(fspb_plan *p) { delete p; }
+
+fspb_status fspb_plan_info(const fspb_plan *p, fspb_plan_desc *d)
+{
+    g_last_error.clear();
+    if (!p || !d) return fail(FSPB_ERR_INVALID, "plan or desc is NULL");
+    d->n_beamlets = p->h.n_beamlets;
+    d->n_voxels = p->n_voxels;
+    d->table_entries = p->table_entries;
+    d->n_tiles = p->h.n_tiles;
+    d->max_table = p->h.max_table;
+    d->reserved = 0;
+    return FSPB_OK;
+}
+
+fspb_status fspb_plan_get_tables(fspb_plan *p, float *tables, int64_t *offsets, void *stream)
+{
+    g_last_error.clear();
+    if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
+    if (!p->traced) return fail(FSPB_ERR_STATE, "fspb_raytrace must run before fspb_plan_get_tables");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (offsets) {
+        int64_t acc = 0;
+        for (size_t j = 0; j < p->recs.size(); ++j) {
+            offsets[j] = acc;
+            acc += p->recs[j].n_table;
+        }
+        offsets[p->recs.size()] = acc;
+    }
+    if (tables && p->table_entries > 0) {
+        FSPB_HIP(hipMemcpyAsync(tables, p->h.tables, sizeof(float) * (size_t)p->table_entries, hipMemcpyDeviceToHost, s),
+                 "read tables");
+        FSPB_HIP(hipStreamSynchronize(s), "synchronise tables");
+    }
+    return FSPB_OK;
+}
+
+}  // extern "C"

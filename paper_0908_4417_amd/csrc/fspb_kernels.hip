@@ -1,0 +1,550 @@
+/*
+ * gfx950 kernels of the FSPB dose-coefficient path.
+ *
+ *   k_prep      density mask (one bit per voxel) and per-grid-row extent of
+ *               voxels above rho_min                          -- one wave per grid row
+ *   k_raytrace  radiological-depth table of every beamlet (Sec. 2.2): Siddon
+ *               crossings in FP64, compensated FP32 path sums  -- one wave per beamlet
+ *   k_count     VOI members per tile of 64 grid rows (Sec. 2.1 VOI rule)
+ *                                                              -- one wave per tile
+ *   k_rowsum    nonzeros per beamlet row                       -- one wave per beamlet
+ *   k_scan      exclusive scan -> CSR row pointers              -- one workgroup
+ *   k_fill      Eq. 2-3 at every VOI voxel, compacted with wave ballots into
+ *               ascending CSR columns                          -- one workgroup per beamlet
+ *
+ * The dose arithmetic is FP32; only the ray's plane-crossing parameters and
+ * the per-row VOI interval are FP64.  Count and fill decide membership with
+ * the same code (row_span + mask bit), so the fill writes exactly the counted
+ * number of entries.
+ */
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fspb_device.h"
+
+namespace fspb {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ inline int mbcnt64(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ inline T wave_incl_scan(T x)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T y = __shfl_up(x, d, kWave);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+/* ---------------------------------------------------------------- prep */
+
+__global__ __launch_bounds__(kBlock) void k_prep(const PlanDev *__restrict__ plans)
+{
+    const PlanDev &P = plans[0];
+    const int row = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (row >= P.ny * P.nz) return;
+    const int lane = lane_id();
+    const float *d = P.density + (size_t)row * P.nx;
+    uint32_t *bits = P.bits + (size_t)row * P.wpr;
+    int first = P.nx, last = -1;
+    for (int x0 = 0; x0 < P.nx; x0 += kWave) {
+        const int x = x0 + lane;
+        const bool m = x < P.nx && d[x] > P.rho_min;
+        const uint64_t b = __ballot(m);
+        const int w = (x0 >> 5) + lane;
+        if (lane < 2 && w < P.wpr) bits[w] = lane ? (uint32_t)(b >> 32) : (uint32_t)b;
+        if (b) {
+            first = min(first, x0 + __ffsll((unsigned long long)b) - 1);
+            last = x0 + 63 - __clzll((long long)b);
+        }
+    }
+    if (lane == 0) P.ext[row] = make_int2(first, last);   // first > last: no member voxel
+}
+
+/* ------------------------------------------------------------ raytrace */
+
+/* Compensated FP32 pair: value = s + c. */
+struct cpair { float s, c; };
+
+__device__ inline cpair cp_add(cpair a, cpair b)
+{
+    const float s = a.s + b.s;
+    const float bb = s - a.s;
+    const float e = (a.s - (s - bb)) + (b.s - bb);      // two-sum error
+    return {s, (a.c + b.c) + e};
+}
+
+/*
+ * Path integral of density over [tA + m step, min(tA + (m+1) step, tB)] of
+ * beamlet R's axis: an incremental Siddon walk.  Crossing parameters are
+ * recomputed from integer plane indices (no drift) in FP64; each segment's
+ * voxel is the one holding its midpoint; rho * length is accumulated in FP32
+ * with Neumaier compensation and the product's rounding error added back.
+ */
+__device__ cpair interval_integral(const PlanDev &P, const BeamletRec &R, int m, int n)
+{
+    const double t_end = (m == n - 2) ? R.tB : R.tA + (double)(m + 1) * R.step;
+    double t = R.tA + (double)m * R.step;
+    const int nv[3] = {P.nx, P.ny, P.nz};
+    double an[3], inv_e[3], inv_sp[3];
+    int pn[3], dp[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        inv_sp[k] = 1.0 / P.sp[k];
+        const double e = R.e[k];
+        dp[k] = 0;
+        an[k] = 1e300;
+        inv_e[k] = 0.0;
+        if (e != 0.0) {
+            inv_e[k] = 1.0 / e;
+            const double c = (R.S[k] + t * e - P.lo[k]) * inv_sp[k];
+            int p;
+            if (e > 0.0) {
+                p = (int)floor(c) + 1;
+                dp[k] = 1;
+            } else {
+                p = (int)ceil(c) - 1;
+                dp[k] = -1;
+            }
+            double a = (P.lo[k] + p * P.sp[k] - R.S[k]) * inv_e[k];
+            if (a <= t) {
+                p += dp[k];
+                a = (P.lo[k] + p * P.sp[k] - R.S[k]) * inv_e[k];
+            }
+            pn[k] = p;
+            an[k] = a;
+        }
+    }
+    cpair acc = {0.0f, 0.0f};
+    for (int it = 0; it < P.ray_iters; ++it) {
+        const double tn = fmin(fmin(an[0], an[1]), fmin(an[2], t_end));
+        if (tn > t) {
+            const double mid = 0.5 * (t + tn);
+            int idx[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                int v = (int)floor((R.S[k] + mid * R.e[k] - P.lo[k]) * inv_sp[k]);
+                idx[k] = min(max(v, 0), nv[k] - 1);
+            }
+            const float rho = P.density[((size_t)idx[2] * P.ny + idx[1]) * P.nx + idx[0]];
+            const float len = (float)(tn - t);
+            const float prod = rho * len;
+            const float perr = fmaf(rho, len, -prod);
+            const float s = acc.s + prod;
+            acc.c += (fabsf(acc.s) >= fabsf(prod)) ? ((acc.s - s) + prod) : ((prod - s) + acc.s);
+            acc.c += perr;
+            acc.s = s;
+        }
+        t = tn;
+        if (t >= t_end) break;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (an[k] == tn) {
+                pn[k] += dp[k];
+                an[k] = (P.lo[k] + pn[k] * P.sp[k] - R.S[k]) * inv_e[k];
+            }
+        }
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_raytrace(const PlanDev *__restrict__ plans)
+{
+    const PlanDev &P = plans[0];
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j >= P.n_beamlets) return;
+    const int lane = lane_id();
+    const BeamletRec &R = P.rec[j];
+    const int n = R.n_table;
+    if (n == 0) return;
+    float *tab = P.tables + R.table_off;
+    if (lane == 0) tab[0] = 0.0f;
+    cpair carry = {0.0f, 0.0f};
+    for (int m0 = 0; m0 < n - 1; m0 += kWave) {
+        const int m = m0 + lane;
+        cpair acc = {0.0f, 0.0f};
+        if (m < n - 1) acc = interval_integral(P, R, m, n);
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            cpair y = {__shfl_up(acc.s, d, kWave), __shfl_up(acc.c, d, kWave)};
+            if (lane >= d) acc = cp_add(y, acc);
+        }
+        const cpair tot = cp_add(carry, acc);
+        if (m < n - 1) tab[m + 1] = tot.s + tot.c;
+        const cpair last = {__shfl(acc.s, kWave - 1, kWave), __shfl(acc.c, kWave - 1, kWave)};
+        carry = cp_add(carry, last);
+    }
+}
+
+/* --------------------------------------------------------- VOI per row */
+
+/* FP64 affine coefficients of t', U = (P-S).eu', V = (P-S).ev' along a grid row. */
+struct RowAffine { double t0, U0, V0; };
+
+__device__ inline RowAffine row_affine(const PlanDev &P, const BeamletRec &R, int iy, int iz)
+{
+    const double wx = P.org[0] - R.S[0];
+    const double wy = P.org[1] + iy * P.sp[1] - R.S[1];
+    const double wz = P.org[2] + iz * P.sp[2] - R.S[2];
+    RowAffine a;
+    a.t0 = wx * R.e[0] + wy * R.e[1] + wz * R.e[2];
+    a.U0 = wx * R.eu[0] + wy * R.eu[1] + wz * R.eu[2];
+    a.V0 = wx * R.ev[0] + wy * R.ev[1] + wz * R.ev[2];
+    return a;
+}
+
+/*
+ * Columns [lo, hi] of grid row (iy, iz) whose centres satisfy
+ * |U| <= (cu/SAD) t' and |V| <= (cv/SAD) t' (the VOI, which is convex, so an
+ * interval), intersected with the row's extent of voxels above rho_min.
+ * Solved in FP64 from the four linear inequalities.  Returns false if empty.
+ */
+__device__ inline bool row_span(const PlanDev &P, const BeamletRec &R, int iy, int iz, int &lo, int &hi,
+                                RowAffine &a)
+{
+    a = row_affine(P, R, iy, iz);
+    const double t1 = P.sp[0] * R.e[0];
+    const double U1 = P.sp[0] * R.eu[0];
+    const double V1 = P.sp[0] * R.ev[0];
+    const double c0[4] = {a.U0 - R.cu_sad * a.t0, -a.U0 - R.cu_sad * a.t0,
+                          a.V0 - R.cv_sad * a.t0, -a.V0 - R.cv_sad * a.t0};
+    const double c1[4] = {U1 - R.cu_sad * t1, -U1 - R.cu_sad * t1,
+                          V1 - R.cv_sad * t1, -V1 - R.cv_sad * t1};
+    double xlo = -1.0, xhi = (double)P.nx;          // already clipped to the grid
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {                   // c0 + c1 x <= 0
+        if (c1[c] > 0.0) xhi = fmin(xhi, -c0[c] / c1[c]);
+        else if (c1[c] < 0.0) xlo = fmax(xlo, -c0[c] / c1[c]);
+        else ok = ok && !(c0[c] > 0.0);
+    }
+    const int2 ext = P.ext[iz * P.ny + iy];
+    xlo = fmin(xlo, (double)P.nx);                  // both bounds now in [-1, nx]
+    xhi = fmax(xhi, -1.0);
+    lo = max((int)ceil(xlo), max(ext.x, 0));
+    hi = min((int)floor(xhi), min(ext.y, P.nx - 1));
+    return ok && lo <= hi;
+}
+
+__device__ inline int popcount_range(const uint32_t *row, int lo, int hi)
+{
+    const int w0 = lo >> 5, w1 = hi >> 5;
+    int c = 0;
+    for (int w = w0; w <= w1; ++w) {
+        uint32_t m = row[w];
+        if (w == w0) m &= 0xffffffffu << (lo & 31);
+        if (w == w1) m &= 0xffffffffu >> (31 - (hi & 31));
+        c += __popc(m);
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count(const PlanDev *__restrict__ plans)
+{
+    const PlanDev &P = plans[0];
+    const int t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (t >= P.n_tiles) return;
+    const int lane = lane_id();
+    const BeamletRec &R = P.rec[P.tile_beamlet[t]];
+    const int r = (t - R.tile0) * kRowsPerTile + lane;
+    int cnt = 0;
+    if (r < R.n_iy * R.n_iz) {
+        const int iy = R.iy0 + r % R.n_iy, iz = R.iz0 + r / R.n_iy;
+        int lo, hi;
+        RowAffine a;
+        if (row_span(P, R, iy, iz, lo, hi, a))
+            cnt = popcount_range(P.bits + (size_t)(iz * P.ny + iy) * P.wpr, lo, hi);
+    }
+    cnt = wave_sum(cnt);
+    if (lane == 0) P.tile_count[t] = cnt;
+}
+
+/* ---------------------------------------------------------------- scan */
+
+__global__ __launch_bounds__(kBlock) void k_rowsum(const PlanDev *__restrict__ plans)
+{
+    const PlanDev &P = plans[0];
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j >= P.n_beamlets) return;
+    const BeamletRec &R = P.rec[j];
+    int64_t s = 0;
+    for (int k = lane_id(); k < R.n_tiles; k += kWave) s += P.tile_count[R.tile0 + k];
+    s = wave_sum(s);
+    if (lane_id() == 0) P.row_nnz[j] = s;
+}
+
+constexpr int kScanBlock = 1024;
+
+/* Exclusive scan of row_nnz into indptr[0..n]; indptr[n] = nnz. One workgroup. */
+__global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__ plans,
+                                                      const OutDev *__restrict__ outs)
+{
+    const PlanDev &P = plans[0];
+    int64_t *indptr = outs[0].indptr;
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    __shared__ int64_t carry_s;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < P.n_beamlets; base += kScanBlock) {
+        const int i = base + tid;
+        const int64_t v = i < P.n_beamlets ? P.row_nnz[i] : 0;
+        const int64_t inc = wave_incl_scan(v);
+        if (lane == kWave - 1) wsum[wave] = inc;
+        __syncthreads();
+        int64_t woff = 0;
+        for (int w = 0; w < wave; ++w) woff += wsum[w];
+        const int64_t carry = carry_s;
+        if (i < P.n_beamlets) indptr[i] = carry + woff + inc - v;
+        __syncthreads();
+        if (tid == kScanBlock - 1) carry_s = carry + woff + inc;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        indptr[P.n_beamlets] = carry_s;
+        P.nnz[0] = carry_s;
+    }
+}
+
+/* ---------------------------------------------------------------- fill */
+
+/*
+ * One bracket of Eq. 3 at offset x, half-width h, 1/(sqrt2 sigma) = is.  Both
+ * branches are written with erfc of a non-negative argument: inside the
+ * beamlet 2 - erfc(alpha) - erfc(beta), outside erfc(alpha) - erfc(beta), so
+ * tails keep their relative accuracy.
+ */
+__device__ inline float edge_pair(float x, float h, float is)
+{
+    const float ax = fabsf(x);
+    const float ea = erfcf(fabsf(h - ax) * is);
+    const float eb = erfcf((h + ax) * is);
+    return (ax <= h ? 2.0f - ea : ea) - eb;
+}
+
+struct FillShared {
+    float2 *tab;   // depth table: (d_k, d_{k+1} - d_k)
+    float2 *pdd;   // depth dose: (p_k, p_{k+1} - p_k)
+    int *tpre;     // exclusive prefix of the beamlet's tile counts
+};
+
+__device__ inline float dose_value(const PlanDev &P, const BeamletRec &R, const FillShared &sh,
+                                   float s, float U, float V)
+{
+    const float tp = s + R.tA_f;                    // t' = |SO'|
+    const float g = (float)R.sad * __builtin_amdgcn_rcpf(tp);   // SAD / t'
+    const float u = U * g, v = V * g;
+    // radiological depth at O' (linear interpolation in the table, clamped)
+    const int n = R.n_table;
+    const float tau = fminf(fmaxf(s * R.inv_step_f, 0.0f), (float)(n - 1));
+    const int k = min((int)tau, n - 2);
+    const float2 q = sh.tab[k];
+    const float d = fmaf(tau - (float)k, q.y, q.x);
+    // depth dose
+    const float x = fminf(d * P.pdd_inv_step, (float)(P.n_pdd - 1));
+    const int kp = min((int)x, P.n_pdd - 2);
+    const float2 qp = sh.pdd[kp];
+    const float pdd = fmaf(x - (float)kp, qp.y, qp.x);
+    // lateral profile, Eq. 3
+    float L = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kMaxTerms; ++i) {
+        if (i < P.n_terms) {
+            const float sig = fmaf(P.sig1[i], d, P.sig0[i]);
+            const float is = 0.70710678118654752f * __builtin_amdgcn_rcpf(sig);
+            const float eu = edge_pair(u, P.c2[i] * R.half_a, is);
+            const float ev = edge_pair(v, P.c2[i] * R.half_b, is);
+            L = fmaf(P.w4[i] * eu, ev, L);
+        }
+    }
+    return pdd * g * g * L;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
+                                                  const OutDev *__restrict__ outs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PlanDev &P = plans[0];
+    const OutDev &O = outs[0];
+    const int j = blockIdx.x;
+    const BeamletRec &R = P.rec[j];
+    if (R.n_tiles == 0) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+
+    FillShared sh;
+    sh.tab = reinterpret_cast<float2 *>(smem);
+    sh.pdd = sh.tab + P.max_table;
+    sh.tpre = reinterpret_cast<int *>(sh.pdd + P.n_pdd);
+    __shared__ int wsum[kWavesPerBlock];
+
+    const float *tab = P.tables + R.table_off;
+    for (int i = tid; i < R.n_table; i += kBlock) {
+        const float d0 = tab[i];
+        sh.tab[i] = make_float2(d0, (i + 1 < R.n_table ? tab[i + 1] : d0) - d0);
+    }
+    for (int i = tid; i < P.n_pdd; i += kBlock) {
+        const float p0 = P.pdd[i];
+        sh.pdd[i] = make_float2(p0, (i + 1 < P.n_pdd ? P.pdd[i + 1] : p0) - p0);
+    }
+    // exclusive scan of this beamlet's tile counts
+    int carry = 0;
+    for (int base = 0; base < R.n_tiles; base += kBlock) {
+        const int i = base + tid;
+        const int v = i < R.n_tiles ? P.tile_count[R.tile0 + i] : 0;
+        const int inc = wave_incl_scan(v);
+        if (lane == kWave - 1) wsum[wave] = inc;
+        __syncthreads();
+        int woff = 0;
+        for (int w = 0; w < wave; ++w) woff += wsum[w];
+        if (i < R.n_tiles) sh.tpre[i] = carry + woff + inc - v;
+        int tot = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) tot += wsum[w];
+        carry += tot;
+        __syncthreads();
+    }
+
+    const int64_t row_base = O.indptr[j];
+    const int n_rows = R.n_iy * R.n_iz;
+    const float t1f = (float)(P.sp[0] * R.e[0]);
+    const float U1f = (float)(P.sp[0] * R.eu[0]);
+    const float V1f = (float)(P.sp[0] * R.ev[0]);
+
+    for (int tl = wave; tl < R.n_tiles; tl += kWavesPerBlock) {
+        if (P.tile_count[R.tile0 + tl] == 0) continue;
+        const int64_t out0 = row_base + sh.tpre[tl];
+        // lane = grid row of this tile
+        const int r = tl * kRowsPerTile + lane;
+        int lo = 0, hi = -1, grow = 0;
+        float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
+        if (r < n_rows) {
+            const int iy = R.iy0 + r % R.n_iy, iz = R.iz0 + r / R.n_iy;
+            RowAffine a;
+            if (row_span(P, R, iy, iz, lo, hi, a)) {
+                grow = iz * P.ny + iy;
+                const double x = (double)lo;
+                s_lo = (float)(a.t0 + x * (P.sp[0] * R.e[0]) - R.tA);
+                U_lo = (float)(a.U0 + x * (P.sp[0] * R.eu[0]));
+                V_lo = (float)(a.V0 + x * (P.sp[0] * R.ev[0]));
+            } else {
+                lo = 0;
+                hi = -1;
+            }
+        }
+        const int cnt = hi - lo + 1;
+        const int incl = wave_incl_scan(cnt);
+        const int excl = incl - cnt;
+        const int total = __shfl(incl, kWave - 1, kWave);
+        int running = 0;
+        for (int c0 = 0; c0 < total; c0 += kWave) {
+            const int p = c0 + lane;
+            const bool valid = p < total;
+            // row of candidate p: the last row whose exclusive prefix is <= p
+            int rr = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int e = __shfl(excl, rr + step, kWave);
+                if (e <= p) rr += step;
+            }
+            const int k = p - __shfl(excl, rr, kWave);
+            const int ix = __shfl(lo, rr, kWave) + k;
+            const int gr = __shfl(grow, rr, kWave);
+            const float sl = __shfl(s_lo, rr, kWave);
+            const float ul = __shfl(U_lo, rr, kWave);
+            const float vl = __shfl(V_lo, rr, kWave);
+            bool member = false;
+            if (valid) {
+                const uint32_t wbits = P.bits[(size_t)gr * P.wpr + (ix >> 5)];
+                member = (wbits >> (ix & 31)) & 1u;
+            }
+            const uint64_t mask = __ballot(member);
+            const int slot = running + mbcnt64(mask);
+            running += __popcll(mask);
+            if (member) {
+                const float kf = (float)k;
+                const float D = dose_value(P, R, sh, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                           fmaf(kf, V1f, vl));
+                const int64_t o = out0 + slot;
+                if (o < O.capacity) {
+                    O.indices[o] = gr * P.nx + ix;
+                    O.values[o] = D;
+                } else {
+                    *O.overflow = 1;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+/* ------------------------------------------------------------ launchers */
+
+static inline unsigned blocks_for(int64_t items, int per_block)
+{
+    return (unsigned)((items + per_block - 1) / per_block);
+}
+
+hipError_t launch_prep(const PlanDev *dplan, const PlanDev &h, hipStream_t s)
+{
+    const int64_t rows = (int64_t)h.ny * h.nz;
+    hipLaunchKernelGGL(k_prep, dim3(blocks_for(rows, kWavesPerBlock)), dim3(kBlock), 0, s, dplan);
+    return hipGetLastError();
+}
+
+hipError_t launch_raytrace(const PlanDev *dplan, const PlanDev &h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_raytrace, dim3(blocks_for(h.n_beamlets, kWavesPerBlock)), dim3(kBlock), 0, s,
+                       dplan);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const PlanDev *dplan, const PlanDev &h, hipStream_t s)
+{
+    if (h.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count, dim3(blocks_for(h.n_tiles, kWavesPerBlock)), dim3(kBlock), 0, s, dplan);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rowsum, dim3(blocks_for(h.n_beamlets, kWavesPerBlock)), dim3(kBlock), 0, s,
+                       dplan);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, dplan, dout);
+    return hipGetLastError();
+}
+
+size_t fill_shared_bytes(const PlanDev &h)
+{
+    return sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) + sizeof(int) * ((size_t)h.max_tiles + 1);
+}
+
+hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(h.n_beamlets), dim3(kBlock), fill_shared_bytes(h), s, dplan, dout);
+    return hipGetLastError();
+}
+
+}  // namespace fspb

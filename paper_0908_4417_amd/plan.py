@@ -1,0 +1,116 @@
+"""High-level plan object: torch-owned device buffers around the C ABI."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class CSR:
+    """D_ij with rows = beamlets, columns = voxel linear indices (ascending per row)."""
+    indptr: "torch.Tensor"      # int64 [n_beamlets + 1]
+    indices: "torch.Tensor"     # int32 [nnz]
+    values: "torch.Tensor"      # float32 [nnz]
+    n_voxels: int
+
+    @property
+    def nnz(self):
+        return int(self.indices.numel())
+
+
+def _structs(problem, density_ptr):
+    g = problem.grid
+    nz, ny, nx = g.density.shape
+    grid = L.FspbGrid(nx, ny, nz, 0, (C.c_double * 3)(*g.spacing), (C.c_double * 3)(*g.origin),
+                      C.c_void_p(density_ptr))
+    beams = (L.FspbBeam * len(problem.beams))()
+    for k, b in enumerate(problem.beams):
+        beams[k] = L.FspbBeam(b.gantry_deg, (C.c_double * 3)(*b.isocenter), b.sad, b.beamlet_a,
+                              b.beamlet_b, b.u0, b.v0, b.nu, b.nv)
+    kp = problem.kernel
+    pdd = np.ascontiguousarray(kp.pdd, dtype=np.float32)
+    pad = lambda v: (C.c_double * 4)(*(list(v) + [0.0] * (4 - len(v))))
+    kern = L.FspbKernel(kp.n_terms, len(pdd), pad(kp.weight), pad(kp.sigma0), pad(kp.sigma_slope),
+                        pad(kp.width_scale), pdd.ctypes.data_as(C.POINTER(C.c_float)), kp.pdd_step,
+                        kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min, 0)
+    return grid, beams, kern, pdd
+
+
+class Plan:
+    """One FSPB plan on a GPU.
+
+    ``problem`` is a ``fspb_inputs.Problem`` (or anything with the same
+    fields).  The density is copied to the device once; the plan borrows that
+    tensor, and ``set_density`` may overwrite it in place (same shape) before
+    the next ``raytrace``.
+    """
+
+    def __init__(self, problem, device="cuda:0", density=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if density is None:
+            density = torch.from_numpy(np.ascontiguousarray(problem.grid.density, dtype=np.float32))
+        self.density = density.to(self.device, dtype=torch.float32).contiguous()
+        grid, beams, kern, self._pdd = _structs(problem, self.density.data_ptr())
+        st, _, need = L.fspb_plan_create(grid, beams, len(problem.beams), kern, None, 0)
+        assert st == L.FSPB_ERR_CAPACITY
+        self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        st, handle, _ = L.fspb_plan_create(grid, beams, len(problem.beams), kern, aligned, need)
+        self.handle = handle
+        self.desc = L.fspb_plan_info(handle)
+        self.n_beamlets = self.desc.n_beamlets
+        self.n_voxels = self.desc.n_voxels
+        self.indptr = torch.empty(self.n_beamlets + 1, dtype=torch.int64, device=self.device)
+        self.indices = None
+        self.values = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            L.fspb_plan_destroy(h)
+            self.handle = None
+
+    def _stream(self, stream):
+        s = stream if stream is not None else self.torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def set_density(self, density):
+        self.density.copy_(density)
+
+    def raytrace(self, stream=None):
+        L.fspb_raytrace(self.handle, self._stream(stream))
+
+    def dose_coeffs(self, stream=None):
+        """Count, size the outputs (grown when needed) and fill; returns nnz."""
+        s = self._stream(stream)
+        cap = 0 if self.indices is None else self.indices.numel()
+        st, nnz = L.fspb_dose_coeffs(self.handle, self.indptr.data_ptr(),
+                                     self.indices.data_ptr() if cap else None,
+                                     self.values.data_ptr() if cap else None, cap, s)
+        if st == L.FSPB_ERR_CAPACITY:
+            self.indices = self.torch.empty(max(nnz, 1), dtype=self.torch.int32, device=self.device)
+            self.values = self.torch.empty(max(nnz, 1), dtype=self.torch.float32, device=self.device)
+            st, nnz = L.fspb_dose_coeffs(self.handle, self.indptr.data_ptr(),
+                                         self.indices.data_ptr(), self.values.data_ptr(),
+                                         self.indices.numel(), s)
+        self.nnz = nnz
+        return nnz
+
+    def compute(self, stream=None):
+        self.raytrace(stream)
+        nnz = self.dose_coeffs(stream)
+        return CSR(self.indptr, self.indices[:nnz], self.values[:nnz], self.n_voxels)
+
+    def tables(self, stream=None):
+        """Depth tables copied to host: (float32 values, int64 offsets)."""
+        tab = np.zeros(max(int(self.desc.table_entries), 1), dtype=np.float32)
+        off = np.zeros(self.n_beamlets + 1, dtype=np.int64)
+        L.fspb_plan_get_tables(self.handle, tab.ctypes.data, off.ctypes.data, self._stream(stream))
+        return tab[:int(self.desc.table_entries)], off
