@@ -12,6 +12,9 @@ namespace fspb {
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kRowsPerTile = 64;     // grid rows (iy, iz) per count/fill tile: one per lane
 constexpr int kMaxTerms = 4;
+// erfc on [0, kErfcMax] by piecewise quadratics on kErfcIntervals equal intervals
+constexpr int kErfcIntervals = 512;
+constexpr float kErfcMax = 4.0f;
 
 /* Per-beamlet record, built in FP64 on the host (Fig. 1 geometry). */
 struct alignas(16) BeamletRec {
@@ -49,6 +52,7 @@ struct alignas(16) PlanDev {
     float c2[kMaxTerms];
     float pdd_inv_step;
     const float *pdd;
+    const float4 *erfc_tab;      // [kErfcIntervals] (c0, c1, c2, 0) on each interval
     // beamlets and tables
     int32_t n_beamlets, max_table;
     int32_t ray_iters;           // bound on the per-interval Siddon loop

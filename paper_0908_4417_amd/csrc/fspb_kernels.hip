@@ -329,23 +329,35 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__
 
 /* ---------------------------------------------------------------- fill */
 
+/* erfc(z) for z >= 0 from the LDS table (piecewise quadratic, held at kErfcMax). */
+__device__ inline float erfc_lds(const float4 *__restrict__ tab, float z)
+{
+    constexpr float kScale = kErfcIntervals / kErfcMax;
+    const float x = fminf(z * kScale, (float)kErfcIntervals - 1.0f / 1024.0f);
+    const int k = (int)x;
+    const float f = x - (float)k;
+    const float4 c = tab[k];
+    return fmaf(fmaf(c.z, f, c.y), f, c.x);
+}
+
 /*
  * One bracket of Eq. 3 at offset x, half-width h, 1/(sqrt2 sigma) = is.  Both
  * branches are written with erfc of a non-negative argument: inside the
  * beamlet 2 - erfc(alpha) - erfc(beta), outside erfc(alpha) - erfc(beta), so
  * tails keep their relative accuracy.
  */
-__device__ inline float edge_pair(float x, float h, float is)
+__device__ inline float edge_pair(const float4 *__restrict__ tab, float x, float h, float is)
 {
     const float ax = fabsf(x);
-    const float ea = erfcf(fabsf(h - ax) * is);
-    const float eb = erfcf((h + ax) * is);
+    const float ea = erfc_lds(tab, fabsf(h - ax) * is);
+    const float eb = erfc_lds(tab, (h + ax) * is);
     return (ax <= h ? 2.0f - ea : ea) - eb;
 }
 
 struct FillShared {
     float2 *tab;   // depth table: (d_k, d_{k+1} - d_k)
     float2 *pdd;   // depth dose: (p_k, p_{k+1} - p_k)
+    float4 *erfc;  // erfc quadratics
     int *tpre;     // exclusive prefix of the beamlet's tile counts
 };
 
@@ -373,13 +385,15 @@ __device__ inline float dose_value(const PlanDev &P, const BeamletRec &R, const 
         if (i < P.n_terms) {
             const float sig = fmaf(P.sig1[i], d, P.sig0[i]);
             const float is = 0.70710678118654752f * __builtin_amdgcn_rcpf(sig);
-            const float eu = edge_pair(u, P.c2[i] * R.half_a, is);
-            const float ev = edge_pair(v, P.c2[i] * R.half_b, is);
+            const float eu = edge_pair(sh.erfc, u, P.c2[i] * R.half_a, is);
+            const float ev = edge_pair(sh.erfc, v, P.c2[i] * R.half_b, is);
             L = fmaf(P.w4[i] * eu, ev, L);
         }
     }
     return pdd * g * g * L;
 }
+
+__device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
 __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
                                                   const OutDev *__restrict__ outs)
@@ -393,11 +407,13 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
 
     FillShared sh;
-    sh.tab = reinterpret_cast<float2 *>(smem);
+    sh.erfc = reinterpret_cast<float4 *>(smem);
+    sh.tab = reinterpret_cast<float2 *>(sh.erfc + kErfcIntervals);
     sh.pdd = sh.tab + P.max_table;
     sh.tpre = reinterpret_cast<int *>(sh.pdd + P.n_pdd);
     __shared__ int wsum[kWavesPerBlock];
 
+    for (int i = tid; i < kErfcIntervals; i += kBlock) sh.erfc[i] = P.erfc_tab[i];
     const float *tab = P.tables + R.table_off;
     for (int i = tid; i < R.n_table; i += kBlock) {
         const float d0 = tab[i];
@@ -426,14 +442,13 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
 
     const int64_t row_base = O.indptr[j];
     const int n_rows = R.n_iy * R.n_iz;
-    const float t1f = (float)(P.sp[0] * R.e[0]);
-    const float U1f = (float)(P.sp[0] * R.eu[0]);
-    const float V1f = (float)(P.sp[0] * R.ev[0]);
+    const double t1 = P.sp[0] * R.e[0], u1 = P.sp[0] * R.eu[0], v1 = P.sp[0] * R.ev[0];
+    const float t1f = (float)t1, U1f = (float)u1, V1f = (float)v1;
 
     for (int tl = wave; tl < R.n_tiles; tl += kWavesPerBlock) {
         if (P.tile_count[R.tile0 + tl] == 0) continue;
         const int64_t out0 = row_base + sh.tpre[tl];
-        // lane = grid row of this tile
+        // lane = grid row of this tile: its VOI interval and FP32 start values
         const int r = tl * kRowsPerTile + lane;
         int lo = 0, hi = -1, grow = 0;
         float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
@@ -443,9 +458,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
             if (row_span(P, R, iy, iz, lo, hi, a)) {
                 grow = iz * P.ny + iy;
                 const double x = (double)lo;
-                s_lo = (float)(a.t0 + x * (P.sp[0] * R.e[0]) - R.tA);
-                U_lo = (float)(a.U0 + x * (P.sp[0] * R.eu[0]));
-                V_lo = (float)(a.V0 + x * (P.sp[0] * R.ev[0]));
+                s_lo = (float)(a.t0 + x * t1 - R.tA);
+                U_lo = (float)(a.U0 + x * u1);
+                V_lo = (float)(a.V0 + x * v1);
             } else {
                 lo = 0;
                 hi = -1;
@@ -455,23 +470,23 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
         const int incl = wave_incl_scan(cnt);
         const int excl = incl - cnt;
         const int total = __shfl(incl, kWave - 1, kWave);
+        // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
+        // rows are walked once, wave-uniformly, as the chunks advance
+        int rcur = 0;
         int running = 0;
         for (int c0 = 0; c0 < total; c0 += kWave) {
+            while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
             const int p = c0 + lane;
-            const bool valid = p < total;
-            // row of candidate p: the last row whose exclusive prefix is <= p
-            int rr = 0;
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1) {
-                const int e = __shfl(excl, rr + step, kWave);
-                if (e <= p) rr += step;
+            int rr = rcur;
+            for (int q = rcur + 1; q < kWave; ++q) {
+                const int eq = readlane(excl, q);
+                if (eq > c0 + kWave - 1) break;
+                if (p >= eq) rr = q;
             }
+            const bool valid = p < total;
             const int k = p - __shfl(excl, rr, kWave);
             const int ix = __shfl(lo, rr, kWave) + k;
             const int gr = __shfl(grow, rr, kWave);
-            const float sl = __shfl(s_lo, rr, kWave);
-            const float ul = __shfl(U_lo, rr, kWave);
-            const float vl = __shfl(V_lo, rr, kWave);
             bool member = false;
             if (valid) {
                 const uint32_t wbits = P.bits[(size_t)gr * P.wpr + (ix >> 5)];
@@ -480,10 +495,12 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
             const uint64_t mask = __ballot(member);
             const int slot = running + mbcnt64(mask);
             running += __popcll(mask);
+            const float sl = __shfl(s_lo, rr, kWave);
+            const float ul = __shfl(U_lo, rr, kWave);
+            const float vl = __shfl(V_lo, rr, kWave);
             if (member) {
                 const float kf = (float)k;
-                const float D = dose_value(P, R, sh, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
-                                           fmaf(kf, V1f, vl));
+                const float D = dose_value(P, R, sh, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
                 const int64_t o = out0 + slot;
                 if (o < O.capacity) {
                     O.indices[o] = gr * P.nx + ix;
@@ -538,7 +555,8 @@ hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const Pl
 
 size_t fill_shared_bytes(const PlanDev &h)
 {
-    return sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) + sizeof(int) * ((size_t)h.max_tiles + 1);
+    return sizeof(float4) * kErfcIntervals + sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) +
+           sizeof(int) * ((size_t)h.max_tiles + 1);
 }
 
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)
