@@ -27,6 +27,10 @@ struct alignas(16) BeamletRec {
     double cu_sad, cv_sad;  // cutoff / SAD: |U| <= cu_sad t', |V| <= cv_sad t'
     float half_a, half_b;   // a/2, b/2 at the iso plane
     float tA_f, inv_step_f;
+    float sad_f, tau_max_f;   // SAD; n_table - 1
+    float t1_f, U1_f, V1_f;   // change of t', U, V per voxel step along x
+    float pad_f;
+    float ha[kMaxTerms], hb[kMaxTerms];   // c2_k a/2, c2_k b/2
     int32_t n_table;      // table points (0: axis misses the grid)
     int32_t table_off;    // first entry in the plan's table array
     int32_t iy0, n_iy;    // bounding rows of the VOI
@@ -50,7 +54,7 @@ struct alignas(16) PlanDev {
     float w4[kMaxTerms];         // c1 / 4
     float sig0[kMaxTerms], sig1[kMaxTerms];
     float c2[kMaxTerms];
-    float pdd_inv_step;
+    float pdd_inv_step, pdd_max;   // 1/step; n_pdd - 1
     const float *pdd;
     const float4 *erfc_tab;      // [kErfcIntervals] (c0, c1, c2, 0) on each interval
     // beamlets and tables

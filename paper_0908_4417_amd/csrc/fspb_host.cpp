@@ -314,6 +314,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
         h.c2[i] = on ? (float)K->width_scale[i] : 1.0f;
     }
     h.pdd_inv_step = (float)(1.0 / K->pdd_step);
+    h.pdd_max = (float)(K->n_pdd - 1);
     p->n_voxels = g->nx * g->ny * g->nz;
 
     // ---- beamlet geometry (FP64)
@@ -368,6 +369,16 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
                 R.table_off = (int32_t)table_off;
                 R.tA_f = (float)tA;
                 R.inv_step_f = (float)(1.0 / R.step);
+                R.sad_f = (float)B.sad;
+                R.tau_max_f = (float)(R.n_table - 1);
+                R.t1_f = (float)(g->spacing[0] * e.x);
+                R.U1_f = (float)(g->spacing[0] * eu.x);
+                R.V1_f = (float)(g->spacing[0] * ev.x);
+                for (int i = 0; i < fspb::kMaxTerms; ++i) {
+                    const double c2 = i < K->n_terms ? K->width_scale[i] : 1.0;
+                    R.ha[i] = (float)(0.5 * c2 * B.beamlet_a);
+                    R.hb[i] = (float)(0.5 * c2 * B.beamlet_b);
+                }
                 table_off += R.n_table;
                 max_table = std::max(max_table, R.n_table);
                 max_step = std::max(max_step, R.step);

@@ -329,136 +329,176 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__
 
 /* ---------------------------------------------------------------- fill */
 
-/* erfc(z) for z >= 0 from the LDS table (piecewise quadratic, held at kErfcMax). */
-__device__ inline float erfc_lds(const float4 *__restrict__ tab, float z)
+/* Global-address-space views of pointers read from plan records (global_* instead of flat_*). */
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ inline gptr<T> as_global(T *p)
 {
-    constexpr float kScale = kErfcIntervals / kErfcMax;
-    const float x = fminf(z * kScale, (float)kErfcIntervals - 1.0f / 1024.0f);
-    const int k = (int)x;
-    const float f = x - (float)k;
+    return (gptr<T>)(p);
+}
+
+/*
+ * erfc(z / kScale) for a table coordinate x = z kScale >= 0: piecewise
+ * quadratic from LDS, held at the last interval's end.
+ */
+__device__ inline float erfc_lds(const float4 *__restrict__ tab, float x)
+{
+    const float xc = fminf(x, (float)kErfcIntervals - 1.0f / 1024.0f);
+    const int k = (int)xc;
+    const float f = __builtin_amdgcn_fractf(xc);
     const float4 c = tab[k];
     return fmaf(fmaf(c.z, f, c.y), f, c.x);
 }
 
 /*
- * One bracket of Eq. 3 at offset x, half-width h, 1/(sqrt2 sigma) = is.  Both
- * branches are written with erfc of a non-negative argument: inside the
- * beamlet 2 - erfc(alpha) - erfc(beta), outside erfc(alpha) - erfc(beta), so
- * tails keep their relative accuracy.
+ * One bracket of Eq. 3, erf((h - x) is) + erf((h + x) is), with
+ * is = 1/(sqrt2 sigma) and both arguments pre-multiplied by the table scale
+ * (isk = is * kScale).  Written with erfc of non-negative arguments: inside
+ * the beamlet 2 - erfc(alpha) - erfc(beta), outside erfc(alpha) - erfc(beta),
+ * so tails keep their relative accuracy.
  */
-__device__ inline float edge_pair(const float4 *__restrict__ tab, float x, float h, float is)
+__device__ inline float edge_pair(const float4 *__restrict__ tab, float ax, float h, float isk)
 {
-    const float ax = fabsf(x);
-    const float ea = erfc_lds(tab, fabsf(h - ax) * is);
-    const float eb = erfc_lds(tab, (h + ax) * is);
+    const float hk = h * isk;
+    const float ea = erfc_lds(tab, fabsf(fmaf(-ax, isk, hk)));
+    const float eb = erfc_lds(tab, fmaf(ax, isk, hk));
     return (ax <= h ? 2.0f - ea : ea) - eb;
 }
 
-struct FillShared {
-    float2 *tab;   // depth table: (d_k, d_{k+1} - d_k)
-    float2 *pdd;   // depth dose: (p_k, p_{k+1} - p_k)
-    float4 *erfc;  // erfc quadratics
-    int *tpre;     // exclusive prefix of the beamlet's tile counts
+/* Per-beamlet constants of the fill, held in registers. */
+template <int K>
+struct FillConst {
+    float sad, tA, inv_step, tau_max, pdd_inv, pdd_max;
+    float w4[K], sig0[K], sig1[K], ha[K], hb[K];
 };
 
-__device__ inline float dose_value(const PlanDev &P, const BeamletRec &R, const FillShared &sh,
+template <int K>
+__device__ inline float dose_value(const FillConst<K> &c, const float2 *__restrict__ tab,
+                                   const float2 *__restrict__ pdd, const float4 *__restrict__ etab,
                                    float s, float U, float V)
 {
-    const float tp = s + R.tA_f;                    // t' = |SO'|
-    const float g = (float)R.sad * __builtin_amdgcn_rcpf(tp);   // SAD / t'
-    const float u = U * g, v = V * g;
-    // radiological depth at O' (linear interpolation in the table, clamped)
-    const int n = R.n_table;
-    const float tau = fminf(fmaxf(s * R.inv_step_f, 0.0f), (float)(n - 1));
-    const int k = min((int)tau, n - 2);
-    const float2 q = sh.tab[k];
-    const float d = fmaf(tau - (float)k, q.y, q.x);
-    // depth dose
-    const float x = fminf(d * P.pdd_inv_step, (float)(P.n_pdd - 1));
-    const int kp = min((int)x, P.n_pdd - 2);
-    const float2 qp = sh.pdd[kp];
-    const float pdd = fmaf(x - (float)kp, qp.y, qp.x);
+    constexpr float kIsScale = 0.70710678118654752f * (float)kErfcIntervals / kErfcMax;
+    const float tp = s + c.tA;                      // t' = |SO'|
+    const float g = c.sad * __builtin_amdgcn_rcpf(tp);   // SAD / t'
+    const float au = fabsf(U * g), av = fabsf(V * g);
+    // radiological depth at O': linear interpolation in the table (last entry has slope 0)
+    const float tau = __builtin_amdgcn_fmed3f(s * c.inv_step, 0.0f, c.tau_max);
+    const float2 q = tab[(int)tau];
+    const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
+    // depth dose, held at the last node
+    const float x = fminf(d * c.pdd_inv, c.pdd_max);
+    const float2 qp = pdd[(int)x];
+    const float A = fmaf(__builtin_amdgcn_fractf(x), qp.y, qp.x) * g * g;
     // lateral profile, Eq. 3
     float L = 0.0f;
 #pragma unroll
-    for (int i = 0; i < kMaxTerms; ++i) {
-        if (i < P.n_terms) {
-            const float sig = fmaf(P.sig1[i], d, P.sig0[i]);
-            const float is = 0.70710678118654752f * __builtin_amdgcn_rcpf(sig);
-            const float eu = edge_pair(sh.erfc, u, P.c2[i] * R.half_a, is);
-            const float ev = edge_pair(sh.erfc, v, P.c2[i] * R.half_b, is);
-            L = fmaf(P.w4[i] * eu, ev, L);
-        }
+    for (int i = 0; i < K; ++i) {
+        const float isk = kIsScale * __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
+        const float eu = edge_pair(etab, au, c.ha[i], isk);
+        const float ev = edge_pair(etab, av, c.hb[i], isk);
+        L = fmaf(c.w4[i] * eu, ev, L);
     }
-    return pdd * g * g * L;
+    return A * L;
 }
 
 __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+template <int K>
 __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const PlanDev &P = plans[0];
-    const OutDev &O = outs[0];
     const int j = blockIdx.x;
     const BeamletRec &R = P.rec[j];
-    if (R.n_tiles == 0) return;
+    const int n_tiles = R.n_tiles;
+    if (n_tiles == 0) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
 
-    FillShared sh;
-    sh.erfc = reinterpret_cast<float4 *>(smem);
-    sh.tab = reinterpret_cast<float2 *>(sh.erfc + kErfcIntervals);
-    sh.pdd = sh.tab + P.max_table;
-    sh.tpre = reinterpret_cast<int *>(sh.pdd + P.n_pdd);
+    // ---- constants into registers
+    const int n_table = R.n_table, n_pdd = P.n_pdd, tile0 = R.tile0;
+    const int iy0 = R.iy0, n_iy = R.n_iy, iz0 = R.iz0, n_rows = R.n_iy * R.n_iz;
+    const int nx = P.nx, ny = P.ny, wpr = P.wpr;
+    FillConst<K> c;
+    c.sad = R.sad_f;
+    c.tA = R.tA_f;
+    c.inv_step = R.inv_step_f;
+    c.tau_max = R.tau_max_f;
+    c.pdd_inv = P.pdd_inv_step;
+    c.pdd_max = P.pdd_max;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        c.w4[i] = P.w4[i];
+        c.sig0[i] = P.sig0[i];
+        c.sig1[i] = P.sig1[i];
+        c.ha[i] = R.ha[i];
+        c.hb[i] = R.hb[i];
+    }
+    const double tA = R.tA;
+    const double t1 = P.sp[0] * R.e[0], u1 = P.sp[0] * R.eu[0], v1 = P.sp[0] * R.ev[0];
+    const float t1f = R.t1_f, U1f = R.U1_f, V1f = R.V1_f;
+    const gptr<const uint32_t> bits = as_global<const uint32_t>(P.bits);
+    const gptr<const int32_t> tile_count = as_global<const int32_t>(P.tile_count);
+    const OutDev &O = outs[0];
+    const gptr<int32_t> out_idx = as_global<int32_t>(O.indices);
+    const gptr<float> out_val = as_global<float>(O.values);
+    const int64_t capacity = O.capacity;
+    const int64_t row_base = O.indptr[j];
+
+    // ---- LDS: erfc table, depth table, depth dose, tile prefix
+    float4 *s_erfc = reinterpret_cast<float4 *>(smem);
+    float2 *s_tab = reinterpret_cast<float2 *>(s_erfc + kErfcIntervals);
+    float2 *s_pdd = s_tab + P.max_table;
+    int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
     __shared__ int wsum[kWavesPerBlock];
 
-    for (int i = tid; i < kErfcIntervals; i += kBlock) sh.erfc[i] = P.erfc_tab[i];
-    const float *tab = P.tables + R.table_off;
-    for (int i = tid; i < R.n_table; i += kBlock) {
-        const float d0 = tab[i];
-        sh.tab[i] = make_float2(d0, (i + 1 < R.n_table ? tab[i + 1] : d0) - d0);
-    }
-    for (int i = tid; i < P.n_pdd; i += kBlock) {
-        const float p0 = P.pdd[i];
-        sh.pdd[i] = make_float2(p0, (i + 1 < P.n_pdd ? P.pdd[i + 1] : p0) - p0);
+    {
+        const float4 *et = P.erfc_tab;
+        for (int i = tid; i < kErfcIntervals; i += kBlock) s_erfc[i] = et[i];
+        const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
+        for (int i = tid; i < n_table; i += kBlock) {
+            const float d0 = tab[i];
+            s_tab[i] = make_float2(d0, (i + 1 < n_table ? tab[i + 1] : d0) - d0);
+        }
+        const gptr<const float> pd = as_global<const float>(P.pdd);
+        for (int i = tid; i < n_pdd; i += kBlock) {
+            const float p0 = pd[i];
+            s_pdd[i] = make_float2(p0, (i + 1 < n_pdd ? pd[i + 1] : p0) - p0);
+        }
     }
     // exclusive scan of this beamlet's tile counts
     int carry = 0;
-    for (int base = 0; base < R.n_tiles; base += kBlock) {
+    for (int base = 0; base < n_tiles; base += kBlock) {
         const int i = base + tid;
-        const int v = i < R.n_tiles ? P.tile_count[R.tile0 + i] : 0;
+        const int v = i < n_tiles ? tile_count[tile0 + i] : 0;
         const int inc = wave_incl_scan(v);
         if (lane == kWave - 1) wsum[wave] = inc;
         __syncthreads();
         int woff = 0;
         for (int w = 0; w < wave; ++w) woff += wsum[w];
-        if (i < R.n_tiles) sh.tpre[i] = carry + woff + inc - v;
+        if (i < n_tiles) s_tpre[i] = carry + woff + inc - v;
         int tot = 0;
         for (int w = 0; w < kWavesPerBlock; ++w) tot += wsum[w];
         carry += tot;
         __syncthreads();
     }
 
-    const int64_t row_base = O.indptr[j];
-    const int n_rows = R.n_iy * R.n_iz;
-    const double t1 = P.sp[0] * R.e[0], u1 = P.sp[0] * R.eu[0], v1 = P.sp[0] * R.ev[0];
-    const float t1f = (float)t1, U1f = (float)u1, V1f = (float)v1;
-
-    for (int tl = wave; tl < R.n_tiles; tl += kWavesPerBlock) {
-        if (P.tile_count[R.tile0 + tl] == 0) continue;
-        const int64_t out0 = row_base + sh.tpre[tl];
+    for (int tl = wave; tl < n_tiles; tl += kWavesPerBlock) {
+        if (tile_count[tile0 + tl] == 0) continue;
+        const int64_t out0 = row_base + s_tpre[tl];
         // lane = grid row of this tile: its VOI interval and FP32 start values
         const int r = tl * kRowsPerTile + lane;
         int lo = 0, hi = -1, grow = 0;
         float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
         if (r < n_rows) {
-            const int iy = R.iy0 + r % R.n_iy, iz = R.iz0 + r / R.n_iy;
+            const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
             RowAffine a;
             if (row_span(P, R, iy, iz, lo, hi, a)) {
-                grow = iz * P.ny + iy;
+                grow = iz * ny + iy;
                 const double x = (double)lo;
-                s_lo = (float)(a.t0 + x * t1 - R.tA);
+                s_lo = (float)(a.t0 + x * t1 - tA);
                 U_lo = (float)(a.U0 + x * u1);
                 V_lo = (float)(a.V0 + x * v1);
             } else {
@@ -473,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
         // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
         // rows are walked once, wave-uniformly, as the chunks advance
         int rcur = 0;
-        int running = 0;
+        int64_t written = out0;
         for (int c0 = 0; c0 < total; c0 += kWave) {
             while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
             const int p = c0 + lane;
@@ -483,32 +523,32 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
                 if (eq > c0 + kWave - 1) break;
                 if (p >= eq) rr = q;
             }
-            const bool valid = p < total;
             const int k = p - __shfl(excl, rr, kWave);
             const int ix = __shfl(lo, rr, kWave) + k;
             const int gr = __shfl(grow, rr, kWave);
             bool member = false;
-            if (valid) {
-                const uint32_t wbits = P.bits[(size_t)gr * P.wpr + (ix >> 5)];
-                member = (wbits >> (ix & 31)) & 1u;
-            }
+            if (p < total) member = (bits[(uint32_t)(gr * wpr) + ((uint32_t)ix >> 5)] >> (ix & 31)) & 1u;
             const uint64_t mask = __ballot(member);
-            const int slot = running + mbcnt64(mask);
-            running += __popcll(mask);
+            const uint32_t slot = (uint32_t)mbcnt64(mask);
             const float sl = __shfl(s_lo, rr, kWave);
             const float ul = __shfl(U_lo, rr, kWave);
             const float vl = __shfl(V_lo, rr, kWave);
+            // this chunk's entries go to [written, written + popcount); the base is wave-uniform
+            const gptr<int32_t> ip = out_idx + written;
+            const gptr<float> vp = out_val + written;
+            const bool room = written + kWave <= capacity;
             if (member) {
                 const float kf = (float)k;
-                const float D = dose_value(P, R, sh, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
-                const int64_t o = out0 + slot;
-                if (o < O.capacity) {
-                    O.indices[o] = gr * P.nx + ix;
-                    O.values[o] = D;
+                const float D = dose_value<K>(c, s_tab, s_pdd, s_erfc, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                              fmaf(kf, V1f, vl));
+                if (room || written + slot < capacity) {
+                    ip[slot] = gr * nx + ix;
+                    vp[slot] = D;
                 } else {
                     *O.overflow = 1;
                 }
             }
+            written += __popcll(mask);
         }
     }
 }
@@ -561,7 +601,14 @@ size_t fill_shared_bytes(const PlanDev &h)
 
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill, dim3(h.n_beamlets), dim3(kBlock), fill_shared_bytes(h), s, dplan, dout);
+    const dim3 grid(h.n_beamlets), block(kBlock);
+    const size_t lds = fill_shared_bytes(h);
+    switch (h.n_terms) {
+    case 1: hipLaunchKernelGGL(k_fill<1>, grid, block, lds, s, dplan, dout); break;
+    case 2: hipLaunchKernelGGL(k_fill<2>, grid, block, lds, s, dplan, dout); break;
+    case 3: hipLaunchKernelGGL(k_fill<3>, grid, block, lds, s, dplan, dout); break;
+    default: hipLaunchKernelGGL(k_fill<4>, grid, block, lds, s, dplan, dout); break;
+    }
     return hipGetLastError();
 }
 
