@@ -40,8 +40,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=1, choices=[1, 2],
-                    help="1: 128^3 slab (default); 2: 256x256x100 pelvis")
+    ap.add_argument("--workload", type=int, default=1, choices=[1, 2, 3],
+                    help="1: 128^3 slab (default); 2: 256x256x100 pelvis; "
+                         "3: 32 uneven plans as one captured graph")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -103,6 +104,48 @@ def cpu_baseline(prob, target_s, n_beamlets):
                       f"FP64 C oracle, OpenMP over rows"}
 
 
+def bench_batch(args):
+    """32 plans of uneven size, computed by one graph launch per step."""
+    import torch
+    import fspb_inputs as fi
+    from paper_0908_4417_amd import Plan, Batch
+    probs = fi.batched_configs(n_plans=32)
+    plans = [Plan(p, "cuda:0") for p in probs]
+    batch = Batch(plans)
+    cfg = batch.tune()
+    total = int(sum(batch.nnz))
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        batch.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert batch.check() == 0
+    dev_ms = e0.elapsed_time(e1) / args.steps
+    achieved = 8.0 * total / (cfg.fill_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(total * args.steps / wall, 1), "unit": "D_ij nonzeros/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": fi.CONFIG_NAMES[3], "plans": len(plans),
+                   "beamlets": int(sum(p.n_beamlets for p in plans)), "nnz": total},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "kp_fill",
+                     "bytes_per_launch": 8.0 * total},
+        "graph_device_ms": round(dev_ms, 4),
+        "tuned_fill": {"waves_per_group": cfg.waves_per_group, "groups_per_cu": cfg.groups_per_cu,
+                       "order": "longest-first" if cfg.order == 0 else "plan", "fill_ms": round(cfg.fill_ms, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -113,6 +156,9 @@ def main():
               f"shards by beamlet rows across GPUs but this build measures a single MI355X.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == 3:
+        bench_batch(args)
+        return
     import torch
     import fspb_inputs as fi
     import paper_0908_4417_amd as m

@@ -191,6 +191,80 @@ fspb_status fspb_plan_set_timing(fspb_plan *plan, int32_t enable);
 /* Wait for the last recorded events and report the intervals (HOST out). */
 fspb_status fspb_plan_get_timing(fspb_plan *plan, fspb_timing *out);
 
+/* ------------------------------------------------------------------------
+ * Batches: many plans (uneven grids, beams, beamlet sizes) computed by one
+ * captured HIP graph of persistent kernels.  Each stage (mask, depth tables,
+ * counts, row sums, row pointers, fill) is one launch over all plans; the
+ * fill pulls (plan, beamlet) work items from a device queue, longest rows
+ * first.  Output sizes are fixed by a counting pass at creation, so a run
+ * needs no host synchronisation and can be replayed.  Plans stay owned by
+ * the caller and must outlive the batch; while a plan belongs to a batch it
+ * must not be run on its own concurrently with the batch (they share its
+ * workspace).
+ * ------------------------------------------------------------------------ */
+typedef struct fspb_batch fspb_batch;
+
+/* Launch shape of the batched fill. */
+typedef struct {
+    int32_t waves_per_group;     /* fill workgroup size in 64-wide waves: 2, 4 or 8 */
+    int32_t groups_per_cu;       /* persistent fill grid = groups_per_cu x compute units, 1..16 */
+    int32_t order;               /* 0: longest beamlet rows first, 1: plan order */
+    int32_t tuned;               /* out: 1 if the shape came from fspb_batch_tune or its cache */
+    float fill_ms;               /* out: fill time measured for this shape by the tuner (0 if none) */
+    int32_t reserved;
+} fspb_batch_config;
+
+/*
+ * Create a batch over plans[0..n_plans) (each created by fspb_plan_create;
+ * density grids in place).  Runs the mask, ray-trace and counting stages once
+ * on `stream` and synchronises to size every plan's output.
+ * workspace: DEVICE, 256-byte aligned, caller-owned; NULL = size query
+ * (returns CAPACITY with *workspace_needed set).
+ */
+fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *workspace,
+                              size_t workspace_bytes, size_t *workspace_needed, void *stream,
+                              fspb_batch **out);
+
+/* Nonzeros of plan `plan` (index into the creation array) found by the sizing pass. */
+fspb_status fspb_batch_nnz(const fspb_batch *batch, int32_t plan, int64_t *nnz);
+
+/*
+ * Bind the CSR outputs of plan `plan`: DEVICE indptr (n_beamlets + 1 int64),
+ * indices (int32) and values (float) of `capacity` entries, capacity >=
+ * fspb_batch_nnz.  Every plan must be bound before fspb_batch_run.
+ */
+fspb_status fspb_batch_bind(fspb_batch *batch, int32_t plan, int64_t *indptr, int32_t *indices,
+                            float *values, int64_t capacity);
+
+/*
+ * Time every fill launch shape on this batch (outputs must be bound), keep the
+ * fastest and remember it for batches of the same shape class in this process
+ * (number of plans, beamlets and nonzeros rounded to two digits, term count).
+ * Synchronises `stream`.
+ */
+fspb_status fspb_batch_tune(fspb_batch *batch, void *stream);
+
+fspb_status fspb_batch_get_config(const fspb_batch *batch, fspb_batch_config *cfg);
+/* Set the launch shape explicitly (the graph is captured again on the next run). */
+fspb_status fspb_batch_set_config(fspb_batch *batch, const fspb_batch_config *cfg);
+
+/*
+ * Enqueue the whole batch on `stream` as one graph launch (captured on first
+ * use).  No host synchronisation.
+ */
+fspb_status fspb_batch_run(fspb_batch *batch, void *stream);
+
+/*
+ * Synchronise `stream` and report whether any plan produced more nonzeros than
+ * its bound capacity since the last check (possible only if densities changed
+ * after creation): OVERFLOW, with the plan's excess entries dropped.  Clears
+ * the flags.
+ */
+fspb_status fspb_batch_check(fspb_batch *batch, void *stream);
+
+/* Release the batch's host state (graph included). NULL is a no-op. */
+void fspb_batch_destroy(fspb_batch *batch);
+
 /* Human-readable name of a status code (static storage). */
 const char *fspb_status_string(fspb_status s);
 

@@ -57,6 +57,11 @@ class FspbTiming(C.Structure):
                 ("scan_ms", C.c_float), ("fill_ms", C.c_float), ("valid", C.c_int32)]
 
 
+class FspbBatchConfig(C.Structure):
+    _fields_ = [("waves_per_group", C.c_int32), ("groups_per_cu", C.c_int32), ("order", C.c_int32),
+                ("tuned", C.c_int32), ("fill_ms", C.c_float), ("reserved", C.c_int32)]
+
+
 class FspbPlanDesc(C.Structure):
     _fields_ = [("n_beamlets", C.c_int32), ("n_voxels", C.c_int32), ("table_entries", C.c_int64),
                 ("n_tiles", C.c_int64), ("max_table", C.c_int32), ("reserved", C.c_int32)]
@@ -75,6 +80,17 @@ _SIGS = {
     "fspb_plan_get_tables": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_plan_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "fspb_plan_get_timing": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fspb_batch_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t,
+                                      C.POINTER(C.c_size_t), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fspb_batch_nnz": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
+    "fspb_batch_bind": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_int64]),
+    "fspb_batch_tune": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fspb_batch_get_config": (C.c_int32, [C.c_void_p, C.POINTER(FspbBatchConfig)]),
+    "fspb_batch_set_config": (C.c_int32, [C.c_void_p, C.POINTER(FspbBatchConfig)]),
+    "fspb_batch_run": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fspb_batch_check": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fspb_batch_destroy": (None, [C.c_void_p]),
     "fspb_status_string": (C.c_char_p, [C.c_int32]),
     "fspb_last_error": (C.c_char_p, []),
 }
@@ -163,3 +179,56 @@ def fspb_plan_get_timing(plan):
     t = FspbTiming()
     _check(lib().fspb_plan_get_timing(plan, C.byref(t)))
     return t
+
+
+def fspb_batch_create(plan_handles, workspace, workspace_bytes, stream):
+    """Returns (status, batch handle or None, workspace bytes needed)."""
+    arr = (C.c_void_p * len(plan_handles))(*plan_handles)
+    need = C.c_size_t(0)
+    handle = C.c_void_p(None)
+    st = lib().fspb_batch_create(arr, len(plan_handles), workspace, workspace_bytes, C.byref(need),
+                                 stream, C.byref(handle))
+    if st not in (FSPB_OK, FSPB_ERR_CAPACITY):
+        _check(st)
+    return st, (handle.value if st == FSPB_OK else None), need.value
+
+
+def fspb_batch_nnz(batch, plan):
+    n = C.c_int64(0)
+    _check(lib().fspb_batch_nnz(batch, plan, C.byref(n)))
+    return n.value
+
+
+def fspb_batch_bind(batch, plan, indptr, indices, values, capacity):
+    return _check(lib().fspb_batch_bind(batch, plan, indptr, indices, values, capacity))
+
+
+def fspb_batch_tune(batch, stream):
+    return _check(lib().fspb_batch_tune(batch, stream))
+
+
+def fspb_batch_get_config(batch):
+    c = FspbBatchConfig()
+    _check(lib().fspb_batch_get_config(batch, C.byref(c)))
+    return c
+
+
+def fspb_batch_set_config(batch, waves_per_group, groups_per_cu, order):
+    c = FspbBatchConfig(waves_per_group, groups_per_cu, order, 0, 0.0, 0)
+    return _check(lib().fspb_batch_set_config(batch, C.byref(c)))
+
+
+def fspb_batch_run(batch, stream):
+    return _check(lib().fspb_batch_run(batch, stream))
+
+
+def fspb_batch_check(batch, stream):
+    """Returns the status (OK or OVERFLOW) instead of raising on OVERFLOW."""
+    st = lib().fspb_batch_check(batch, stream)
+    if st not in (FSPB_OK, FSPB_ERR_OVERFLOW):
+        _check(st)
+    return st
+
+
+def fspb_batch_destroy(batch):
+    lib().fspb_batch_destroy(batch)

@@ -88,5 +88,14 @@ hipError_t launch_count(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
 hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h,
                               hipStream_t s);
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s);
+size_t fill_shared_bytes(const PlanDev &h);
+
+/* Batched launches over n_plans plans (persistent grids). */
+hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,
+                             int grid, hipStream_t s);   // stage 0 prep, 1 raytrace, 2 count, 3 rowsum
+hipError_t launch_batch_scan(const PlanDev *const *plans, const OutDev *outs, int n_plans, hipStream_t s);
+hipError_t launch_batch_reset(int *counters, int n, hipStream_t s);
+hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const OutDev *outs, const int2 *items,
+                             int n_items, int *counter, int grid, size_t lds, hipStream_t s);
 
 }  // namespace fspb

@@ -9,6 +9,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -21,10 +24,6 @@
 using fspb::BeamletRec;
 using fspb::OutDev;
 using fspb::PlanDev;
-
-namespace fspb {
-size_t fill_shared_bytes(const PlanDev &h);
-}
 
 namespace {
 
@@ -610,5 +609,399 @@ fspb_status fspb_plan_get_tables(fspb_plan *p, float *tables, int64_t *offsets, 
     }
     return FSPB_OK;
 }
+
+}  // extern "C"
+
+/* ======================================================================
+ * Batches
+ * ====================================================================== */
+
+namespace {
+
+struct BatchKey {
+    int32_t n_plans, max_terms;
+    int64_t beamlets, nnz2;   // nnz rounded to two significant digits
+    bool operator<(const BatchKey &o) const
+    {
+        if (n_plans != o.n_plans) return n_plans < o.n_plans;
+        if (max_terms != o.max_terms) return max_terms < o.max_terms;
+        if (beamlets != o.beamlets) return beamlets < o.beamlets;
+        return nnz2 < o.nnz2;
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<BatchKey, fspb_batch_config> g_tune_cache;
+
+int64_t two_digits(int64_t v)
+{
+    int64_t scale = 1;
+    while (v >= 100) {
+        v /= 10;
+        scale *= 10;
+    }
+    return v * scale;
+}
+
+}  // namespace
+
+struct fspb_batch {
+    std::vector<fspb_plan *> plans;
+    int32_t n = 0;
+    // device arrays (caller workspace)
+    const PlanDev **d_plans = nullptr;
+    OutDev *d_outs = nullptr;
+    int64_t *d_start[4] = {};     // item prefix per wave stage: rows, beamlets, tiles, beamlets
+    int2 *d_items[2] = {};        // fill items: longest first, plan order
+    int *d_counter = nullptr;
+    int32_t n_items = 0;
+    int64_t total[4] = {};
+    std::vector<int64_t> nnz;
+    std::vector<OutDev> outs;
+    std::vector<bool> bound;
+    int32_t max_terms = 1;
+    size_t lds = 0;
+    int cus = 256;
+    fspb_batch_config cfg{4, 4, 0, 0, 0.0f, 0};
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~fspb_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+namespace {
+
+int wave_grid(const fspb_batch *b, int64_t items)
+{
+    // persistent grid: enough 4-wave groups to fill the chip several times over
+    const int64_t want = (items + fspb::kWave - 1) / 4;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)b->cus * 16));
+}
+
+fspb_status enqueue_stages(fspb_batch *b, hipStream_t s, bool with_fill)
+{
+    FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
+    for (int st = 0; st < 4; ++st) {
+        if (b->total[st] == 0) continue;
+        FSPB_HIP(fspb::launch_batch_wave(st, b->d_plans, b->d_start[st], b->n, wave_grid(b, b->total[st]), s),
+                 "launch batch stage");
+    }
+    FSPB_HIP(fspb::launch_batch_scan(b->d_plans, b->d_outs, b->n, s), "launch batch scan");
+    if (with_fill && b->n_items > 0) {
+        const int grid = std::max(1, std::min(b->n_items, b->cfg.groups_per_cu * b->cus));
+        FSPB_HIP(fspb::launch_batch_fill(b->max_terms, b->cfg.waves_per_group, b->d_plans, b->d_outs,
+                                         b->d_items[b->cfg.order], b->n_items, b->d_counter, grid, b->lds, s),
+                 "launch batch fill");
+    }
+    return FSPB_OK;
+}
+
+fspb_status launch_fill_only(fspb_batch *b, hipStream_t s)
+{
+    FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
+    const int grid = std::max(1, std::min(b->n_items, b->cfg.groups_per_cu * b->cus));
+    FSPB_HIP(fspb::launch_batch_fill(b->max_terms, b->cfg.waves_per_group, b->d_plans, b->d_outs,
+                                     b->d_items[b->cfg.order], b->n_items, b->d_counter, grid, b->lds, s),
+             "launch batch fill");
+    return FSPB_OK;
+}
+
+bool valid_config(const fspb_batch_config &c)
+{
+    return (c.waves_per_group == 2 || c.waves_per_group == 4 || c.waves_per_group == 8) && c.groups_per_cu >= 1 &&
+           c.groups_per_cu <= 16 && (c.order == 0 || c.order == 1);
+}
+
+BatchKey key_of(const fspb_batch *b)
+{
+    int64_t beamlets = 0, nnz = 0;
+    for (int i = 0; i < b->n; ++i) {
+        beamlets += b->plans[i]->h.n_beamlets;
+        nnz += b->nnz[i];
+    }
+    return BatchKey{b->n, b->max_terms, beamlets, two_digits(nnz)};
+}
+
+}  // namespace
+
+extern "C" {
+
+fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *workspace, size_t workspace_bytes,
+                              size_t *workspace_needed, void *stream, fspb_batch **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(FSPB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!plans || n_plans < 1) return fail(FSPB_ERR_INVALID, "plans is NULL or n_plans < 1");
+    if (n_plans > 4096) return fail(FSPB_ERR_INVALID, "at most 4096 plans per batch");
+    for (int i = 0; i < n_plans; ++i) {
+        if (!plans[i]) return fail(FSPB_ERR_INVALID, "plans[%d] is NULL", i);
+        for (int k = 0; k < i; ++k)
+            if (plans[k] == plans[i]) return fail(FSPB_ERR_INVALID, "plan %d appears twice", i);
+    }
+    if (!workspace && !workspace_needed) return fail(FSPB_ERR_INVALID, "workspace and workspace_needed are both NULL");
+
+    int64_t beamlets = 0, rows = 0, tiles = 0;
+    for (int i = 0; i < n_plans; ++i) {
+        beamlets += plans[i]->h.n_beamlets;
+        rows += (int64_t)plans[i]->h.ny * plans[i]->h.nz;
+        tiles += plans[i]->h.n_tiles;
+    }
+    if (beamlets >= (int64_t)1 << 31) return fail(FSPB_ERR_INVALID, "too many beamlets in the batch");
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t o_plans = take(sizeof(PlanDev *) * n_plans);
+    const size_t o_outs = take(sizeof(OutDev) * n_plans);
+    size_t o_start[4];
+    for (int st = 0; st < 4; ++st) o_start[st] = take(sizeof(int64_t) * (n_plans + 1));
+    const size_t o_items0 = take(sizeof(int2) * (size_t)std::max<int64_t>(beamlets, 1));
+    const size_t o_items1 = take(sizeof(int2) * (size_t)std::max<int64_t>(beamlets, 1));
+    const size_t o_counter = take(64);
+    if (workspace_needed) *workspace_needed = off;
+    if (!workspace) return fail(FSPB_ERR_CAPACITY, "batch workspace query: %zu bytes needed", off);
+    if (workspace_bytes < off)
+        return fail(FSPB_ERR_CAPACITY, "batch workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, off);
+    if ((uintptr_t)workspace % 256 != 0) return fail(FSPB_ERR_INVALID, "workspace must be 256-byte aligned");
+
+    fspb_batch *b = new (std::nothrow) fspb_batch;
+    if (!b) return fail(FSPB_ERR_NOMEM, "cannot allocate the batch");
+    std::unique_ptr<fspb_batch> guard(b);
+    b->plans.assign(plans, plans + n_plans);
+    b->n = n_plans;
+    char *ws = static_cast<char *>(workspace);
+    b->d_plans = reinterpret_cast<const PlanDev **>(ws + o_plans);
+    b->d_outs = reinterpret_cast<OutDev *>(ws + o_outs);
+    for (int st = 0; st < 4; ++st) b->d_start[st] = reinterpret_cast<int64_t *>(ws + o_start[st]);
+    b->d_items[0] = reinterpret_cast<int2 *>(ws + o_items0);
+    b->d_items[1] = reinterpret_cast<int2 *>(ws + o_items1);
+    b->d_counter = reinterpret_cast<int *>(ws + o_counter);
+    int dev = 0;
+    FSPB_HIP(hipGetDevice(&dev), "get device");
+    FSPB_HIP(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev), "query compute units");
+
+    std::vector<const PlanDev *> pp(n_plans);
+    std::vector<int64_t> start[4];
+    for (int st = 0; st < 4; ++st) start[st].assign(n_plans + 1, 0);
+    b->outs.assign(n_plans, OutDev{});
+    b->bound.assign(n_plans, false);
+    for (int i = 0; i < n_plans; ++i) {
+        const PlanDev &h = plans[i]->h;
+        pp[i] = plans[i]->d_plan;
+        start[0][i + 1] = start[0][i] + (int64_t)h.ny * h.nz;
+        start[1][i + 1] = start[1][i] + h.n_beamlets;
+        start[2][i + 1] = start[2][i] + h.n_tiles;
+        start[3][i + 1] = start[3][i] + h.n_beamlets;
+        b->max_terms = std::max(b->max_terms, h.n_terms);
+        b->lds = std::max(b->lds, fspb::fill_shared_bytes(h));
+        b->outs[i].overflow = plans[i]->d_overflow;
+    }
+    for (int st = 0; st < 4; ++st) b->total[st] = start[st][n_plans];
+    FSPB_HIP(hipMemcpy(b->d_plans, pp.data(), sizeof(PlanDev *) * n_plans, hipMemcpyHostToDevice), "upload plan table");
+    for (int st = 0; st < 4; ++st)
+        FSPB_HIP(hipMemcpy(b->d_start[st], start[st].data(), sizeof(int64_t) * (n_plans + 1), hipMemcpyHostToDevice),
+                 "upload item ranges");
+
+    // sizing pass: mask, tables, counts, row sums
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
+    for (int st = 0; st < 4; ++st)
+        if (b->total[st] > 0)
+            FSPB_HIP(fspb::launch_batch_wave(st, b->d_plans, b->d_start[st], n_plans, wave_grid(b, b->total[st]), s),
+                     "launch batch stage");
+    std::vector<std::vector<int64_t>> rn(n_plans);
+    for (int i = 0; i < n_plans; ++i) {
+        rn[i].resize(plans[i]->h.n_beamlets);
+        FSPB_HIP(hipMemcpyAsync(rn[i].data(), plans[i]->h.row_nnz, sizeof(int64_t) * rn[i].size(),
+                                hipMemcpyDeviceToHost, s),
+                 "read row counts");
+    }
+    FSPB_HIP(hipStreamSynchronize(s), "synchronise sizing pass");
+    b->nnz.assign(n_plans, 0);
+    std::vector<std::pair<int64_t, int2>> items;
+    items.reserve((size_t)beamlets);
+    for (int i = 0; i < n_plans; ++i)
+        for (int j = 0; j < (int)rn[i].size(); ++j) {
+            b->nnz[i] += rn[i][j];
+            if (rn[i][j] > 0) items.push_back({rn[i][j], make_int2(i, j)});
+        }
+    b->n_items = (int32_t)items.size();
+    std::vector<int2> natural(items.size()), longest(items.size());
+    for (size_t k = 0; k < items.size(); ++k) natural[k] = items[k].second;
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<int64_t, int2> &a, const std::pair<int64_t, int2> &c) { return a.first > c.first; });
+    for (size_t k = 0; k < items.size(); ++k) longest[k] = items[k].second;
+    if (!items.empty()) {
+        FSPB_HIP(hipMemcpy(b->d_items[0], longest.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice),
+                 "upload fill queue");
+        FSPB_HIP(hipMemcpy(b->d_items[1], natural.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice),
+                 "upload fill queue");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key_of(b));
+        if (it != g_tune_cache.end()) b->cfg = it->second;
+    }
+    FSPB_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "create capture stream");
+    *out = guard.release();
+    return FSPB_OK;
+}
+
+fspb_status fspb_batch_nnz(const fspb_batch *b, int32_t plan, int64_t *nnz)
+{
+    g_last_error.clear();
+    if (!b || !nnz) return fail(FSPB_ERR_INVALID, "batch or nnz is NULL");
+    if (plan < 0 || plan >= b->n) return fail(FSPB_ERR_INVALID, "plan index %d out of range", plan);
+    *nnz = b->nnz[plan];
+    return FSPB_OK;
+}
+
+fspb_status fspb_batch_bind(fspb_batch *b, int32_t plan, int64_t *indptr, int32_t *indices, float *values,
+                            int64_t capacity)
+{
+    g_last_error.clear();
+    if (!b) return fail(FSPB_ERR_INVALID, "batch is NULL");
+    if (plan < 0 || plan >= b->n) return fail(FSPB_ERR_INVALID, "plan index %d out of range", plan);
+    if (!indptr || ((!indices || !values) && b->nnz[plan] > 0))
+        return fail(FSPB_ERR_INVALID, "output pointers are NULL");
+    if (capacity < b->nnz[plan])
+        return fail(FSPB_ERR_CAPACITY, "plan %d needs %lld entries, capacity %lld", plan, (long long)b->nnz[plan],
+                    (long long)capacity);
+    OutDev &o = b->outs[plan];
+    o.indptr = indptr;
+    o.indices = indices;
+    o.values = values;
+    o.capacity = capacity;
+    FSPB_HIP(hipMemcpy(b->d_outs + plan, &o, sizeof(OutDev), hipMemcpyHostToDevice), "upload output record");
+    b->bound[plan] = true;
+    b->drop_graph();
+    return FSPB_OK;
+}
+
+fspb_status fspb_batch_get_config(const fspb_batch *b, fspb_batch_config *cfg)
+{
+    g_last_error.clear();
+    if (!b || !cfg) return fail(FSPB_ERR_INVALID, "batch or cfg is NULL");
+    *cfg = b->cfg;
+    return FSPB_OK;
+}
+
+fspb_status fspb_batch_set_config(fspb_batch *b, const fspb_batch_config *cfg)
+{
+    g_last_error.clear();
+    if (!b || !cfg) return fail(FSPB_ERR_INVALID, "batch or cfg is NULL");
+    if (!valid_config(*cfg)) return fail(FSPB_ERR_INVALID, "invalid launch shape");
+    b->cfg = *cfg;
+    b->cfg.tuned = 0;
+    b->cfg.fill_ms = 0.0f;
+    b->drop_graph();
+    return FSPB_OK;
+}
+
+fspb_status fspb_batch_tune(fspb_batch *b, void *stream)
+{
+    g_last_error.clear();
+    if (!b) return fail(FSPB_ERR_INVALID, "batch is NULL");
+    for (int i = 0; i < b->n; ++i)
+        if (!b->bound[i]) return fail(FSPB_ERR_STATE, "plan %d has no bound outputs", i);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    fspb_status st = enqueue_stages(b, s, false);
+    if (st != FSPB_OK) return st;
+    hipEvent_t e0, e1;
+    FSPB_HIP(hipEventCreate(&e0), "create event");
+    FSPB_HIP(hipEventCreate(&e1), "create event");
+    const fspb_batch_config saved = b->cfg;
+    fspb_batch_config best = saved;
+    float best_ms = 1e30f;
+    for (int order = 0; order < 2; ++order)
+        for (int w : {2, 4, 8})
+            for (int g : {1, 2, 4, 8}) {
+                b->cfg = fspb_batch_config{w, g, order, 0, 0.0f, 0};
+                float ms = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    FSPB_HIP(hipEventRecord(e0, s), "record event");
+                    st = launch_fill_only(b, s);
+                    if (st != FSPB_OK) return st;
+                    FSPB_HIP(hipEventRecord(e1, s), "record event");
+                    FSPB_HIP(hipEventSynchronize(e1), "wait event");
+                    float t = 0.0f;
+                    FSPB_HIP(hipEventElapsedTime(&t, e0, e1), "elapsed");
+                    ms = std::min(ms, t);
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = b->cfg;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    best.tuned = 1;
+    best.fill_ms = best_ms;
+    b->cfg = best;
+    b->drop_graph();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key_of(b)] = best;
+    return FSPB_OK;
+}
+
+fspb_status fspb_batch_run(fspb_batch *b, void *stream)
+{
+    g_last_error.clear();
+    if (!b) return fail(FSPB_ERR_INVALID, "batch is NULL");
+    for (int i = 0; i < b->n; ++i)
+        if (!b->bound[i]) return fail(FSPB_ERR_STATE, "plan %d has no bound outputs", i);
+    if (!b->exec) {
+        FSPB_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        fspb_status st = enqueue_stages(b, b->cap_stream, true);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (st != FSPB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        b->graph = g;
+        FSPB_HIP(hipGraphInstantiateWithFlags(&b->exec, b->graph, 0), "instantiate graph");
+    }
+    FSPB_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)), "launch graph");
+    return FSPB_OK;
+}
+
+fspb_status fspb_batch_check(fspb_batch *b, void *stream)
+{
+    g_last_error.clear();
+    if (!b) return fail(FSPB_ERR_INVALID, "batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> flags(b->n, 0);
+    for (int i = 0; i < b->n; ++i)
+        FSPB_HIP(hipMemcpyAsync(&flags[i], b->plans[i]->d_overflow, sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                 "read overflow flag");
+    FSPB_HIP(hipStreamSynchronize(s), "synchronise check");
+    int first = -1;
+    for (int i = 0; i < b->n; ++i)
+        if (flags[i]) {
+            if (first < 0) first = i;
+            FSPB_HIP(hipMemset(b->plans[i]->d_overflow, 0, sizeof(int32_t)), "clear overflow flag");
+        }
+    if (first >= 0) return fail(FSPB_ERR_OVERFLOW, "plan %d produced more nonzeros than its capacity", first);
+    return FSPB_OK;
+}
+
+void fspb_batch_destroy(fspb_batch *b) { delete b; }
 
 }  // extern "C"

@@ -59,11 +59,9 @@ __device__ inline T wave_sum(T x)
 
 /* ---------------------------------------------------------------- prep */
 
-__global__ __launch_bounds__(kBlock) void k_prep(const PlanDev *__restrict__ plans)
+/* Mask bits and member extent of grid row `row` (= iz * ny + iy); one wave. */
+__device__ void prep_row(const PlanDev &P, int row)
 {
-    const PlanDev &P = plans[0];
-    const int row = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (row >= P.ny * P.nz) return;
     const int lane = lane_id();
     const float *d = P.density + (size_t)row * P.nx;
     uint32_t *bits = P.bits + (size_t)row * P.wpr;
@@ -80,6 +78,13 @@ __global__ __launch_bounds__(kBlock) void k_prep(const PlanDev *__restrict__ pla
         }
     }
     if (lane == 0) P.ext[row] = make_int2(first, last);   // first > last: no member voxel
+}
+
+__global__ __launch_bounds__(kBlock) void k_prep(const PlanDev *__restrict__ plans)
+{
+    const PlanDev &P = plans[0];
+    const int row = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (row < P.ny * P.nz) prep_row(P, row);
 }
 
 /* ------------------------------------------------------------ raytrace */
@@ -169,11 +174,9 @@ __device__ cpair interval_integral(const PlanDev &P, const BeamletRec &R, int m,
     return acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_raytrace(const PlanDev *__restrict__ plans)
+/* Depth table of beamlet j; one wave, lanes over table intervals. */
+__device__ void raytrace_beamlet(const PlanDev &P, int j)
 {
-    const PlanDev &P = plans[0];
-    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (j >= P.n_beamlets) return;
     const int lane = lane_id();
     const BeamletRec &R = P.rec[j];
     const int n = R.n_table;
@@ -195,6 +198,13 @@ __global__ __launch_bounds__(kBlock) void k_raytrace(const PlanDev *__restrict__
         const cpair last = {__shfl(acc.s, kWave - 1, kWave), __shfl(acc.c, kWave - 1, kWave)};
         carry = cp_add(carry, last);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_raytrace(const PlanDev *__restrict__ plans)
+{
+    const PlanDev &P = plans[0];
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j < P.n_beamlets) raytrace_beamlet(P, j);
 }
 
 /* --------------------------------------------------------- VOI per row */
@@ -260,11 +270,9 @@ __device__ inline int popcount_range(const uint32_t *row, int lo, int hi)
     return c;
 }
 
-__global__ __launch_bounds__(kBlock) void k_count(const PlanDev *__restrict__ plans)
+/* VOI members of tile t (64 grid rows of one beamlet); one wave. */
+__device__ void count_tile(const PlanDev &P, int t)
 {
-    const PlanDev &P = plans[0];
-    const int t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (t >= P.n_tiles) return;
     const int lane = lane_id();
     const BeamletRec &R = P.rec[P.tile_beamlet[t]];
     const int r = (t - R.tile0) * kRowsPerTile + lane;
@@ -280,13 +288,18 @@ __global__ __launch_bounds__(kBlock) void k_count(const PlanDev *__restrict__ pl
     if (lane == 0) P.tile_count[t] = cnt;
 }
 
-/* ---------------------------------------------------------------- scan */
-
-__global__ __launch_bounds__(kBlock) void k_rowsum(const PlanDev *__restrict__ plans)
+__global__ __launch_bounds__(kBlock) void k_count(const PlanDev *__restrict__ plans)
 {
     const PlanDev &P = plans[0];
-    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (j >= P.n_beamlets) return;
+    const int t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (t < P.n_tiles) count_tile(P, t);
+}
+
+/* ---------------------------------------------------------------- scan */
+
+/* Nonzeros of beamlet row j from its tile counts; one wave. */
+__device__ void rowsum_beamlet(const PlanDev &P, int j)
+{
     const BeamletRec &R = P.rec[j];
     int64_t s = 0;
     for (int k = lane_id(); k < R.n_tiles; k += kWave) s += P.tile_count[R.tile0 + k];
@@ -294,14 +307,18 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(const PlanDev *__restrict__ p
     if (lane_id() == 0) P.row_nnz[j] = s;
 }
 
-constexpr int kScanBlock = 1024;
-
-/* Exclusive scan of row_nnz into indptr[0..n]; indptr[n] = nnz. One workgroup. */
-__global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__ plans,
-                                                      const OutDev *__restrict__ outs)
+__global__ __launch_bounds__(kBlock) void k_rowsum(const PlanDev *__restrict__ plans)
 {
     const PlanDev &P = plans[0];
-    int64_t *indptr = outs[0].indptr;
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j < P.n_beamlets) rowsum_beamlet(P, j);
+}
+
+constexpr int kScanBlock = 1024;
+
+/* Exclusive scan of row_nnz into indptr[0..n]; indptr[n] = nnz.  One workgroup of kScanBlock. */
+__device__ void scan_plan(const PlanDev &P, int64_t *indptr)
+{
     __shared__ int64_t wsum[kScanBlock / kWave];
     __shared__ int64_t carry_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
@@ -325,6 +342,12 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__
         indptr[P.n_beamlets] = carry_s;
         P.nnz[0] = carry_s;
     }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__ plans,
+                                                      const OutDev *__restrict__ outs)
+{
+    scan_plan(plans[0], outs[0].indptr);
 }
 
 /* ---------------------------------------------------------------- fill */
@@ -371,10 +394,11 @@ __device__ inline float edge_pair(const float4 *__restrict__ tab, float ax, floa
 template <int K>
 struct FillConst {
     float sad, tA, inv_step, tau_max, pdd_inv, pdd_max;
+    int n_terms;
     float w4[K], sig0[K], sig1[K], ha[K], hb[K];
 };
 
-template <int K>
+template <int K, bool GUARD>
 __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restrict__ tab,
                                    const float2 *__restrict__ pdd, const float4 *__restrict__ etab,
                                    float s, float U, float V)
@@ -395,6 +419,7 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
     float L = 0.0f;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
+        if (GUARD && i >= c.n_terms) break;
         const float isk = kIsScale * __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
         const float eu = edge_pair(etab, au, c.ha[i], isk);
         const float ev = edge_pair(etab, av, c.hb[i], isk);
@@ -405,16 +430,19 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
 
 __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
-                                                  const OutDev *__restrict__ outs)
+/*
+ * D_ij of beamlet j (one CSR row) by a workgroup of W waves: LDS-staged
+ * tables, then each wave takes tiles of 64 grid rows; a tile's VOI candidates
+ * are flattened across its rows, 64 per chunk, members compacted by ballot.
+ * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K).
+ */
+template <int K, int W, bool GUARD>
+__device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const PlanDev &P = plans[0];
-    const int j = blockIdx.x;
     const BeamletRec &R = P.rec[j];
     const int n_tiles = R.n_tiles;
     if (n_tiles == 0) return;
+    constexpr int kB = W * kWave;
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
 
     // ---- constants into registers
@@ -428,6 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
     c.tau_max = R.tau_max_f;
     c.pdd_inv = P.pdd_inv_step;
     c.pdd_max = P.pdd_max;
+    c.n_terms = P.n_terms;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         c.w4[i] = P.w4[i];
@@ -441,7 +470,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
     const float t1f = R.t1_f, U1f = R.U1_f, V1f = R.V1_f;
     const gptr<const uint32_t> bits = as_global<const uint32_t>(P.bits);
     const gptr<const int32_t> tile_count = as_global<const int32_t>(P.tile_count);
-    const OutDev &O = outs[0];
     const gptr<int32_t> out_idx = as_global<int32_t>(O.indices);
     const gptr<float> out_val = as_global<float>(O.values);
     const int64_t capacity = O.capacity;
@@ -452,25 +480,25 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
     float2 *s_tab = reinterpret_cast<float2 *>(s_erfc + kErfcIntervals);
     float2 *s_pdd = s_tab + P.max_table;
     int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
-    __shared__ int wsum[kWavesPerBlock];
+    __shared__ int wsum[W];
 
     {
         const float4 *et = P.erfc_tab;
-        for (int i = tid; i < kErfcIntervals; i += kBlock) s_erfc[i] = et[i];
+        for (int i = tid; i < kErfcIntervals; i += kB) s_erfc[i] = et[i];
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
-        for (int i = tid; i < n_table; i += kBlock) {
+        for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
             s_tab[i] = make_float2(d0, (i + 1 < n_table ? tab[i + 1] : d0) - d0);
         }
         const gptr<const float> pd = as_global<const float>(P.pdd);
-        for (int i = tid; i < n_pdd; i += kBlock) {
+        for (int i = tid; i < n_pdd; i += kB) {
             const float p0 = pd[i];
             s_pdd[i] = make_float2(p0, (i + 1 < n_pdd ? pd[i + 1] : p0) - p0);
         }
     }
     // exclusive scan of this beamlet's tile counts
     int carry = 0;
-    for (int base = 0; base < n_tiles; base += kBlock) {
+    for (int base = 0; base < n_tiles; base += kB) {
         const int i = base + tid;
         const int v = i < n_tiles ? tile_count[tile0 + i] : 0;
         const int inc = wave_incl_scan(v);
@@ -480,12 +508,12 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
         for (int w = 0; w < wave; ++w) woff += wsum[w];
         if (i < n_tiles) s_tpre[i] = carry + woff + inc - v;
         int tot = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) tot += wsum[w];
+        for (int w = 0; w < W; ++w) tot += wsum[w];
         carry += tot;
         __syncthreads();
     }
 
-    for (int tl = wave; tl < n_tiles; tl += kWavesPerBlock) {
+    for (int tl = wave; tl < n_tiles; tl += W) {
         if (tile_count[tile0 + tl] == 0) continue;
         const int64_t out0 = row_base + s_tpre[tl];
         // lane = grid row of this tile: its VOI interval and FP32 start values
@@ -539,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
             const bool room = written + kWave <= capacity;
             if (member) {
                 const float kf = (float)k;
-                const float D = dose_value<K>(c, s_tab, s_pdd, s_erfc, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                const float D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erfc, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
                                               fmaf(kf, V1f, vl));
                 if (room || written + slot < capacity) {
                     ip[slot] = gr * nx + ix;
@@ -551,6 +579,81 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
             written += __popcll(mask);
         }
     }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
+                                                  const OutDev *__restrict__ outs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    fill_beamlet<K, kWavesPerBlock, false>(plans[0], outs[0], blockIdx.x, smem);
+}
+
+/* ------------------------------------------------------------ batches */
+
+/*
+ * Persistent kernels over many plans.  Wave-level stages walk a global item
+ * index grid-stride; item i belongs to the plan p with start[p] <= i <
+ * start[p+1] (few plans: a short uniform search).  The fill pulls
+ * (plan, beamlet) items from an atomic queue, longest rows first.
+ */
+__device__ inline int plan_of(const int64_t *__restrict__ start, int n_plans, int64_t i)
+{
+    int lo = 0, hi = n_plans - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void kp_wave(const PlanDev *const *__restrict__ plans,
+                                                  const int64_t *__restrict__ start, int n_plans)
+{
+    const int64_t total = start[n_plans];
+    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < total; w += nw) {
+        const int p = plan_of(start, n_plans, w);
+        const PlanDev &P = *plans[p];
+        const int i = (int)(w - start[p]);
+        if (STAGE == 0) prep_row(P, i);
+        else if (STAGE == 1) raytrace_beamlet(P, i);
+        else if (STAGE == 2) count_tile(P, i);
+        else rowsum_beamlet(P, i);
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void kp_scan(const PlanDev *const *__restrict__ plans,
+                                                       const OutDev *__restrict__ outs)
+{
+    scan_plan(*plans[blockIdx.x], outs[blockIdx.x].indptr);
+}
+
+template <int K, int W>
+__global__ __launch_bounds__(W * kWave) void kp_fill(const PlanDev *const *__restrict__ plans,
+                                                     const OutDev *__restrict__ outs,
+                                                     const int2 *__restrict__ items, int n_items,
+                                                     int *__restrict__ counter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int w = s_item;
+        __syncthreads();
+        if (w >= n_items) break;
+        const int2 it = items[w];
+        fill_beamlet<K, W, true>(*plans[it.x], outs[it.x], it.y, smem);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset(int *__restrict__ counters, int n)
+{
+    if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
 }  // namespace
@@ -597,6 +700,55 @@ size_t fill_shared_bytes(const PlanDev &h)
 {
     return sizeof(float4) * kErfcIntervals + sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) +
            sizeof(int) * ((size_t)h.max_tiles + 1);
+}
+
+hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,
+                             int grid, hipStream_t s)
+{
+    const dim3 g(grid), b(kBlock);
+    switch (stage) {
+    case 0: hipLaunchKernelGGL(kp_wave<0>, g, b, 0, s, plans, start, n_plans); break;
+    case 1: hipLaunchKernelGGL(kp_wave<1>, g, b, 0, s, plans, start, n_plans); break;
+    case 2: hipLaunchKernelGGL(kp_wave<2>, g, b, 0, s, plans, start, n_plans); break;
+    default: hipLaunchKernelGGL(kp_wave<3>, g, b, 0, s, plans, start, n_plans); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_scan(const PlanDev *const *plans, const OutDev *outs, int n_plans, hipStream_t s)
+{
+    hipLaunchKernelGGL(kp_scan, dim3(n_plans), dim3(kScanBlock), 0, s, plans, outs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(int *counters, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_kp_fill_k(int W, const PlanDev *const *plans, const OutDev *outs, const int2 *items,
+                                   int n_items, int *counter, int grid, size_t lds, hipStream_t s)
+{
+    const dim3 g(grid);
+    switch (W) {
+    case 2: hipLaunchKernelGGL((kp_fill<K, 2>), g, dim3(2 * kWave), lds, s, plans, outs, items, n_items, counter); break;
+    case 8: hipLaunchKernelGGL((kp_fill<K, 8>), g, dim3(8 * kWave), lds, s, plans, outs, items, n_items, counter); break;
+    default: hipLaunchKernelGGL((kp_fill<K, 4>), g, dim3(4 * kWave), lds, s, plans, outs, items, n_items, counter); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const OutDev *outs, const int2 *items,
+                             int n_items, int *counter, int grid, size_t lds, hipStream_t s)
+{
+    switch (K) {
+    case 1: return launch_kp_fill_k<1>(W, plans, outs, items, n_items, counter, grid, lds, s);
+    case 2: return launch_kp_fill_k<2>(W, plans, outs, items, n_items, counter, grid, lds, s);
+    case 3: return launch_kp_fill_k<3>(W, plans, outs, items, n_items, counter, grid, lds, s);
+    default: return launch_kp_fill_k<4>(W, plans, outs, items, n_items, counter, grid, lds, s);
+    }
 }
 
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)

@@ -114,3 +114,64 @@ class Plan:
         off = np.zeros(self.n_beamlets + 1, dtype=np.int64)
         L.fspb_plan_get_tables(self.handle, tab.ctypes.data, off.ctypes.data, self._stream(stream))
         return tab[:int(self.desc.table_entries)], off
+
+
+class Batch:
+    """Many plans computed by one captured graph of persistent kernels.
+
+    ``plans`` are ``Plan`` objects on the same device; they must outlive the
+    batch.  Outputs are allocated from the sizing pass and bound at creation.
+    """
+
+    def __init__(self, plans, stream=None):
+        torch = plans[0].torch
+        self.torch = torch
+        self.plans = list(plans)
+        self.device = plans[0].device
+        s = self._stream(stream)
+        handles = [p.handle for p in self.plans]
+        st, _, need = L.fspb_batch_create(handles, None, 0, s)
+        assert st == L.FSPB_ERR_CAPACITY
+        self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        st, self.handle, _ = L.fspb_batch_create(handles, aligned, need, s)
+        self.nnz = [L.fspb_batch_nnz(self.handle, i) for i in range(len(self.plans))]
+        self.indptr, self.indices, self.values = [], [], []
+        for i, p in enumerate(self.plans):
+            ip = torch.empty(p.n_beamlets + 1, dtype=torch.int64, device=self.device)
+            ix = torch.empty(max(self.nnz[i], 1), dtype=torch.int32, device=self.device)
+            vv = torch.empty(max(self.nnz[i], 1), dtype=torch.float32, device=self.device)
+            L.fspb_batch_bind(self.handle, i, ip.data_ptr(), ix.data_ptr(), vv.data_ptr(), ix.numel())
+            self.indptr.append(ip)
+            self.indices.append(ix)
+            self.values.append(vv)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            L.fspb_batch_destroy(h)
+            self.handle = None
+
+    def _stream(self, stream):
+        s = stream if stream is not None else self.torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def tune(self, stream=None):
+        L.fspb_batch_tune(self.handle, self._stream(stream))
+        return self.config()
+
+    def config(self):
+        return L.fspb_batch_get_config(self.handle)
+
+    def set_config(self, waves_per_group, groups_per_cu, order):
+        L.fspb_batch_set_config(self.handle, waves_per_group, groups_per_cu, order)
+
+    def run(self, stream=None):
+        L.fspb_batch_run(self.handle, self._stream(stream))
+
+    def check(self, stream=None):
+        return L.fspb_batch_check(self.handle, self._stream(stream))
+
+    def outputs(self):
+        return [CSR(self.indptr[i], self.indices[i][:self.nnz[i]], self.values[i][:self.nnz[i]],
+                    p.n_voxels) for i, p in enumerate(self.plans)]
