@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--surrogate-epochs", type=int, default=300,
+                    help="training epochs of the kernel surrogate compared with the analytic "
+                         "fill on the pelvis workload (0 skips the comparison)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (reference "
                          "dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -102,6 +105,57 @@ def cpu_baseline(prob, target_s, n_beamlets):
             "kind": "oracle",
             "sample": f"{done} of {n_beamlets} beamlet rows (seeded order), {nz} nonzeros in {dt:.1f} s; "
                       f"FP64 C oracle, OpenMP over rows"}
+
+
+def surrogate_comparison(epochs):
+    """Train the kernel surrogate on the GPU and compare its fused fill with the analytic fill.
+
+    Workload: the 256 x 256 x 100 pelvis (9 beams, 0.25 cm beamlets).  The
+    surrogate is trained on 1e7 seeded samples of the analytic kernel; both
+    fills are timed with HIP events, and the surrogate's summed dose (uniform
+    fluence) is compared with the analytic fill's.  The FP64 judgement of both
+    is in tests/test_gpu_surrogate.py and tests/test_gpu_parity.py.
+    """
+    import torch
+    import fspb_inputs as fi
+    import paper_0908_4417_amd as m
+    from paper_0908_4417_amd import Plan, Surrogate
+    prob = fi.make_config(4)
+    dev = "cuda:0"
+    n_samples = 10_000_000
+    sur = Surrogate(prob.kernel, fi.surrogate_init(5), max_batch=16384)
+    raw = fi.surrogate_samples(n_samples, seed=5, core=0.5, log_a=True).astype(np.float32)
+    f, t = sur.targets(torch.from_numpy(raw).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = sur.train(f, t, epochs=epochs, batch=16384, lr_max=3e-3, lr_min=1e-6, seed=5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del f, t
+    plan = Plan(prob, dev)
+    m.fspb_plan_set_timing(plan.handle, 1)
+
+    def run():
+        times = []
+        for _ in range(4):
+            csr = plan.compute()
+            times.append(m.fspb_plan_get_timing(plan.handle).fill_ms)
+        torch.cuda.synchronize()
+        dose = torch.zeros(plan.n_voxels, dtype=torch.float64, device=dev)
+        dose.index_add_(0, csr.indices.long(), csr.values.double())
+        return min(times[1:]), dose, csr.values.double().clone()
+
+    ta, Da, va = run()
+    plan.set_surrogate(sur)
+    ts, Ds, vs = run()
+    dmax = Da.max().item()
+    return {"workload": "surrogate_on_pelvis", "samples": n_samples, "epochs": epochs,
+            "train_s": round(train_s, 3), "final_loss": float(losses[-1]),
+            "fill_ms_analytic": round(ta, 4), "fill_ms_surrogate": round(ts, 4),
+            "surrogate_speedup": round(ta / ts, 4),
+            "max_dose_err_vs_analytic": round((Ds - Da).abs().max().item() / dmax, 6),
+            "rms_dose_err_vs_analytic": round(((Ds - Da)[Da > 0] ** 2).mean().sqrt().item() / dmax, 6),
+            "max_coeff_err_vs_analytic": round((vs - va).abs().max().item() / va.max().item(), 6)}
 
 
 def bench_batch(args):
@@ -240,6 +294,9 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
         "device_ms_per_plan": round(sum(kt.values()), 4),
     }
+    if args.surrogate_epochs > 0:
+        del indices, values, ws
+        out["surrogate"] = surrogate_comparison(args.surrogate_epochs)
     if not args.no_cpu_baseline and args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, desc.n_beamlets)
     print(json.dumps(out), flush=True)

@@ -26,7 +26,7 @@ __all__ = [
     "Grid", "Beam", "KernelParams", "Problem",
     "pdd_table", "default_kernel", "water_phantom", "slab_phantom",
     "pelvis_phantom", "coplanar_beams", "make_config", "batched_configs",
-    "surrogate_samples", "table1_case", "CONFIG_NAMES",
+    "surrogate_samples", "surrogate_init", "table1_case", "CONFIG_NAMES",
 ]
 
 
@@ -342,19 +342,49 @@ def batched_configs(n_plans: int = 32, base_seed: int = 4000, scale: float = 1.0
 
 
 def surrogate_samples(n: int, seed: int, d_max: float = 30.0, uv_max: float = 3.0,
-                      a_range=(0.25, 1.0)):
-    """Uniform training/evaluation points (d, |u|, |v|, a) for the kernel surrogate.
+                      a_range=(0.25, 1.0), core: float = 0.0, core_uv: float = 1.0, core_d: float = 5.0,
+                      log_a: bool = False):
+    """Training/evaluation points (d, |u|, |v|, a) for the kernel surrogate.
 
     float64 array [n, 4]; the profile is even in u and v, so only |u|, |v|
-    are drawn.
+    are drawn.  A fraction ``1 - core`` is uniform over the whole box; the
+    fraction ``core`` is uniform over the beamlet core |u|, |v| <= core_uv,
+    half of it also restricted to the build-up region d <= core_d (where the
+    kernel is largest and steepest).  With ``log_a`` the beamlet side is drawn
+    log-uniformly (narrow beamlets, whose profiles are sharpest, get more
+    samples).
     """
     rng = np.random.default_rng(seed)
     out = np.empty((n, 4), dtype=np.float64)
     out[:, 0] = rng.uniform(0.0, d_max, n)
     out[:, 1] = rng.uniform(0.0, uv_max, n)
     out[:, 2] = rng.uniform(0.0, uv_max, n)
-    out[:, 3] = rng.uniform(a_range[0], a_range[1], n)
+    if log_a:
+        out[:, 3] = np.exp(rng.uniform(np.log(a_range[0]), np.log(a_range[1]), n))
+    else:
+        out[:, 3] = rng.uniform(a_range[0], a_range[1], n)
+    nc = int(round(core * n))
+    if nc:
+        out[:nc, 1] = rng.uniform(0.0, core_uv, nc)
+        out[:nc, 2] = rng.uniform(0.0, core_uv, nc)
+        out[:nc // 2, 0] = rng.uniform(0.0, core_d, nc // 2)
+        rng.shuffle(out, axis=0)
     return out
+
+
+def surrogate_init(seed: int, hidden: int = 64, n_in: int = 4):
+    """Seeded initial parameters of the 4 -> 64 -> 64 -> 1 surrogate (float32, 4545 values).
+
+    Layout W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3; weights uniform
+    in +-sqrt(6 / (fan_in + fan_out)), biases zero.
+    """
+    rng = np.random.default_rng(seed)
+    lim = lambda fi, fo: np.sqrt(6.0 / (fi + fo))
+    w1 = rng.uniform(-lim(n_in, hidden), lim(n_in, hidden), hidden * n_in)
+    w2 = rng.uniform(-lim(hidden, hidden), lim(hidden, hidden), hidden * hidden)
+    w3 = rng.uniform(-lim(hidden, 1), lim(hidden, 1), hidden)
+    z = np.zeros(hidden)
+    return np.concatenate([w1, z, w2, z, w3, [0.0]]).astype(np.float32)
 
 
 def table1_case(case: int, seed: int = 6) -> Problem:

@@ -265,6 +265,86 @@ fspb_status fspb_batch_check(fspb_batch *batch, void *stream);
 /* Release the batch's host state (graph included). NULL is a no-op. */
 void fspb_batch_destroy(fspb_batch *batch);
 
+/* ------------------------------------------------------------------------
+ * Learned kernel surrogate.  A 4 -> 64 -> 64 -> 1 perceptron with SiLU
+ * activations approximates K(d, u, v, a) = PDD(d) F(u, v; a, a, d) (Eq. 2-3
+ * without the inverse square) for square beamlets over the training box
+ * d in [0, 30] cm, |u|, |v| <= 3 cm, a in [0.25, 1] cm.  It is trained on
+ * the GPU by the library's own forward and backward kernels (BF16 matrix
+ * cores with FP32 accumulation for the 64 x 64 layer, FP32 elsewhere, Adam on
+ * FP32 master weights) from kernel values the analytic path generates.  A
+ * plan with a surrogate attached evaluates it inside the fill for every VOI
+ * voxel within the box and falls back to Eq. 2-3 outside it.
+ *
+ * Parameter vector (4545 FP32 values): W1[64][4], b1[64], W2[64][64], b2[64],
+ * W3[64], b3; W[o][i] maps input i to output o.  Inputs are the features
+ * 2 sqrt(d/30) - 1, 2 sqrt(|u|/3) - 1, 2 sqrt(|v|/3) - 1, (a - 0.625)/0.375.
+ * ------------------------------------------------------------------------ */
+typedef struct fspb_surrogate fspb_surrogate;
+
+#define FSPB_SURROGATE_PARAMS 4545
+
+typedef struct {
+    int32_t epochs;              /* passes over the sample set, >= 1 */
+    int32_t batch;               /* samples per step, multiple of 64, <= the max_batch of create */
+    float lr_max, lr_min;        /* cosine learning-rate schedule over all steps */
+    float beta1, beta2, eps;     /* Adam */
+    int32_t reserved;
+    uint64_t seed;               /* seeds the per-epoch sample order (SplitMix64 of seed, epoch) */
+} fspb_train_config;
+
+/*
+ * Create a surrogate for the kernel parameters `kernel` (its depth-dose table
+ * is copied; cutoffs and table_step are ignored) with initial parameters
+ * init_params (HOST, FSPB_SURROGATE_PARAMS floats).  max_batch bounds the
+ * training batch (multiple of 64).  workspace: DEVICE, 256-byte aligned,
+ * caller-owned; NULL = size query (returns CAPACITY).
+ */
+fspb_status fspb_surrogate_create(const fspb_kernel *kernel, const float *init_params, int32_t max_batch,
+                                  void *workspace, size_t workspace_bytes, size_t *workspace_needed,
+                                  fspb_surrogate **out);
+
+/*
+ * Training data from the analytic kernel: for n samples (DEVICE, [n][4] =
+ * d, u, v, a) write their features (DEVICE, [n][4]) and targets K (DEVICE, [n]).
+ */
+fspb_status fspb_surrogate_targets(fspb_surrogate *sur, const float *samples, int64_t n, float *features,
+                                   float *targets, void *stream);
+
+/* Outputs of the network for n feature rows (DEVICE in, DEVICE out). */
+fspb_status fspb_surrogate_forward(fspb_surrogate *sur, const float *features, int64_t n, float *out,
+                                   void *stream);
+
+/*
+ * Gradient of the mean squared error over n samples (n <= max_batch) with
+ * respect to every parameter: grad (DEVICE, FSPB_SURROGATE_PARAMS floats),
+ * *loss (HOST).  Synchronises `stream`.
+ */
+fspb_status fspb_surrogate_gradient(fspb_surrogate *sur, const float *features, const float *targets, int64_t n,
+                                    float *grad, float *loss, void *stream);
+
+/*
+ * Train on n samples (features/targets on the DEVICE).  loss_per_epoch (HOST,
+ * cfg->epochs floats, may be NULL) receives the mean squared error of each
+ * epoch's last batch.  Synchronises `stream` once per epoch.
+ */
+fspb_status fspb_surrogate_train(fspb_surrogate *sur, const float *features, const float *targets, int64_t n,
+                                 const fspb_train_config *cfg, float *loss_per_epoch, void *stream);
+
+/* Copy the parameters to / from HOST memory (FSPB_SURROGATE_PARAMS floats). */
+fspb_status fspb_surrogate_get_params(fspb_surrogate *sur, float *params, void *stream);
+fspb_status fspb_surrogate_set_params(fspb_surrogate *sur, const float *params);
+
+/*
+ * Attach a surrogate to a plan (NULL detaches it: analytic fill).  The plan's
+ * kernel parameters must equal the surrogate's (same terms, widths, sigma
+ * law and depth-dose table); the surrogate must outlive the attachment.
+ */
+fspb_status fspb_plan_set_surrogate(fspb_plan *plan, const fspb_surrogate *sur);
+
+/* Release the surrogate's host state. NULL is a no-op. */
+void fspb_surrogate_destroy(fspb_surrogate *sur);
+
 /* Human-readable name of a status code (static storage). */
 const char *fspb_status_string(fspb_status s);
 

@@ -92,6 +92,7 @@ def lib():
             "ofs_lateral": (d, [P(OKernel), d, d, d, d, d]),
             "ofs_dose": (d, [P(OKernel), P(OBeamlet), d, d, d, d]),
             "ofs_kernel_value": (d, [P(OKernel), d, d, d, d]),
+            "ofs_kernel_values": (None, [P(OKernel), P(d), i64, P(d)]),
             "ofs_voi_member": (i32, [P(OGrid), P(OKernel), P(OBeamlet), i32, i32, i32,
                                      P(d), P(d), P(d)]),
             "ofs_beamlet_row": (i64, [P(OGrid), P(OKernel), P(OBeamlet), P(d), P(C.c_int32),
@@ -248,8 +249,11 @@ class OraclePlan:
 
     def kernel_values(self, pts):
         """K(d, u, v, a) for an [n, 4] array."""
-        L = lib()
-        return np.array([L.ofs_kernel_value(C.byref(self.kernel), *map(float, p)) for p in pts])
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        out = np.zeros(pts.shape[0], dtype=np.float64)
+        lib().ofs_kernel_values(C.byref(self.kernel), _ptr(pts, C.c_double), pts.shape[0],
+                                _ptr(out, C.c_double))
+        return out
 
 
 def siddon(problem_or_plan, S, e, tA, tB):

@@ -368,6 +368,13 @@ double ofs_kernel_value(const ofs_kernel *K, double d, double u, double v, doubl
     return ofs_pdd(K, d) * ofs_lateral(K, u, v, a, a, d);
 }
 
+/* ofs_kernel_value at n points pts[n][4] = (d, u, v, a). */
+void ofs_kernel_values(const ofs_kernel *K, const double *pts, int64_t n, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = ofs_kernel_value(K, pts[4 * i], pts[4 * i + 1], pts[4 * i + 2], pts[4 * i + 3]);
+}
+
 /*
  * VOI membership of the voxel centre P (Sec. 2.1, last paragraph): with
  * w = P - S, t' = w.e, u = (w.eu) SAD / t', v = (w.ev) SAD / t', the voxel

@@ -8,10 +8,13 @@
  * PDD(d) F(u, v; a, a, d) (Eq. 2-3 without the inverse-square factor) with a
  * 4 -> 64 -> 64 -> 1 multilayer perceptron, SiLU activations, trained by mean
  * squared error.  Feature map (part of the model's definition):
- *   x0 = d / 15 - 1,  x1 = |u| / 1.5 - 1,  x2 = |v| / 1.5 - 1,
+ *   x0 = 2 sqrt(d / 30) - 1,  x1 = 2 sqrt(|u| / 3) - 1,  x2 = 2 sqrt(|v| / 3) - 1,
  *   x3 = (a - 0.625) / 0.375,
  * so the training box d in [0, 30], |u|, |v| in [0, 3], a in [0.25, 1] maps to
- * [-1, 1]^4.
+ * [-1, 1]^4.  The square roots spread the steep parts of K -- the depth-dose
+ * build-up near d = 0 and the beamlet edges near |u|, |v| = a/2 -- over more
+ * of the feature range; K is even in u and v and linear in d near 0, so it
+ * stays smooth in these coordinates.
  *
  * Parameter layout (4545 values): W1[64][4], b1[64], W2[64][64], b2[64],
  * W3[64], b3[1]; W[o][i] multiplies input i into output o.
@@ -65,9 +68,9 @@ static double silu_grad(double z)
 void ofs_surrogate_features(const double *raw, int64_t n, double *feat)
 {
     for (int64_t i = 0; i < n; ++i) {
-        feat[4 * i + 0] = raw[4 * i + 0] / 15.0 - 1.0;
-        feat[4 * i + 1] = fabs(raw[4 * i + 1]) / 1.5 - 1.0;
-        feat[4 * i + 2] = fabs(raw[4 * i + 2]) / 1.5 - 1.0;
+        feat[4 * i + 0] = 2.0 * sqrt(fmax(raw[4 * i + 0], 0.0) / 30.0) - 1.0;
+        feat[4 * i + 1] = 2.0 * sqrt(fabs(raw[4 * i + 1]) / 3.0) - 1.0;
+        feat[4 * i + 2] = 2.0 * sqrt(fabs(raw[4 * i + 2]) / 3.0) - 1.0;
         feat[4 * i + 3] = (raw[4 * i + 3] - 0.625) / 0.375;
     }
 }

@@ -62,6 +62,15 @@ class FspbBatchConfig(C.Structure):
                 ("tuned", C.c_int32), ("fill_ms", C.c_float), ("reserved", C.c_int32)]
 
 
+class FspbTrainConfig(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr_max", C.c_float), ("lr_min", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("reserved", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+SURROGATE_PARAMS = 4545
+
+
 class FspbPlanDesc(C.Structure):
     _fields_ = [("n_beamlets", C.c_int32), ("n_voxels", C.c_int32), ("table_entries", C.c_int64),
                 ("n_tiles", C.c_int64), ("max_table", C.c_int32), ("reserved", C.c_int32)]
@@ -91,6 +100,20 @@ _SIGS = {
     "fspb_batch_run": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fspb_batch_check": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fspb_batch_destroy": (None, [C.c_void_p]),
+    "fspb_surrogate_create": (C.c_int32, [C.POINTER(FspbKernel), C.POINTER(C.c_float), C.c_int32,
+                                          C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t),
+                                          C.POINTER(C.c_void_p)]),
+    "fspb_surrogate_targets": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                           C.c_void_p]),
+    "fspb_surrogate_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "fspb_surrogate_gradient": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                            C.POINTER(C.c_float), C.c_void_p]),
+    "fspb_surrogate_train": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                         C.POINTER(FspbTrainConfig), C.POINTER(C.c_float), C.c_void_p]),
+    "fspb_surrogate_get_params": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float), C.c_void_p]),
+    "fspb_surrogate_set_params": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float)]),
+    "fspb_plan_set_surrogate": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fspb_surrogate_destroy": (None, [C.c_void_p]),
     "fspb_status_string": (C.c_char_p, [C.c_int32]),
     "fspb_last_error": (C.c_char_p, []),
 }
@@ -232,3 +255,61 @@ def fspb_batch_check(batch, stream):
 
 def fspb_batch_destroy(batch):
     lib().fspb_batch_destroy(batch)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def fspb_surrogate_create(kernel, init_params, max_batch, workspace, workspace_bytes):
+    import numpy as np
+    init = np.ascontiguousarray(init_params, dtype=np.float32)
+    need = C.c_size_t(0)
+    handle = C.c_void_p(None)
+    st = lib().fspb_surrogate_create(C.byref(kernel), _fptr(init), max_batch, workspace, workspace_bytes,
+                                     C.byref(need), C.byref(handle))
+    if st not in (FSPB_OK, FSPB_ERR_CAPACITY):
+        _check(st)
+    return st, (handle.value if st == FSPB_OK else None), need.value
+
+
+def fspb_surrogate_targets(sur, samples, n, features, targets, stream):
+    return _check(lib().fspb_surrogate_targets(sur, samples, n, features, targets, stream))
+
+
+def fspb_surrogate_forward(sur, features, n, out, stream):
+    return _check(lib().fspb_surrogate_forward(sur, features, n, out, stream))
+
+
+def fspb_surrogate_gradient(sur, features, targets, n, grad, stream):
+    loss = C.c_float(0.0)
+    _check(lib().fspb_surrogate_gradient(sur, features, targets, n, grad, C.byref(loss), stream))
+    return loss.value
+
+
+def fspb_surrogate_train(sur, features, targets, n, cfg, stream):
+    import numpy as np
+    losses = np.zeros(cfg.epochs, dtype=np.float32)
+    _check(lib().fspb_surrogate_train(sur, features, targets, n, C.byref(cfg), _fptr(losses), stream))
+    return losses
+
+
+def fspb_surrogate_get_params(sur, stream):
+    import numpy as np
+    p = np.zeros(SURROGATE_PARAMS, dtype=np.float32)
+    _check(lib().fspb_surrogate_get_params(sur, _fptr(p), stream))
+    return p
+
+
+def fspb_surrogate_set_params(sur, params):
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    return _check(lib().fspb_surrogate_set_params(sur, _fptr(p)))
+
+
+def fspb_plan_set_surrogate(plan, sur):
+    return _check(lib().fspb_plan_set_surrogate(plan, sur))
+
+
+def fspb_surrogate_destroy(sur):
+    lib().fspb_surrogate_destroy(sur)

@@ -31,6 +31,8 @@ struct alignas(16) BeamletRec {
     float t1_f, U1_f, V1_f;   // change of t', U, V per voxel step along x
     float pad_f;
     float ha[kMaxTerms], hb[kMaxTerms];   // c2_k a/2, c2_k b/2
+    float a_f;                // beamlet side a (the surrogate's fourth input)
+    int32_t mlp_ok;           // square beamlet with a inside the surrogate's training box
     int32_t n_table;      // table points (0: axis misses the grid)
     int32_t table_off;    // first entry in the plan's table array
     int32_t iy0, n_iy;    // bounding rows of the VOI
@@ -69,6 +71,10 @@ struct alignas(16) PlanDev {
     int32_t *tile_count;         // [n_tiles]
     int64_t *row_nnz;            // [n_beamlets]
     int64_t *nnz;                // [1]
+    // attached kernel surrogate (use_mlp = 0: analytic fill)
+    const float *mlp_p;          // FP32 parameters
+    const uint16_t *mlp_w2;      // BF16 W2 [out][in]
+    int32_t use_mlp, pad1;
 };
 
 /* Caller-owned CSR output of one plan (device pointers). */

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "fspb_device.h"
+#include "fspb_mlp.h"
 
 using fspb::BeamletRec;
 using fspb::OutDev;
@@ -89,6 +90,10 @@ struct fspb_plan {
     int64_t table_entries = 0;
     int32_t n_voxels = 0;
     bool traced = false;
+    // kernel parameters (to check a surrogate against)
+    int32_t n_terms = 0;
+    double weight[4] = {}, sigma0[4] = {}, sigma_slope[4] = {}, width_scale[4] = {}, pdd_step = 0.0;
+    std::vector<float> pdd;
     // optional kernel timing: events bracket prep, raytrace, count, scan, fill
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -314,6 +319,15 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     }
     h.pdd_inv_step = (float)(1.0 / K->pdd_step);
     h.pdd_max = (float)(K->n_pdd - 1);
+    p->n_terms = K->n_terms;
+    for (int i = 0; i < K->n_terms; ++i) {
+        p->weight[i] = K->weight[i];
+        p->sigma0[i] = K->sigma0[i];
+        p->sigma_slope[i] = K->sigma_slope[i];
+        p->width_scale[i] = K->width_scale[i];
+    }
+    p->pdd_step = K->pdd_step;
+    p->pdd.assign(K->pdd, K->pdd + K->n_pdd);
     p->n_voxels = g->nx * g->ny * g->nz;
 
     // ---- beamlet geometry (FP64)
@@ -373,6 +387,9 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
                 R.t1_f = (float)(g->spacing[0] * e.x);
                 R.U1_f = (float)(g->spacing[0] * eu.x);
                 R.V1_f = (float)(g->spacing[0] * ev.x);
+                R.a_f = (float)B.beamlet_a;
+                R.mlp_ok = (B.beamlet_a == B.beamlet_b && B.beamlet_a >= fspb::kMlpAMin &&
+                            B.beamlet_a <= fspb::kMlpAMax) ? 1 : 0;
                 for (int i = 0; i < fspb::kMaxTerms; ++i) {
                     const double c2 = i < K->n_terms ? K->width_scale[i] : 1.0;
                     R.ha[i] = (float)(0.5 * c2 * B.beamlet_a);
@@ -1003,5 +1020,257 @@ fspb_status fspb_batch_check(fspb_batch *b, void *stream)
 }
 
 void fspb_batch_destroy(fspb_batch *b) { delete b; }
+
+}  // extern "C"
+
+/* ======================================================================
+ * Kernel surrogate
+ * ====================================================================== */
+
+struct fspb_surrogate {
+    fspb::MlpTargetDev tk{};
+    float *params = nullptr, *m1 = nullptr, *m2 = nullptr, *partials = nullptr, *grad = nullptr;
+    uint16_t *w2 = nullptr, *w2t = nullptr;
+    int32_t max_batch = 0;
+    int64_t adam_step = 0;
+    int32_t n_terms = 0;
+    double weight[4] = {}, sigma0[4] = {}, sigma_slope[4] = {}, width_scale[4] = {}, pdd_step = 0.0;
+    std::vector<float> pdd;
+};
+
+namespace {
+
+fspb::MlpDev mlp_view(const fspb_surrogate *s) { return fspb::MlpDev{s->params, s->w2, s->w2t}; }
+
+/* SplitMix64 (Steele, Lea and Flood 2014): the per-epoch sample order. */
+uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+uint64_t gcd_u64(uint64_t a, uint64_t b)
+{
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+fspb_status fspb_surrogate_create(const fspb_kernel *K, const float *init, int32_t max_batch, void *workspace,
+                                  size_t workspace_bytes, size_t *workspace_needed, fspb_surrogate **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(FSPB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!K || !init) return fail(FSPB_ERR_INVALID, "kernel or init_params is NULL");
+    if (K->n_terms < 1 || K->n_terms > 4) return fail(FSPB_ERR_INVALID, "kernel.n_terms must be 1..4");
+    for (int i = 0; i < K->n_terms; ++i)
+        if (!(K->sigma0[i] > 0.0) || !(K->sigma_slope[i] >= 0.0) || !(K->width_scale[i] > 0.0) ||
+            !std::isfinite(K->weight[i]))
+            return fail(FSPB_ERR_INVALID, "kernel term %d has invalid parameters", i);
+    if (!K->pdd || K->n_pdd < 2 || K->n_pdd > 4096 || !(K->pdd_step > 0.0))
+        return fail(FSPB_ERR_INVALID, "kernel depth-dose table is invalid");
+    if (max_batch < 64 || max_batch % 64 != 0 || max_batch > (1 << 20))
+        return fail(FSPB_ERR_INVALID, "max_batch must be a positive multiple of 64 (<= 2^20)");
+    for (int i = 0; i < fspb::kMlpParams; ++i)
+        if (!std::isfinite(init[i])) return fail(FSPB_ERR_INVALID, "init_params[%d] is not finite", i);
+    if (!workspace && !workspace_needed) return fail(FSPB_ERR_INVALID, "workspace and workspace_needed are both NULL");
+    const int waves = max_batch / 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t o_p = take(sizeof(float) * fspb::kPartialStride), o_m1 = take(sizeof(float) * fspb::kPartialStride);
+    const size_t o_m2 = take(sizeof(float) * fspb::kPartialStride), o_g = take(sizeof(float) * fspb::kPartialStride);
+    const size_t o_w2 = take(2 * fspb::kMlpH * fspb::kMlpH), o_w2t = take(2 * fspb::kMlpH * fspb::kMlpH);
+    const size_t o_pdd = take(sizeof(float) * K->n_pdd), o_erfc = take(sizeof(float4) * fspb::kErfcIntervals);
+    const size_t o_part = take(sizeof(float) * fspb::kPartialStride * (size_t)waves);
+    if (workspace_needed) *workspace_needed = off;
+    if (!workspace) return fail(FSPB_ERR_CAPACITY, "surrogate workspace query: %zu bytes needed", off);
+    if (workspace_bytes < off) return fail(FSPB_ERR_CAPACITY, "surrogate workspace too small (%zu < %zu)", workspace_bytes, off);
+    if ((uintptr_t)workspace % 256 != 0) return fail(FSPB_ERR_INVALID, "workspace must be 256-byte aligned");
+    fspb_surrogate *s = new (std::nothrow) fspb_surrogate;
+    if (!s) return fail(FSPB_ERR_NOMEM, "cannot allocate the surrogate");
+    std::unique_ptr<fspb_surrogate> guard(s);
+    char *ws = static_cast<char *>(workspace);
+    s->params = reinterpret_cast<float *>(ws + o_p);
+    s->m1 = reinterpret_cast<float *>(ws + o_m1);
+    s->m2 = reinterpret_cast<float *>(ws + o_m2);
+    s->grad = reinterpret_cast<float *>(ws + o_g);
+    s->w2 = reinterpret_cast<uint16_t *>(ws + o_w2);
+    s->w2t = reinterpret_cast<uint16_t *>(ws + o_w2t);
+    s->partials = reinterpret_cast<float *>(ws + o_part);
+    s->max_batch = max_batch;
+    s->n_terms = K->n_terms;
+    s->tk.n_terms = K->n_terms;
+    s->tk.n_pdd = K->n_pdd;
+    for (int i = 0; i < 4; ++i) {
+        const bool on = i < K->n_terms;
+        s->weight[i] = on ? K->weight[i] : 0.0;
+        s->sigma0[i] = on ? K->sigma0[i] : 0.0;
+        s->sigma_slope[i] = on ? K->sigma_slope[i] : 0.0;
+        s->width_scale[i] = on ? K->width_scale[i] : 0.0;
+        s->tk.w4[i] = on ? (float)(0.25 * K->weight[i]) : 0.0f;
+        s->tk.sig0[i] = on ? (float)K->sigma0[i] : 1.0f;
+        s->tk.sig1[i] = on ? (float)K->sigma_slope[i] : 0.0f;
+        s->tk.c2[i] = on ? (float)K->width_scale[i] : 1.0f;
+    }
+    s->pdd_step = K->pdd_step;
+    s->pdd.assign(K->pdd, K->pdd + K->n_pdd);
+    s->tk.pdd_inv_step = (float)(1.0 / K->pdd_step);
+    s->tk.pdd_max = (float)(K->n_pdd - 1);
+    s->tk.pdd = reinterpret_cast<float *>(ws + o_pdd);
+    s->tk.erfc_tab = reinterpret_cast<float4 *>(ws + o_erfc);
+    FSPB_HIP(hipMemcpy((void *)s->tk.pdd, K->pdd, sizeof(float) * K->n_pdd, hipMemcpyHostToDevice), "upload depth dose");
+    std::vector<float4> et;
+    erfc_table(et);
+    FSPB_HIP(hipMemcpy((void *)s->tk.erfc_tab, et.data(), sizeof(float4) * et.size(), hipMemcpyHostToDevice),
+             "upload erfc table");
+    FSPB_HIP(hipMemcpy(s->params, init, sizeof(float) * fspb::kMlpParams, hipMemcpyHostToDevice), "upload parameters");
+    FSPB_HIP(hipMemset(s->m1, 0, sizeof(float) * fspb::kPartialStride), "clear Adam moments");
+    FSPB_HIP(hipMemset(s->m2, 0, sizeof(float) * fspb::kPartialStride), "clear Adam moments");
+    FSPB_HIP(fspb::launch_mlp_bf16_copies(s->params, s->w2, s->w2t, nullptr), "launch bf16 copies");
+    FSPB_HIP(hipDeviceSynchronize(), "synchronise surrogate creation");
+    *out = guard.release();
+    return FSPB_OK;
+}
+
+fspb_status fspb_surrogate_targets(fspb_surrogate *s, const float *samples, int64_t n, float *features, float *targets,
+                                   void *stream)
+{
+    g_last_error.clear();
+    if (!s || !samples || !features || !targets || n < 0) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    FSPB_HIP(fspb::launch_mlp_targets(s->tk, samples, n, features, targets, static_cast<hipStream_t>(stream)),
+             "launch targets");
+    return FSPB_OK;
+}
+
+fspb_status fspb_surrogate_forward(fspb_surrogate *s, const float *features, int64_t n, float *out, void *stream)
+{
+    g_last_error.clear();
+    if (!s || !features || !out || n < 0) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    FSPB_HIP(fspb::launch_mlp_forward(mlp_view(s), features, n, out, static_cast<hipStream_t>(stream)),
+             "launch forward");
+    return FSPB_OK;
+}
+
+fspb_status fspb_surrogate_gradient(fspb_surrogate *s, const float *features, const float *targets, int64_t n,
+                                    float *grad, float *loss, void *stream)
+{
+    g_last_error.clear();
+    if (!s || !features || !targets || !grad || !loss) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    if (n < 1 || n > s->max_batch) return fail(FSPB_ERR_INVALID, "n must be 1..max_batch");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int waves = (int)((n + 63) / 64);
+    FSPB_HIP(fspb::launch_mlp_grad(mlp_view(s), features, targets, n, 0, n, 1, 0, 1.0f / (float)n, s->partials, st),
+             "launch gradient");
+    FSPB_HIP(fspb::launch_mlp_reduce(s->params, s->m1, s->m2, s->w2, s->w2t, s->partials, waves, 0, 0.f, 0.f, 0.f, 0.f,
+                                     1.f, 1.f, s->grad, st),
+             "launch reduce");
+    FSPB_HIP(hipMemcpyAsync(grad, s->grad, sizeof(float) * fspb::kMlpParams, hipMemcpyDeviceToDevice, st), "copy gradient");
+    float lsum = 0.0f;
+    FSPB_HIP(hipMemcpyAsync(&lsum, s->grad + fspb::kMlpParams, sizeof(float), hipMemcpyDeviceToHost, st), "read loss");
+    FSPB_HIP(hipStreamSynchronize(st), "synchronise gradient");
+    *loss = lsum / (float)n;
+    return FSPB_OK;
+}
+
+fspb_status fspb_surrogate_train(fspb_surrogate *s, const float *features, const float *targets, int64_t n,
+                                 const fspb_train_config *cfg, float *loss_per_epoch, void *stream)
+{
+    g_last_error.clear();
+    if (!s || !features || !targets || !cfg) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    if (cfg->epochs < 1 || cfg->batch < 64 || cfg->batch % 64 != 0 || cfg->batch > s->max_batch)
+        return fail(FSPB_ERR_INVALID, "epochs >= 1 and batch a multiple of 64 up to max_batch are required");
+    if (n < cfg->batch) return fail(FSPB_ERR_INVALID, "fewer samples than one batch");
+    if (!(cfg->lr_max > 0.0f) || !(cfg->lr_min >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
+        return fail(FSPB_ERR_INVALID, "invalid optimiser settings");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t steps = n / cfg->batch;
+    const int64_t total = steps * cfg->epochs;
+    const int waves = cfg->batch / 64;
+    int64_t k = 0;
+    for (int e = 0; e < cfg->epochs; ++e) {
+        // sample order of this epoch: i -> (offset + i stride) mod n with gcd(stride, n) = 1
+        const uint64_t r1 = splitmix64(cfg->seed ^ (0x51ed2701ull * (uint64_t)(e + 1)));
+        const uint64_t r2 = splitmix64(r1);
+        uint64_t stride = 1 + r1 % (uint64_t)(n - 1 > 0 ? n - 1 : 1);
+        while (gcd_u64(stride, (uint64_t)n) != 1) ++stride;
+        const uint64_t offset = r2 % (uint64_t)n;
+        for (int64_t b = 0; b < steps; ++b, ++k) {
+            const double frac = total > 1 ? (double)k / (double)(total - 1) : 1.0;
+            const float lr = (float)(cfg->lr_min + 0.5 * (cfg->lr_max - cfg->lr_min) * (1.0 + std::cos(kPi * frac)));
+            ++s->adam_step;
+            const float bc1 = (float)(1.0 - std::pow((double)cfg->beta1, (double)s->adam_step));
+            const float bc2 = (float)(1.0 - std::pow((double)cfg->beta2, (double)s->adam_step));
+            FSPB_HIP(fspb::launch_mlp_grad(mlp_view(s), features, targets, n, b * cfg->batch, cfg->batch, stride, offset,
+                                           1.0f / (float)cfg->batch, s->partials, st),
+                     "launch gradient");
+            FSPB_HIP(fspb::launch_mlp_reduce(s->params, s->m1, s->m2, s->w2, s->w2t, s->partials, waves, 1, lr,
+                                             cfg->beta1, cfg->beta2, cfg->eps, bc1, bc2,
+                                             b == steps - 1 ? s->grad : nullptr, st),
+                     "launch Adam");
+        }
+        float lsum = 0.0f;
+        FSPB_HIP(hipMemcpyAsync(&lsum, s->grad + fspb::kMlpParams, sizeof(float), hipMemcpyDeviceToHost, st), "read loss");
+        FSPB_HIP(hipStreamSynchronize(st), "synchronise epoch");
+        if (loss_per_epoch) loss_per_epoch[e] = lsum / (float)cfg->batch;
+    }
+    return FSPB_OK;
+}
+
+fspb_status fspb_surrogate_get_params(fspb_surrogate *s, float *params, void *stream)
+{
+    g_last_error.clear();
+    if (!s || !params) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    FSPB_HIP(hipMemcpyAsync(params, s->params, sizeof(float) * fspb::kMlpParams, hipMemcpyDeviceToHost, st), "read parameters");
+    FSPB_HIP(hipStreamSynchronize(st), "synchronise parameters");
+    return FSPB_OK;
+}
+
+fspb_status fspb_surrogate_set_params(fspb_surrogate *s, const float *params)
+{
+    g_last_error.clear();
+    if (!s || !params) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    for (int i = 0; i < fspb::kMlpParams; ++i)
+        if (!std::isfinite(params[i])) return fail(FSPB_ERR_INVALID, "params[%d] is not finite", i);
+    FSPB_HIP(hipMemcpy(s->params, params, sizeof(float) * fspb::kMlpParams, hipMemcpyHostToDevice), "upload parameters");
+    FSPB_HIP(fspb::launch_mlp_bf16_copies(s->params, s->w2, s->w2t, nullptr), "launch bf16 copies");
+    FSPB_HIP(hipDeviceSynchronize(), "synchronise parameters");
+    return FSPB_OK;
+}
+
+fspb_status fspb_plan_set_surrogate(fspb_plan *p, const fspb_surrogate *s)
+{
+    g_last_error.clear();
+    if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
+    if (s) {
+        bool same = s->n_terms == p->n_terms && s->pdd_step == p->pdd_step && s->pdd == p->pdd;
+        for (int i = 0; same && i < p->n_terms; ++i)
+            same = s->weight[i] == p->weight[i] && s->sigma0[i] == p->sigma0[i] &&
+                   s->sigma_slope[i] == p->sigma_slope[i] && s->width_scale[i] == p->width_scale[i];
+        if (!same) return fail(FSPB_ERR_INVALID, "the surrogate was built for different kernel parameters");
+    }
+    p->h.mlp_p = s ? s->params : nullptr;
+    p->h.mlp_w2 = s ? s->w2 : nullptr;
+    p->h.use_mlp = s ? 1 : 0;
+    FSPB_HIP(hipMemcpy(p->d_plan, &p->h, sizeof(PlanDev), hipMemcpyHostToDevice), "upload plan record");
+    return FSPB_OK;
+}
+
+void fspb_surrogate_destroy(fspb_surrogate *s) { delete s; }
 
 }  // extern "C"

@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include "fspb_device.h"
+#include "fspb_mlp_device.h"
 
 namespace fspb {
 
@@ -436,7 +437,7 @@ __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readla
  * are flattened across its rows, 64 per chunk, members compacted by ballot.
  * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K).
  */
-template <int K, int W, bool GUARD>
+template <int K, int W, bool GUARD, bool SURR>
 __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem)
 {
     const BeamletRec &R = P.rec[j];
@@ -481,6 +482,14 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     float2 *s_pdd = s_tab + P.max_table;
     int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
     __shared__ int wsum[W];
+    // surrogate: per-wave h1 tile after the tile prefix, and W2 fragments in registers
+    uint16_t *s_h1 = reinterpret_cast<uint16_t *>(
+        smem + ((sizeof(float4) * kErfcIntervals + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
+                 sizeof(int) * ((size_t)P.max_tiles + 1) + 15) & ~(size_t)15)) + wave * (64 * mlp::kH1Stride);
+    mlp::W2Frags wf;
+    if (SURR) mlp::load_w2_frags(P.mlp_w2, wf);
+    const float a_f = R.a_f;
+    const bool mlp_ok = SURR && R.mlp_ok;
 
     {
         const float4 *et = P.erfc_tab;
@@ -565,10 +574,29 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             const gptr<int32_t> ip = out_idx + written;
             const gptr<float> vp = out_val + written;
             const bool room = written + kWave <= capacity;
+            float D = 0.0f;
+            if (SURR) {
+                // the network runs on all 64 lanes (matrix cores need the whole wave)
+                const float kf = (float)k;
+                const float sv = fmaf(kf, t1f, sl), Uv = fmaf(kf, U1f, ul), Vv = fmaf(kf, V1f, vl);
+                const float g = c.sad * __builtin_amdgcn_rcpf(sv + c.tA);
+                const float au = fabsf(Uv * g), av = fabsf(Vv * g);
+                const float tau = __builtin_amdgcn_fmed3f(sv * c.inv_step, 0.0f, c.tau_max);
+                const float2 q = s_tab[(int)tau];
+                const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
+                const bool in_box = member && mlp_ok && d <= kMlpDMax && au <= kMlpUVMax &&
+                                    av <= kMlpUVMax;
+                float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (in_box) mlp::features(d, au, av, a_f, x);
+                const float y = mlp::forward_wave(P.mlp_p, wf, x, s_h1);
+                if (in_box) D = y * g * g;
+                else if (member) D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erfc, sv, Uv, Vv);
+            }
             if (member) {
                 const float kf = (float)k;
-                const float D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erfc, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
-                                              fmaf(kf, V1f, vl));
+                if (!SURR)
+                    D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erfc, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                             fmaf(kf, V1f, vl));
                 if (room || written + slot < capacity) {
                     ip[slot] = gr * nx + ix;
                     vp[slot] = D;
@@ -581,12 +609,12 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     }
 }
 
-template <int K>
+template <int K, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    fill_beamlet<K, kWavesPerBlock, false>(plans[0], outs[0], blockIdx.x, smem);
+    fill_beamlet<K, kWavesPerBlock, false, SURR>(plans[0], outs[0], blockIdx.x, smem);
 }
 
 /* ------------------------------------------------------------ batches */
@@ -646,7 +674,7 @@ __global__ __launch_bounds__(W * kWave) void kp_fill(const PlanDev *const *__res
         __syncthreads();
         if (w >= n_items) break;
         const int2 it = items[w];
-        fill_beamlet<K, W, true>(*plans[it.x], outs[it.x], it.y, smem);
+        fill_beamlet<K, W, true, false>(*plans[it.x], outs[it.x], it.y, smem);
         __syncthreads();
     }
 }
@@ -698,8 +726,10 @@ hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const Pl
 
 size_t fill_shared_bytes(const PlanDev &h)
 {
-    return sizeof(float4) * kErfcIntervals + sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) +
-           sizeof(int) * ((size_t)h.max_tiles + 1);
+    size_t b = sizeof(float4) * kErfcIntervals + sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) +
+               sizeof(int) * ((size_t)h.max_tiles + 1);
+    if (h.use_mlp) b = ((b + 15) & ~(size_t)15) + sizeof(uint16_t) * 64 * mlp::kH1Stride * kWavesPerBlock;
+    return b;
 }
 
 hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,
@@ -755,11 +785,20 @@ hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &
 {
     const dim3 grid(h.n_beamlets), block(kBlock);
     const size_t lds = fill_shared_bytes(h);
-    switch (h.n_terms) {
-    case 1: hipLaunchKernelGGL(k_fill<1>, grid, block, lds, s, dplan, dout); break;
-    case 2: hipLaunchKernelGGL(k_fill<2>, grid, block, lds, s, dplan, dout); break;
-    case 3: hipLaunchKernelGGL(k_fill<3>, grid, block, lds, s, dplan, dout); break;
-    default: hipLaunchKernelGGL(k_fill<4>, grid, block, lds, s, dplan, dout); break;
+    if (h.use_mlp) {
+        switch (h.n_terms) {
+        case 1: hipLaunchKernelGGL((k_fill<1, true>), grid, block, lds, s, dplan, dout); break;
+        case 2: hipLaunchKernelGGL((k_fill<2, true>), grid, block, lds, s, dplan, dout); break;
+        case 3: hipLaunchKernelGGL((k_fill<3, true>), grid, block, lds, s, dplan, dout); break;
+        default: hipLaunchKernelGGL((k_fill<4, true>), grid, block, lds, s, dplan, dout); break;
+        }
+    } else {
+        switch (h.n_terms) {
+        case 1: hipLaunchKernelGGL((k_fill<1, false>), grid, block, lds, s, dplan, dout); break;
+        case 2: hipLaunchKernelGGL((k_fill<2, false>), grid, block, lds, s, dplan, dout); break;
+        case 3: hipLaunchKernelGGL((k_fill<3, false>), grid, block, lds, s, dplan, dout); break;
+        default: hipLaunchKernelGGL((k_fill<4, false>), grid, block, lds, s, dplan, dout); break;
+        }
     }
     return hipGetLastError();
 }

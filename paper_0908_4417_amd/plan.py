@@ -73,7 +73,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and L is not None and L.fspb_plan_destroy is not None:
             L.fspb_plan_destroy(h)
             self.handle = None
 
@@ -107,6 +107,11 @@ class Plan:
         self.raytrace(stream)
         nnz = self.dose_coeffs(stream)
         return CSR(self.indptr, self.indices[:nnz], self.values[:nnz], self.n_voxels)
+
+    def set_surrogate(self, sur):
+        """Attach a trained ``Surrogate`` (None: analytic fill)."""
+        L.fspb_plan_set_surrogate(self.handle, sur.handle if sur is not None else None)
+        self._surrogate = sur
 
     def tables(self, stream=None):
         """Depth tables copied to host: (float32 values, int64 offsets)."""
@@ -148,7 +153,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and L is not None and L.fspb_batch_destroy is not None:
             L.fspb_batch_destroy(h)
             self.handle = None
 
@@ -175,3 +180,69 @@ class Batch:
     def outputs(self):
         return [CSR(self.indptr[i], self.indices[i][:self.nnz[i]], self.values[i][:self.nnz[i]],
                     p.n_voxels) for i, p in enumerate(self.plans)]
+
+
+def _kernel_struct(kp):
+    pdd = np.ascontiguousarray(kp.pdd, dtype=np.float32)
+    pad = lambda v: (C.c_double * 4)(*(list(v) + [0.0] * (4 - len(v))))
+    k = L.FspbKernel(kp.n_terms, len(pdd), pad(kp.weight), pad(kp.sigma0), pad(kp.sigma_slope),
+                     pad(kp.width_scale), pdd.ctypes.data_as(C.POINTER(C.c_float)), kp.pdd_step,
+                     kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min, 0)
+    return k, pdd
+
+
+class Surrogate:
+    """Learned kernel surrogate on the GPU (4 -> 64 -> 64 -> 1 SiLU perceptron)."""
+
+    def __init__(self, kernel_params, init_params, max_batch=16384, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        k, self._pdd = _kernel_struct(kernel_params)
+        st, _, need = L.fspb_surrogate_create(k, init_params, max_batch, None, 0)
+        self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        st, self.handle, _ = L.fspb_surrogate_create(k, init_params, max_batch, aligned, need)
+        self.max_batch = max_batch
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and L is not None and L.fspb_surrogate_destroy is not None:
+            L.fspb_surrogate_destroy(h)
+            self.handle = None
+
+    def _stream(self, stream=None):
+        s = stream if stream is not None else self.torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def targets(self, samples):
+        """samples: device float32 [n, 4] (d, u, v, a) -> (features [n, 4], targets [n])."""
+        n = samples.shape[0]
+        f = self.torch.empty((n, 4), dtype=self.torch.float32, device=self.device)
+        t = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        L.fspb_surrogate_targets(self.handle, samples.data_ptr(), n, f.data_ptr(), t.data_ptr(), self._stream())
+        return f, t
+
+    def forward(self, features):
+        n = features.shape[0]
+        out = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        L.fspb_surrogate_forward(self.handle, features.data_ptr(), n, out.data_ptr(), self._stream())
+        return out
+
+    def gradient(self, features, targets):
+        g = self.torch.empty(L.SURROGATE_PARAMS, dtype=self.torch.float32, device=self.device)
+        loss = L.fspb_surrogate_gradient(self.handle, features.data_ptr(), targets.data_ptr(),
+                                         features.shape[0], g.data_ptr(), self._stream())
+        return g, loss
+
+    def train(self, features, targets, epochs, batch=8192, lr_max=3e-3, lr_min=1e-5, seed=0,
+              beta1=0.9, beta2=0.999, eps=1e-8):
+        cfg = L.FspbTrainConfig(epochs, batch, lr_max, lr_min, beta1, beta2, eps, 0, seed)
+        return L.fspb_surrogate_train(self.handle, features.data_ptr(), targets.data_ptr(),
+                                      features.shape[0], cfg, self._stream())
+
+    def get_params(self):
+        return L.fspb_surrogate_get_params(self.handle, self._stream())
+
+    def set_params(self, params):
+        L.fspb_surrogate_set_params(self.handle, params)

@@ -126,3 +126,50 @@ def test_host_pointer_rejected_as_density(fspb):
     base = (ws.ctypes.data + 255) // 256 * 256
     st, need, h = _create(fspb, grid, beams, 2, kern, ws=base, nbytes=(1 << 20) - 256)
     assert st in (fspb.FSPB_ERR_INVALID, fspb.FSPB_ERR_CAPACITY) and h is None
+
+
+def test_batch_arguments_rejected(fspb):
+    L = fspb.lib()
+    h = C.c_void_p(None)
+    need = C.c_size_t(0)
+    assert L.fspb_batch_create(None, 1, None, 0, C.byref(need), None, C.byref(h)) == fspb.FSPB_ERR_INVALID
+    arr = (C.c_void_p * 2)(None, None)
+    assert L.fspb_batch_create(arr, 2, None, 0, C.byref(need), None, C.byref(h)) == fspb.FSPB_ERR_INVALID
+    assert "plans[0] is NULL" in fspb.fspb_last_error()
+    assert L.fspb_batch_create(arr, 0, None, 0, C.byref(need), None, C.byref(h)) == fspb.FSPB_ERR_INVALID
+    n = C.c_int64(0)
+    assert L.fspb_batch_nnz(None, 0, C.byref(n)) == fspb.FSPB_ERR_INVALID
+    assert L.fspb_batch_run(None, None) == fspb.FSPB_ERR_INVALID
+    assert L.fspb_batch_check(None, None) == fspb.FSPB_ERR_INVALID
+    assert L.fspb_batch_tune(None, None) == fspb.FSPB_ERR_INVALID
+    cfg = fspb.FspbBatchConfig(3, 4, 0, 0, 0.0, 0)
+    assert L.fspb_batch_set_config(None, C.byref(cfg)) == fspb.FSPB_ERR_INVALID
+    L.fspb_batch_destroy(None)
+
+
+def test_surrogate_arguments_rejected(fspb):
+    from paper_0908_4417_amd.plan import _kernel_struct
+    L = fspb.lib()
+    k, pdd = _kernel_struct(fi.default_kernel(0))
+    init = np.zeros(fspb.SURROGATE_PARAMS, dtype=np.float32)
+    ip = init.ctypes.data_as(C.POINTER(C.c_float))
+    h = C.c_void_p(None)
+    need = C.c_size_t(0)
+    # size query works without a device
+    assert L.fspb_surrogate_create(C.byref(k), ip, 4096, None, 0, C.byref(need), C.byref(h)) == \
+        fspb.FSPB_ERR_CAPACITY and need.value > 0
+    assert L.fspb_surrogate_create(C.byref(k), ip, 100, None, 0, C.byref(need), C.byref(h)) == \
+        fspb.FSPB_ERR_INVALID                                     # not a multiple of 64
+    bad = init.copy()
+    bad[17] = np.inf
+    assert L.fspb_surrogate_create(C.byref(k), bad.ctypes.data_as(C.POINTER(C.c_float)), 4096, None, 0,
+                                   C.byref(need), C.byref(h)) == fspb.FSPB_ERR_INVALID
+    assert "init_params[17]" in fspb.fspb_last_error()
+    k.n_terms = 0
+    assert L.fspb_surrogate_create(C.byref(k), ip, 4096, None, 0, C.byref(need), C.byref(h)) == \
+        fspb.FSPB_ERR_INVALID
+    assert L.fspb_plan_set_surrogate(None, None) == fspb.FSPB_ERR_INVALID
+    assert L.fspb_surrogate_forward(None, None, 0, None, None) == fspb.FSPB_ERR_INVALID
+    cfg = fspb.FspbTrainConfig(1, 64, 1e-3, 0.0, 0.9, 0.999, 1e-8, 0, 0)
+    assert L.fspb_surrogate_train(None, None, None, 0, C.byref(cfg), None, None) == fspb.FSPB_ERR_INVALID
+    L.fspb_surrogate_destroy(None)

@@ -1,0 +1,123 @@
+"""The learned kernel surrogate on the GPU (through the C ABI) against the FP64 oracle.
+
+* training targets: the GPU's FP32 analytic K(d, u, v, a) vs the oracle's FP64 value;
+* forward pass: GPU (BF16 matrix cores, FP32 elsewhere) vs the oracle's MLP with the
+  same BF16 rounding points;
+* gradient of the mean squared error: GPU backward vs the oracle's backprop with the
+  same BF16 rounding (relative L2 error <= 1e-3), on a batch that is not a multiple of 64.
+"""
+import numpy as np
+import pytest
+
+import fspb_inputs as fi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _sur(params):
+    from paper_0908_4417_amd import Surrogate
+    return Surrogate(fi.default_kernel(3), params, max_batch=4096)
+
+
+def _ora(oracle_lib):
+    g = fi.water_phantom((4, 4, 4), (1.0, 1.0, 1.0))
+    return oracle_lib.OraclePlan(fi.Problem("k", g, fi.coplanar_beams(1, (0, 0, 0), 100.0, 1, 1, 1, 1),
+                                            fi.default_kernel(3)))
+
+
+def test_targets_match_oracle(torch_gpu, oracle_lib):
+    torch = torch_gpu
+    sur = _sur(fi.surrogate_init(1))
+    raw = fi.surrogate_samples(20000, seed=11)
+    f, t = sur.targets(torch.from_numpy(raw.astype(np.float32)).to("cuda:0"))
+    ref = _ora(oracle_lib).kernel_values(raw.astype(np.float32).astype(np.float64))
+    got = t.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= 2e-6 * ref.max()
+    feats = oracle_lib.surrogate_features(raw.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(f.cpu().numpy(), feats, rtol=0, atol=2e-7)
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_forward_matches_bf16_oracle(torch_gpu, oracle_lib, seed):
+    torch = torch_gpu
+    p = fi.surrogate_init(seed)
+    p[256:320] = np.random.default_rng(seed).normal(0, 0.3, 64)        # non-zero biases
+    p[4416:4480] = np.random.default_rng(seed + 1).normal(0, 0.3, 64)
+    p[-1] = 0.17
+    sur = _sur(p)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, (1000, 4)).astype(np.float32)
+    y = sur.forward(torch.from_numpy(x).to("cuda:0")).cpu().numpy().astype(np.float64)
+    ref = oracle_lib.mlp_forward(p.astype(np.float64), x.astype(np.float64), bf16=True)
+    err = np.abs(y - ref)
+    scale = np.max(np.abs(ref))
+    assert err.max() <= 2e-3 * scale, err.max() / scale
+    assert np.sqrt(np.mean(err ** 2)) <= 2e-4 * scale
+
+
+def test_gradient_matches_bf16_oracle(torch_gpu, oracle_lib):
+    torch = torch_gpu
+    p = fi.surrogate_init(4)
+    rng = np.random.default_rng(4)
+    p[256:320] = rng.normal(0, 0.2, 64)
+    p[4416:4480] = rng.normal(0, 0.2, 64)
+    sur = _sur(p)
+    n = 1000                                                          # 15 full waves + a ragged one
+    x = rng.uniform(-1, 1, (n, 4)).astype(np.float32)
+    t = rng.uniform(0, 1, n).astype(np.float32)
+    g, loss = sur.gradient(torch.from_numpy(x).to("cuda:0"), torch.from_numpy(t).to("cuda:0"))
+    g = g.cpu().numpy().astype(np.float64)
+    ref_loss, ref = oracle_lib.mlp_loss_grad(p.astype(np.float64), x.astype(np.float64),
+                                             t.astype(np.float64), bf16=True)
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    print(f"gradient relative L2 error {rel:.2e}", flush=True)
+    assert rel <= 1e-3
+    # every parameter block individually
+    for name, a, b in [("W1", 0, 256), ("b1", 256, 320), ("W2", 320, 4416), ("b2", 4416, 4480),
+                       ("W3", 4480, 4544), ("b3", 4544, 4545)]:
+        r = np.linalg.norm(g[a:b] - ref[a:b]) / max(np.linalg.norm(ref[a:b]), 1e-30)
+        assert r <= 2e-3, (name, r)
+
+
+def test_training_is_deterministic(torch_gpu):
+    """Per-wave gradient partials are summed in a fixed order: same seed, same bits."""
+    torch = torch_gpu
+    raw = fi.surrogate_samples(200_000, seed=21, core=0.5, log_a=True).astype(np.float32)
+    outs = []
+    for _ in range(2):
+        sur = _sur(fi.surrogate_init(9))
+        f, t = sur.targets(torch.from_numpy(raw).to("cuda:0"))
+        losses = sur.train(f, t, epochs=3, batch=4096, lr_max=3e-3, lr_min=1e-5, seed=9)
+        outs.append((sur.get_params(), losses))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1][-1] < outs[0][1][0]
+
+
+def test_fallback_outside_the_training_box(torch_gpu):
+    """Beamlets narrower than the box (a = 0.2) never use the network: bit-identical to analytic."""
+    torch = torch_gpu
+    from paper_0908_4417_amd import Plan
+    g = fi.slab_phantom(3, n=(40, 40, 30), spacing=(0.5, 0.5, 0.5), lung_side=(3, 6), bone_side=(1, 2))
+    prob = fi.Problem("narrow", g, fi.coplanar_beams(2, (0.1, 0.0, 0.05), 100.0, 0.2, 0.2, 4, 4),
+                      fi.default_kernel(3))
+    plan = Plan(prob, "cuda:0")
+    a = plan.compute()
+    ai, av = a.indices.clone(), a.values.clone()
+    sur = _sur(fi.surrogate_init(3))
+    plan.set_surrogate(sur)
+    b = plan.compute()
+    assert torch.equal(ai, b.indices) and torch.equal(av, b.values)
+    # a plan with other kernel parameters is refused
+    import paper_0908_4417_amd as m
+    other = Plan(fi.Problem("o", g, prob.beams, fi.default_kernel(4)), "cuda:0")
+    with pytest.raises(m.FspbError, match="different kernel"):
+        other.set_surrogate(sur)

@@ -2,7 +2,8 @@
 
 * backpropagation equals central finite differences of the loss (FP64);
 * bfloat16 rounding is round-to-nearest-even on the float32 bit pattern;
-* the feature map sends the training box onto [-1, 1]^4.
+* the feature map (square-root stretch of d, |u|, |v|) sends the training box
+  onto [-1, 1]^4, its centre in square-root coordinates onto 0.
 """
 import numpy as np
 import pytest
@@ -71,6 +72,6 @@ def test_bf16_mode_differs_only_by_rounding(oracle_lib):
 
 
 def test_feature_map_box(oracle_lib):
-    raw = np.array([[0.0, 0.0, 0.0, 0.25], [30.0, -3.0, 3.0, 1.0], [15.0, 1.5, -1.5, 0.625]])
+    raw = np.array([[0.0, 0.0, 0.0, 0.25], [30.0, -3.0, 3.0, 1.0], [7.5, 0.75, -0.75, 0.625]])
     f = oracle_lib.surrogate_features(raw)
     np.testing.assert_allclose(f, [[-1, -1, -1, -1], [1, 1, 1, 1], [0, 0, 0, 0]], atol=1e-15)
