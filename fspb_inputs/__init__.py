@@ -343,7 +343,7 @@ def batched_configs(n_plans: int = 32, base_seed: int = 4000, scale: float = 1.0
 
 def surrogate_samples(n: int, seed: int, d_max: float = 30.0, uv_max: float = 3.0,
                       a_range=(0.25, 1.0), core: float = 0.0, core_uv: float = 1.0, core_d: float = 5.0,
-                      log_a: bool = False):
+                      log_a: bool = False, sqrt_uniform: bool = False, zero_depth: float = 0.0):
     """Training/evaluation points (d, |u|, |v|, a) for the kernel surrogate.
 
     float64 array [n, 4]; the profile is even in u and v, so only |u|, |v|
@@ -352,22 +352,36 @@ def surrogate_samples(n: int, seed: int, d_max: float = 30.0, uv_max: float = 3.
     half of it also restricted to the build-up region d <= core_d (where the
     kernel is largest and steepest).  With ``log_a`` the beamlet side is drawn
     log-uniformly (narrow beamlets, whose profiles are sharpest, get more
-    samples).
+    samples).  With ``sqrt_uniform`` d, |u|, |v| are drawn as max * s^2 with s
+    uniform, i.e. uniformly in the surrogate's square-root feature
+    coordinates (dense near d = 0 and near the beamlet axis).  A fraction
+    ``zero_depth`` of the points gets d = 0 exactly: every voxel whose
+    projection on a beamlet axis lies before the entry point, or behind air
+    only, has zero radiological depth, so the fill meets that value often.
     """
     rng = np.random.default_rng(seed)
     out = np.empty((n, 4), dtype=np.float64)
-    out[:, 0] = rng.uniform(0.0, d_max, n)
-    out[:, 1] = rng.uniform(0.0, uv_max, n)
-    out[:, 2] = rng.uniform(0.0, uv_max, n)
+    if sqrt_uniform:
+        out[:, 0] = d_max * rng.uniform(0.0, 1.0, n) ** 2
+        out[:, 1] = uv_max * rng.uniform(0.0, 1.0, n) ** 2
+        out[:, 2] = uv_max * rng.uniform(0.0, 1.0, n) ** 2
+    else:
+        out[:, 0] = rng.uniform(0.0, d_max, n)
+        out[:, 1] = rng.uniform(0.0, uv_max, n)
+        out[:, 2] = rng.uniform(0.0, uv_max, n)
     if log_a:
         out[:, 3] = np.exp(rng.uniform(np.log(a_range[0]), np.log(a_range[1]), n))
     else:
         out[:, 3] = rng.uniform(a_range[0], a_range[1], n)
+    nz0 = int(round(zero_depth * n))
+    if nz0:
+        out[-nz0:, 0] = 0.0
     nc = int(round(core * n))
     if nc:
         out[:nc, 1] = rng.uniform(0.0, core_uv, nc)
         out[:nc, 2] = rng.uniform(0.0, core_uv, nc)
         out[:nc // 2, 0] = rng.uniform(0.0, core_d, nc // 2)
+    if nc or nz0:
         rng.shuffle(out, axis=0)
     return out
 

@@ -345,6 +345,29 @@ fspb_status fspb_plan_set_surrogate(fspb_plan *plan, const fspb_surrogate *sur);
 /* Release the surrogate's host state. NULL is a no-op. */
 void fspb_surrogate_destroy(fspb_surrogate *sur);
 
+/* ------------------------------------------------------------------------
+ * Dose superposition (Eq. 1: D(x) = sum_j w_j D_j(x)) and its adjoint on a
+ * D_ij CSR produced above (rows = beamlets, columns = voxels).
+ * ------------------------------------------------------------------------ */
+
+/*
+ * dose[i] = sum_j w[j] D_ij.  indptr (n_rows + 1), indices, values, w (n_rows)
+ * and dose (n_voxels) are DEVICE pointers; dose is overwritten.  Entries are
+ * added with FP32 atomics, so the rounding of each voxel's sum depends on
+ * the order in which rows land (the value itself is the same to FP32
+ * precision).
+ */
+fspb_status fspb_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
+                              int32_t n_voxels, const float *w, float *dose, void *stream);
+
+/*
+ * g[j] = sum_i D_ij r[i] (the gradient of sum_i r_i D_i with respect to the
+ * beamlet weights).  DEVICE pointers; g has n_rows entries and is overwritten.
+ * Each row is summed by one wave in a fixed order: deterministic.
+ */
+fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values,
+                                  int32_t n_rows, const float *r, float *g, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *fspb_status_string(fspb_status s);
 

@@ -104,6 +104,7 @@ def lib():
             "ofs_plan_tables": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(d), P(i64)]),
             "ofs_plan_counts": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(i64)]),
             "ofs_plan_counts_sel": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(i32), i32, P(i64)]),
+            "ofs_plan_fluence": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(d), P(d), P(d), P(d)]),
             "ofs_plan_rows": (i32, [P(OGrid), P(OBeam), i32, P(OKernel), P(i32), i32, P(i64),
                                     P(i32), P(d)]),
             "ofs_mlp_nparams": (i32, []),
@@ -223,6 +224,23 @@ class OraclePlan:
         """Every row (small problems only)."""
         c = self.counts()
         return self.rows(np.arange(self.n_beamlets), c)
+
+    def fluence_dose(self, w):
+        """Eq. 1: dose of beamlet weights w (FP64, every row computed)."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        nv = self.grid.nx * self.grid.ny * self.grid.nz
+        dose = np.zeros(nv, dtype=np.float64)
+        lib().ofs_plan_fluence(C.byref(self.grid), self.beams, self.n_beams, C.byref(self.kernel),
+                               _ptr(w, C.c_double), _ptr(dose, C.c_double), None, None)
+        return dose
+
+    def fluence_gradient(self, r):
+        """g_j = sum_i D_ij r_i."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        g = np.zeros(self.n_beamlets, dtype=np.float64)
+        lib().ofs_plan_fluence(C.byref(self.grid), self.beams, self.n_beams, C.byref(self.kernel),
+                               None, None, _ptr(r, C.c_double), _ptr(g, C.c_double))
+        return g
 
     # -- point evaluations ---------------------------------------------
     def voi_member(self, j, ix, iy, iz):

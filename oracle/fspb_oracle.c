@@ -566,3 +566,43 @@ int32_t ofs_plan_rows(const ofs_grid *g, const ofs_beam *beams, int32_t n_beams,
     free(bl);
     return bad ? -1 : 0;
 }
+
+/*
+ * Dose of a fluence (Eq. 1): dose[i] = sum_j w[j] D_ij over every beamlet row,
+ * and the adjoint g[j] = sum_i D_ij r[i] (g or r may be NULL to skip it).
+ * dose is overwritten.  Rows are computed independently and added under an
+ * atomic update per voxel.
+ */
+int32_t ofs_plan_fluence(const ofs_grid *g, const ofs_beam *beams, int32_t n_beams, const ofs_kernel *K,
+                         const double *w, double *dose, const double *r, double *grad)
+{
+    int32_t nb = ofs_count_beamlets(beams, n_beams);
+    ofs_beamlet *bl = (ofs_beamlet *)malloc(sizeof(ofs_beamlet) * (size_t)nb);
+    ofs_geometry(g, beams, n_beams, K, bl);
+    int64_t nvox = (int64_t)g->nx * g->ny * g->nz;
+    if (dose) memset(dose, 0, sizeof(double) * (size_t)nvox);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t j = 0; j < nb; ++j) {
+        const ofs_beamlet *b = &bl[j];
+        double *table = (double *)malloc(sizeof(double) * (size_t)(b->n > 0 ? b->n : 1));
+        ofs_depth_table(g, b, table);
+        int64_t n = ofs_beamlet_row(g, K, b, table, NULL, NULL, 0);
+        int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        double *val = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        ofs_beamlet_row(g, K, b, table, idx, val, n);
+        double acc = 0.0;
+        for (int64_t e = 0; e < n; ++e) {
+            if (dose && w) {
+#pragma omp atomic
+                dose[idx[e]] += w[j] * val[e];
+            }
+            if (r) acc += val[e] * r[idx[e]];
+        }
+        if (grad) grad[j] = acc;
+        free(idx);
+        free(val);
+        free(table);
+    }
+    free(bl);
+    return nb;
+}

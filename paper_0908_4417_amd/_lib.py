@@ -114,6 +114,10 @@ _SIGS = {
     "fspb_surrogate_set_params": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float)]),
     "fspb_plan_set_surrogate": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fspb_surrogate_destroy": (None, [C.c_void_p]),
+    "fspb_fluence_dose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_fluence_gradient": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                          C.c_void_p, C.c_void_p]),
     "fspb_status_string": (C.c_char_p, [C.c_int32]),
     "fspb_last_error": (C.c_char_p, []),
 }
@@ -313,3 +317,11 @@ def fspb_plan_set_surrogate(plan, sur):
 
 def fspb_surrogate_destroy(sur):
     lib().fspb_surrogate_destroy(sur)
+
+
+def fspb_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose, stream):
+    return _check(lib().fspb_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose, stream))
+
+
+def fspb_fluence_gradient(indptr, indices, values, n_rows, r, g, stream):
+    return _check(lib().fspb_fluence_gradient(indptr, indices, values, n_rows, r, g, stream))

@@ -96,6 +96,12 @@ hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const Pl
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s);
 size_t fill_shared_bytes(const PlanDev &h);
 
+/* Eq. 1 and its adjoint on a CSR. */
+hipError_t launch_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                               int n_voxels, const float *w, float *dose, hipStream_t s);
+hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                                   const float *r, float *g, hipStream_t s);
+
 /* Batched launches over n_plans plans (persistent grids). */
 hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,
                              int grid, hipStream_t s);   // stage 0 prep, 1 raytrace, 2 count, 3 rowsum

@@ -1274,3 +1274,34 @@ fspb_status fspb_plan_set_surrogate(fspb_plan *p, const fspb_surrogate *s)
 void fspb_surrogate_destroy(fspb_surrogate *s) { delete s; }
 
 }  // extern "C"
+
+/* ======================================================================
+ * Eq. 1: dose of a fluence, and its adjoint
+ * ====================================================================== */
+
+extern "C" {
+
+fspb_status fspb_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
+                              int32_t n_voxels, const float *w, float *dose, void *stream)
+{
+    g_last_error.clear();
+    if (!indptr || !w || !dose || n_rows < 0 || n_voxels < 1) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    if (n_rows > 0 && (!indices || !values)) return fail(FSPB_ERR_INVALID, "indices or values is NULL");
+    FSPB_HIP(fspb::launch_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose,
+                                       static_cast<hipStream_t>(stream)),
+             "launch fluence dose");
+    return FSPB_OK;
+}
+
+fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
+                                  const float *r, float *g, void *stream)
+{
+    g_last_error.clear();
+    if (!indptr || !r || !g || n_rows < 0) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    if (n_rows > 0 && (!indices || !values)) return fail(FSPB_ERR_INVALID, "indices or values is NULL");
+    FSPB_HIP(fspb::launch_fluence_gradient(indptr, indices, values, n_rows, r, g, static_cast<hipStream_t>(stream)),
+             "launch fluence gradient");
+    return FSPB_OK;
+}
+
+}  // extern "C"

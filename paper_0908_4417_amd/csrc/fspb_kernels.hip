@@ -679,6 +679,42 @@ __global__ __launch_bounds__(W * kWave) void kp_fill(const PlanDev *const *__res
     }
 }
 
+/* ------------------------------------------------------------ Eq. 1 */
+
+__global__ __launch_bounds__(kBlock) void k_zero(float *__restrict__ x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = 0.0f;
+}
+
+/* dose[i] += w_j D_ij over row j; one wave per row. */
+__global__ __launch_bounds__(kBlock) void k_fluence_dose(const int64_t *__restrict__ indptr,
+                                                         const int32_t *__restrict__ indices,
+                                                         const float *__restrict__ values, int n_rows,
+                                                         const float *__restrict__ w, float *__restrict__ dose)
+{
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j >= n_rows) return;
+    const float wj = w[j];
+    if (wj == 0.0f) return;
+    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave)
+        atomicAdd(dose + indices[e], wj * values[e]);
+}
+
+/* g_j = sum_i D_ij r_i; one wave per row, lane-strided partial sums then a fixed butterfly. */
+__global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__restrict__ indptr,
+                                                             const int32_t *__restrict__ indices,
+                                                             const float *__restrict__ values, int n_rows,
+                                                             const float *__restrict__ r, float *__restrict__ g)
+{
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j >= n_rows) return;
+    float s = 0.0f;
+    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave) s = fmaf(values[e], r[indices[e]], s);
+    s = wave_sum(s);
+    if (lane_id() == 0) g[j] = s;
+}
+
 __global__ void k_reset(int *__restrict__ counters, int n)
 {
     if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
@@ -779,6 +815,26 @@ hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const Ou
     case 3: return launch_kp_fill_k<3>(W, plans, outs, items, n_items, counter, grid, lds, s);
     default: return launch_kp_fill_k<4>(W, plans, outs, items, n_items, counter, grid, lds, s);
     }
+}
+
+hipError_t launch_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                               int n_voxels, const float *w, float *dose, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n_voxels, kBlock)), dim3(kBlock), 0, s, dose, (int64_t)n_voxels);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_rows == 0) return e;
+    hipLaunchKernelGGL(k_fluence_dose, dim3(blocks_for(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
+                       values, n_rows, w, dose);
+    return hipGetLastError();
+}
+
+hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                                   const float *r, float *g, hipStream_t s)
+{
+    if (n_rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fluence_gradient, dim3(blocks_for(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr,
+                       indices, values, n_rows, r, g);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)

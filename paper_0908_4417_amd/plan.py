@@ -21,6 +21,27 @@ class CSR:
     def nnz(self):
         return int(self.indices.numel())
 
+    def _s(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.values.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def dose(self, w, stream=None):
+        """Eq. 1: dose of the beamlet weights w (device float32, one per row)."""
+        import torch
+        d = torch.empty(self.n_voxels, dtype=torch.float32, device=self.values.device)
+        L.fspb_fluence_dose(self.indptr.data_ptr(), self.indices.data_ptr(), self.values.data_ptr(),
+                            self.indptr.numel() - 1, self.n_voxels, w.data_ptr(), d.data_ptr(), self._s(stream))
+        return d
+
+    def gradient(self, r, stream=None):
+        """g_j = sum_i D_ij r_i for a voxel vector r (device float32)."""
+        import torch
+        g = torch.empty(self.indptr.numel() - 1, dtype=torch.float32, device=self.values.device)
+        L.fspb_fluence_gradient(self.indptr.data_ptr(), self.indices.data_ptr(), self.values.data_ptr(),
+                                self.indptr.numel() - 1, r.data_ptr(), g.data_ptr(), self._s(stream))
+        return g
+
 
 def _structs(problem, density_ptr):
     g = problem.grid
