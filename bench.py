@@ -46,9 +46,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--surrogate-epochs", type=int, default=300,
+    ap.add_argument("--no-eq1", action="store_true", help="skip the Eq. 1 (dose, gradient, transpose) timings")
+    ap.add_argument("--surrogate-epochs", type=int, default=None,
                     help="training epochs of the kernel surrogate compared with the analytic "
-                         "fill on the pelvis workload (0 skips the comparison)")
+                         "fill on the pelvis workload (0 skips it; default: 800 beside the default workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (reference "
                          "dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -111,9 +112,11 @@ def surrogate_comparison(epochs):
     """Train the kernel surrogate on the GPU and compare its fused fill with the analytic fill.
 
     Workload: the 256 x 256 x 100 pelvis (9 beams, 0.25 cm beamlets).  The
-    surrogate is trained on 1e7 seeded samples of the analytic kernel; both
-    fills are timed with HIP events, and the surrogate's summed dose (uniform
-    fluence) is compared with the analytic fill's.  The FP64 judgement of both
+    surrogate is trained on 1e7 seeded samples of the analytic kernel (drawn
+    uniformly in the square-root feature coordinates, beamlet side
+    log-uniform, 10 % at zero depth); both fills are timed with HIP events,
+    and the surrogate's dose of a uniform fluence (Eq. 1) is compared with the
+    analytic fill's.  The FP64 judgement of both
     is in tests/test_gpu_surrogate.py and tests/test_gpu_parity.py.
     """
     import torch
@@ -122,13 +125,13 @@ def surrogate_comparison(epochs):
     from paper_0908_4417_amd import Plan, Surrogate
     prob = fi.make_config(4)
     dev = "cuda:0"
-    n_samples = 10_000_000
+    n_samples = fi.SURROGATE_SAMPLES
     sur = Surrogate(prob.kernel, fi.surrogate_init(5), max_batch=16384)
-    raw = fi.surrogate_samples(n_samples, seed=5, core=0.5, log_a=True).astype(np.float32)
+    raw = fi.surrogate_samples(n_samples, seed=5, **fi.SURROGATE_RECIPE).astype(np.float32)
     f, t = sur.targets(torch.from_numpy(raw).to(dev))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = sur.train(f, t, epochs=epochs, batch=16384, lr_max=3e-3, lr_min=1e-6, seed=5)
+    losses = sur.train(f, t, epochs=epochs, seed=5, **fi.SURROGATE_TRAINING)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del f, t
@@ -140,9 +143,8 @@ def surrogate_comparison(epochs):
         for _ in range(4):
             csr = plan.compute()
             times.append(m.fspb_plan_get_timing(plan.handle).fill_ms)
+        dose = csr.dose(torch.ones(plan.n_beamlets, dtype=torch.float32, device=dev)).double()
         torch.cuda.synchronize()
-        dose = torch.zeros(plan.n_voxels, dtype=torch.float64, device=dev)
-        dose.index_add_(0, csr.indices.long(), csr.values.double())
         return min(times[1:]), dose, csr.values.double().clone()
 
     ta, Da, va = run()
@@ -156,6 +158,47 @@ def surrogate_comparison(epochs):
             "max_dose_err_vs_analytic": round((Ds - Da).abs().max().item() / dmax, 6),
             "rms_dose_err_vs_analytic": round(((Ds - Da)[Da > 0] ** 2).mean().sqrt().item() / dmax, 6),
             "max_coeff_err_vs_analytic": round((vs - va).abs().max().item() / va.max().item(), 6)}
+
+
+def eq1_timings(indptr, indices, values, n_voxels, n_beamlets, reps=5):
+    """Device times (HIP events, launch stream) of Eq. 1 on the plan's D_ij.
+
+    fluence_dose: dose = D w on the beamlet-row CSR (atomics); gradient:
+    g = D^T r; transpose: the voxel-row CSR (stable radix sort); voxel_dose:
+    D w on the voxel rows (no atomics).  Bytes per call: 8 per nonzero plus
+    the vectors.
+    """
+    import torch
+    from paper_0908_4417_amd import CSR
+    dev = indices.device
+    csr = CSR(indptr, indices, values, n_voxels)
+    w = torch.rand(n_beamlets, device=dev)
+    r = torch.rand(n_voxels, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"fluence_dose_ms": timed(lambda: csr.dose(w)), "gradient_ms": timed(lambda: csr.gradient(r))}
+    t0 = time.perf_counter()
+    t = csr.transpose()
+    torch.cuda.synchronize()
+    out["transpose_ms_wall"] = 1e3 * (time.perf_counter() - t0)
+    out["voxel_dose_ms"] = timed(lambda: t.dose(w))
+    d1, d2 = csr.dose(w).double(), t.dose(w).double()
+    out["voxel_vs_atomic_max_rel"] = (d1 - d2).abs().max().item() / d1.abs().max().item()
+    nnz = int(indices.numel())
+    for k in ("fluence_dose", "gradient", "voxel_dose"):
+        out[k + "_GBps"] = round(8.0 * nnz / (out[k + "_ms"] * 1e-3) / 1e9, 1)
+    del t
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
 
 def bench_batch(args):
@@ -294,6 +337,10 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
         "device_ms_per_plan": round(sum(kt.values()), 4),
     }
+    if not args.no_eq1:
+        out["eq1"] = eq1_timings(indptr, indices, values, int(np.prod(prob.grid.shape_xyz)), desc.n_beamlets)
+    if args.surrogate_epochs is None:                # by default only beside the headline workload
+        args.surrogate_epochs = fi.SURROGATE_EPOCHS if args.workload == 1 else 0
     if args.surrogate_epochs > 0:
         del indices, values, ws
         out["surrogate"] = surrogate_comparison(args.surrogate_epochs)

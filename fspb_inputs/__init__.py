@@ -341,6 +341,31 @@ def batched_configs(n_plans: int = 32, base_seed: int = 4000, scale: float = 1.0
     return plans
 
 
+def random_csr(seed: int, n_rows: int, n_cols: int, mean_row: float, empty_frac: float = 0.1):
+    """A seeded sparse matrix in CSR form with ragged rows (input for transpose tests).
+
+    Row lengths are Poisson(mean_row) (a fraction ``empty_frac`` of rows
+    empty), capped at n_cols; each row's columns are distinct and ascending,
+    drawn in a window around a random centre (like a beamlet's VOI) so that
+    columns collide across rows.  Values are uniform in (0, 1].
+    Returns (indptr int64, indices int32, values float32).
+    """
+    rng = np.random.default_rng(seed)
+    lens = np.minimum(rng.poisson(mean_row, n_rows), n_cols)
+    lens[rng.uniform(size=n_rows) < empty_frac] = 0
+    indptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    indices = np.empty(int(indptr[-1]), dtype=np.int32)
+    for j in range(n_rows):
+        k = int(lens[j])
+        if k == 0:
+            continue
+        width = min(n_cols, max(k, int(4 * k)))
+        lo = int(rng.integers(0, n_cols - width + 1))
+        indices[indptr[j]:indptr[j + 1]] = np.sort(rng.choice(width, size=k, replace=False)) + lo
+    values = (1.0 - rng.uniform(size=int(indptr[-1]))).astype(np.float32)
+    return indptr, indices, values
+
+
 def surrogate_samples(n: int, seed: int, d_max: float = 30.0, uv_max: float = 3.0,
                       a_range=(0.25, 1.0), core: float = 0.0, core_uv: float = 1.0, core_d: float = 5.0,
                       log_a: bool = False, sqrt_uniform: bool = False, zero_depth: float = 0.0):
@@ -384,6 +409,16 @@ def surrogate_samples(n: int, seed: int, d_max: float = 30.0, uv_max: float = 3.
     if nc or nz0:
         rng.shuffle(out, axis=0)
     return out
+
+
+# The training set and schedule used for the pelvis surrogate: 1e7 points drawn
+# uniformly in the square-root feature coordinates, beamlet side log-uniform,
+# 10 % of the points at zero depth; 800 epochs of Adam, batch 16384, cosine
+# learning rate 3e-3 -> 1e-6.
+SURROGATE_SAMPLES = 10_000_000
+SURROGATE_RECIPE = {"sqrt_uniform": True, "log_a": True, "zero_depth": 0.1}
+SURROGATE_TRAINING = {"batch": 16384, "lr_max": 3e-3, "lr_min": 1e-6}
+SURROGATE_EPOCHS = 800
 
 
 def surrogate_init(seed: int, hidden: int = 64, n_in: int = 4):

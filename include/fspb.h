@@ -346,8 +346,9 @@ fspb_status fspb_plan_set_surrogate(fspb_plan *plan, const fspb_surrogate *sur);
 void fspb_surrogate_destroy(fspb_surrogate *sur);
 
 /* ------------------------------------------------------------------------
- * Dose superposition (Eq. 1: D(x) = sum_j w_j D_j(x)) and its adjoint on a
- * D_ij CSR produced above (rows = beamlets, columns = voxels).
+ * Dose superposition (Eq. 1: D(x) = sum_j w_j D_j(x)) and its adjoint, on
+ * the beamlet-row CSR produced above (rows = beamlets, columns = voxels) and
+ * on its voxel-row transpose (rows = voxels, columns = beamlets).
  * ------------------------------------------------------------------------ */
 
 /*
@@ -355,18 +356,49 @@ void fspb_surrogate_destroy(fspb_surrogate *sur);
  * and dose (n_voxels) are DEVICE pointers; dose is overwritten.  Entries are
  * added with FP32 atomics, so the rounding of each voxel's sum depends on
  * the order in which rows land (the value itself is the same to FP32
- * precision).
+ * precision; fspb_voxel_dose is the bit-reproducible form).  Entries whose
+ * column lies outside [0, n_voxels) are skipped.
  */
 fspb_status fspb_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
                               int32_t n_voxels, const float *w, float *dose, void *stream);
 
 /*
  * g[j] = sum_i D_ij r[i] (the gradient of sum_i r_i D_i with respect to the
- * beamlet weights).  DEVICE pointers; g has n_rows entries and is overwritten.
- * Each row is summed by one wave in a fixed order: deterministic.
+ * beamlet weights).  DEVICE pointers; r has n_voxels entries, g has n_rows
+ * and is overwritten.  Each row is summed by one wave in a fixed order:
+ * deterministic.  Entries whose column lies outside [0, n_voxels) are skipped.
  */
 fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values,
-                                  int32_t n_rows, const float *r, float *g, void *stream);
+                                  int32_t n_rows, int32_t n_voxels, const float *r, float *g, void *stream);
+
+/*
+ * Voxel-row form of D: the transpose of a beamlet-row CSR (n_rows beamlets,
+ * nnz entries, columns in [0, n_voxels)) by a stable radix sort on the voxel
+ * index.  Each voxel row lists its beamlets in ascending order, so the
+ * result is canonical and bit-reproducible.
+ *   indptr (n_rows + 1, int64), indices (nnz), values (nnz): DEVICE, input;
+ *   t_indptr (n_voxels + 1, int64), t_indices (nnz, beamlet ids),
+ *   t_values (nnz): DEVICE, written.
+ * workspace: DEVICE, 256-byte aligned, caller-owned, about 24 bytes per
+ * entry; NULL = size query (returns FSPB_ERR_CAPACITY and sets
+ * *workspace_needed).  nnz must be below 2^32.  Synchronises `stream` once
+ * (after the voxel-row pointers are known); a column index outside
+ * [0, n_voxels) returns FSPB_ERR_INVALID with only t_indptr written.
+ */
+fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
+                               int32_t n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices,
+                               float *t_values, void *workspace, size_t workspace_bytes, size_t *workspace_needed,
+                               void *stream);
+
+/*
+ * dose[i] = sum_j D_ij w[j] over the voxel-row CSR of fspb_csr_transpose:
+ * each voxel row is summed by 16 lanes in a fixed order (bit-reproducible, no
+ * atomics).  DEVICE pointers; w has n_beamlets entries, dose n_voxels and is
+ * overwritten.  Entries whose beamlet lies outside [0, n_beamlets) are
+ * skipped.
+ */
+fspb_status fspb_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values,
+                            int32_t n_voxels, int32_t n_beamlets, const float *w, float *dose, void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *fspb_status_string(fspb_status s);

@@ -287,6 +287,23 @@ def siddon(problem_or_plan, S, e, tA, tB):
     return vox[:n], ln[:n]
 
 
+def csr_transpose(indptr, indices, values, n_cols):
+    """Voxel-row form of a beamlet-row CSR: the definition of the transpose.
+
+    Every entry (j, i, v) becomes (i, j, v); entries are ordered by voxel i,
+    then beamlet j (a stable sort by column of the row-major entry list).
+    Returns (t_indptr int64 [n_cols + 1], t_indices int32, t_values).
+    """
+    indptr = np.asarray(indptr, dtype=np.int64)
+    indices = np.asarray(indices, dtype=np.int64)
+    values = np.asarray(values)
+    rows = np.repeat(np.arange(len(indptr) - 1, dtype=np.int64), np.diff(indptr))
+    order = np.argsort(indices, kind="stable")
+    counts = np.bincount(indices, minlength=n_cols)
+    t_indptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return t_indptr, rows[order].astype(np.int32), values[order]
+
+
 def set_threads(n):
     lib().ofs_set_threads(int(n))
 

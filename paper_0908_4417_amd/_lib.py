@@ -116,8 +116,13 @@ _SIGS = {
     "fspb_surrogate_destroy": (None, [C.c_void_p]),
     "fspb_fluence_dose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
-    "fspb_fluence_gradient": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
-                                          C.c_void_p, C.c_void_p]),
+    "fspb_fluence_gradient": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fspb_csr_transpose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                       C.POINTER(C.c_size_t), C.c_void_p]),
+    "fspb_voxel_dose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
     "fspb_status_string": (C.c_char_p, [C.c_int32]),
     "fspb_last_error": (C.c_char_p, []),
 }
@@ -323,5 +328,20 @@ def fspb_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose, stream
     return _check(lib().fspb_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose, stream))
 
 
-def fspb_fluence_gradient(indptr, indices, values, n_rows, r, g, stream):
-    return _check(lib().fspb_fluence_gradient(indptr, indices, values, n_rows, r, g, stream))
+def fspb_fluence_gradient(indptr, indices, values, n_rows, n_voxels, r, g, stream):
+    return _check(lib().fspb_fluence_gradient(indptr, indices, values, n_rows, n_voxels, r, g, stream))
+
+
+def fspb_csr_transpose(indptr, indices, values, n_rows, n_voxels, nnz, t_indptr, t_indices, t_values,
+                       workspace, workspace_bytes, stream):
+    """Returns (status, bytes needed); a NULL workspace is the size query."""
+    need = C.c_size_t(0)
+    st = lib().fspb_csr_transpose(indptr, indices, values, n_rows, n_voxels, nnz, t_indptr, t_indices, t_values,
+                                  workspace, workspace_bytes, C.byref(need), stream)
+    if st == FSPB_ERR_CAPACITY and not workspace:
+        return st, need.value
+    return _check(st), need.value
+
+
+def fspb_voxel_dose(t_indptr, t_indices, t_values, n_voxels, n_beamlets, w, dose, stream):
+    return _check(lib().fspb_voxel_dose(t_indptr, t_indices, t_values, n_voxels, n_beamlets, w, dose, stream))

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfspb.so")
-SOURCES = ["fspb_kernels.hip", "fspb_mlp.hip", "fspb_host.cpp"]
+SOURCES = ["fspb_kernels.hip", "fspb_mlp.hip", "fspb_sparse.hip", "fspb_host.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of every code object.

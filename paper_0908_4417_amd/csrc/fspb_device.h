@@ -13,8 +13,13 @@ constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kRowsPerTile = 64;     // grid rows (iy, iz) per count/fill tile: one per lane
 constexpr int kMaxTerms = 4;
 // erfc on [0, kErfcMax] by piecewise quadratics on kErfcIntervals equal intervals
+// (training targets of the kernel surrogate)
 constexpr int kErfcIntervals = 512;
 constexpr float kErfcMax = 4.0f;
+// erf on [-kErfMax, kErfMax] by piecewise quadratics on kErfIntervals equal
+// intervals (the fill); both tables have 128 intervals per unit of argument
+constexpr int kErfIntervals = 1024;
+constexpr float kErfMax = 4.0f;
 
 /* Per-beamlet record, built in FP64 on the host (Fig. 1 geometry). */
 struct alignas(16) BeamletRec {
@@ -58,7 +63,7 @@ struct alignas(16) PlanDev {
     float c2[kMaxTerms];
     float pdd_inv_step, pdd_max;   // 1/step; n_pdd - 1
     const float *pdd;
-    const float4 *erfc_tab;      // [kErfcIntervals] (c0, c1, c2, 0) on each interval
+    const float4 *erf_tab;       // [kErfIntervals] (c0, c1, c2, 0) on each interval
     // beamlets and tables
     int32_t n_beamlets, max_table;
     int32_t ray_iters;           // bound on the per-interval Siddon loop
@@ -97,10 +102,20 @@ hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &
 size_t fill_shared_bytes(const PlanDev &h);
 
 /* Eq. 1 and its adjoint on a CSR. */
+/* Eq. 1 on a beamlet-row CSR and on its voxel-row transpose (fspb_sparse.hip). */
 hipError_t launch_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
                                int n_voxels, const float *w, float *dose, hipStream_t s);
 hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
-                                   const float *r, float *g, hipStream_t s);
+                                   int n_voxels, const float *r, float *g, hipStream_t s);
+hipError_t launch_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values, int n_voxels,
+                             int n_w, const float *w, float *dose, hipStream_t s);
+size_t transpose_workspace(int64_t nnz, int n_voxels);
+int transpose_passes(int n_voxels);
+/* Synchronises s; *bad_host = 1 when a column index lies outside [0, n_voxels)
+ * (then only t_indptr is written). */
+hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                            int n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices, float *t_values,
+                            void *workspace, int32_t *bad_host, hipStream_t s);
 
 /* Batched launches over n_plans plans (persistent grids). */
 hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,

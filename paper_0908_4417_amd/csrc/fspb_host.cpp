@@ -73,7 +73,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 /* Workspace carve: offsets of every device array. */
 struct Layout {
-    size_t plan, out, scal, rec, tile_beamlet, tile_count, row_nnz, tables, pdd, erfc, bits, ext, total;
+    size_t plan, out, scal, rec, tile_beamlet, tile_count, row_nnz, tables, pdd, erf, bits, ext, total;
 };
 
 }  // namespace
@@ -238,7 +238,7 @@ void voi_rows(const fspb_grid *g, V3 S, V3 e, V3 eu, V3 ev, double cu_sad, doubl
 }
 
 /*
- * Piecewise-quadratic erfc used by the fill kernel: on interval k of
+ * Piecewise-quadratic erfc used for the surrogate's training targets: on interval k of
  * [0, kErfcMax] (width w) the quadratic through erfc at the interval's two
  * ends and midpoint, in the local coordinate f in [0, 1]:
  *   erfc(z_k + f w) ~ c0 + f (c1 + f c2).
@@ -252,6 +252,23 @@ void erfc_table(std::vector<float4> &t)
     t.resize(n);
     for (int k = 0; k < n; ++k) {
         const double y0 = std::erfc(k * w), ym = std::erfc((k + 0.5) * w), y1 = std::erfc((k + 1) * w);
+        t[k] = make_float4((float)y0, (float)(4.0 * ym - 3.0 * y0 - y1), (float)(2.0 * (y1 + y0 - 2.0 * ym)), 0.0f);
+    }
+}
+
+/*
+ * Piecewise-quadratic erf used by the fill kernel, the same construction on
+ * [-kErfMax, kErfMax] (kErfIntervals intervals of width w = 1/128): on each
+ * interval the quadratic through erf at both ends and the midpoint.
+ */
+void erf_table(std::vector<float4> &t)
+{
+    const int n = fspb::kErfIntervals;
+    const double w = 2.0 * (double)fspb::kErfMax / n;
+    t.resize(n);
+    for (int k = 0; k < n; ++k) {
+        const double z = -(double)fspb::kErfMax + k * w;
+        const double y0 = std::erf(z), ym = std::erf(z + 0.5 * w), y1 = std::erf(z + w);
         t[k] = make_float4((float)y0, (float)(4.0 * ym - 3.0 * y0 - y1), (float)(2.0 * (y1 + y0 - 2.0 * ym)), 0.0f);
     }
 }
@@ -447,7 +464,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     L.row_nnz = take(sizeof(int64_t) * (size_t)nbl);
     L.tables = take(sizeof(float) * (size_t)std::max<int64_t>(table_off, 1));
     L.pdd = take(sizeof(float) * (size_t)K->n_pdd);
-    L.erfc = take(sizeof(float4) * fspb::kErfcIntervals);
+    L.erf = take(sizeof(float4) * fspb::kErfIntervals);
     L.bits = take(sizeof(uint32_t) * (size_t)grow * h.wpr);
     L.ext = take(sizeof(int2) * (size_t)grow);
     L.total = off;
@@ -481,7 +498,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     h.row_nnz = reinterpret_cast<int64_t *>(ws + L.row_nnz);
     h.tables = reinterpret_cast<float *>(ws + L.tables);
     h.pdd = reinterpret_cast<float *>(ws + L.pdd);
-    h.erfc_tab = reinterpret_cast<float4 *>(ws + L.erfc);
+    h.erf_tab = reinterpret_cast<float4 *>(ws + L.erf);
     h.bits = reinterpret_cast<uint32_t *>(ws + L.bits);
     h.ext = reinterpret_cast<int2 *>(ws + L.ext);
     h.nnz = p->d_nnz;
@@ -498,9 +515,9 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
              "upload depth dose");
     {
         std::vector<float4> et;
-        erfc_table(et);
-        FSPB_HIP(hipMemcpy((void *)h.erfc_tab, et.data(), sizeof(float4) * et.size(), hipMemcpyHostToDevice),
-                 "upload erfc table");
+        erf_table(et);
+        FSPB_HIP(hipMemcpy((void *)h.erf_tab, et.data(), sizeof(float4) * et.size(), hipMemcpyHostToDevice),
+                 "upload erf table");
     }
     FSPB_HIP(hipMemset(p->d_overflow, 0, sizeof(int32_t)), "clear overflow flag");
     guard.p = nullptr;
@@ -1294,13 +1311,51 @@ fspb_status fspb_fluence_dose(const int64_t *indptr, const int32_t *indices, con
 }
 
 fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
-                                  const float *r, float *g, void *stream)
+                                  int32_t n_voxels, const float *r, float *g, void *stream)
 {
     g_last_error.clear();
-    if (!indptr || !r || !g || n_rows < 0) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    if (!indptr || !r || !g || n_rows < 0 || n_voxels < 1) return fail(FSPB_ERR_INVALID, "invalid arguments");
     if (n_rows > 0 && (!indices || !values)) return fail(FSPB_ERR_INVALID, "indices or values is NULL");
-    FSPB_HIP(fspb::launch_fluence_gradient(indptr, indices, values, n_rows, r, g, static_cast<hipStream_t>(stream)),
+    FSPB_HIP(fspb::launch_fluence_gradient(indptr, indices, values, n_rows, n_voxels, r, g,
+                                           static_cast<hipStream_t>(stream)),
              "launch fluence gradient");
+    return FSPB_OK;
+}
+
+fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
+                               int32_t n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices,
+                               float *t_values, void *workspace, size_t workspace_bytes, size_t *workspace_needed,
+                               void *stream)
+{
+    g_last_error.clear();
+    if (n_rows < 0 || n_voxels < 1 || nnz < 0) return fail(FSPB_ERR_INVALID, "n_rows, n_voxels or nnz out of range");
+    if (nnz >= ((int64_t)1 << 32) - 1) return fail(FSPB_ERR_INVALID, "nnz must be below 2^32");
+    const size_t need = fspb::transpose_workspace(nnz, n_voxels);
+    if (workspace_needed) *workspace_needed = need;
+    if (!workspace) return fail(FSPB_ERR_CAPACITY, "workspace query: %zu bytes needed", need);
+    if (workspace_bytes < need)
+        return fail(FSPB_ERR_CAPACITY, "workspace of %zu bytes; %zu needed", workspace_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(FSPB_ERR_INVALID, "workspace is not 256-byte aligned");
+    if (!indptr || !t_indptr) return fail(FSPB_ERR_INVALID, "indptr or t_indptr is NULL");
+    if (nnz > 0 && (!indices || !values || !t_indices || !t_values))
+        return fail(FSPB_ERR_INVALID, "entry arrays are NULL");
+    int32_t bad = 0;
+    FSPB_HIP(fspb::launch_transpose(indptr, indices, values, n_rows, n_voxels, nnz, t_indptr, t_indices, t_values,
+                                    workspace, &bad, static_cast<hipStream_t>(stream)),
+             "launch transpose");
+    if (bad) return fail(FSPB_ERR_INVALID, "a column index lies outside [0, n_voxels)");
+    return FSPB_OK;
+}
+
+fspb_status fspb_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values,
+                            int32_t n_voxels, int32_t n_beamlets, const float *w, float *dose, void *stream)
+{
+    g_last_error.clear();
+    if (!t_indptr || !w || !dose || n_voxels < 1 || n_beamlets < 0) return fail(FSPB_ERR_INVALID, "invalid arguments");
+    if (!t_indices || !t_values) return fail(FSPB_ERR_INVALID, "t_indices or t_values is NULL");
+    FSPB_HIP(fspb::launch_voxel_dose(t_indptr, t_indices, t_values, n_voxels, n_beamlets, w, dose,
+                                     static_cast<hipStream_t>(stream)),
+             "launch voxel dose");
     return FSPB_OK;
 }
 

@@ -353,6 +353,14 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__
 
 /* ---------------------------------------------------------------- fill */
 
+/* A wave-uniform 64-bit value moved to scalar registers (keeps address arithmetic scalar). */
+__device__ inline int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 /* Global-address-space views of pointers read from plan records (global_* instead of flat_*). */
 template <typename T>
 using gptr = __attribute__((address_space(1))) T *;
@@ -364,12 +372,14 @@ __device__ inline gptr<T> as_global(T *p)
 }
 
 /*
- * erfc(z / kScale) for a table coordinate x = z kScale >= 0: piecewise
- * quadratic from LDS, held at the last interval's end.
+ * erf(z) at the table coordinate x = (z + kErfMax) kErfScale: piecewise
+ * quadratic from LDS, held at the ends of [-kErfMax, kErfMax].
  */
-__device__ inline float erfc_lds(const float4 *__restrict__ tab, float x)
+constexpr float kErfScale = (float)kErfIntervals / (2.0f * kErfMax);
+
+__device__ inline float erf_lds(const float4 *__restrict__ tab, float x)
 {
-    const float xc = fminf(x, (float)kErfcIntervals - 1.0f / 1024.0f);
+    const float xc = __builtin_amdgcn_fmed3f(x, 0.0f, (float)kErfIntervals - 1.0f / 1024.0f);
     const int k = (int)xc;
     const float f = __builtin_amdgcn_fractf(xc);
     const float4 c = tab[k];
@@ -378,17 +388,12 @@ __device__ inline float erfc_lds(const float4 *__restrict__ tab, float x)
 
 /*
  * One bracket of Eq. 3, erf((h - x) is) + erf((h + x) is), with
- * is = 1/(sqrt2 sigma) and both arguments pre-multiplied by the table scale
- * (isk = is * kScale).  Written with erfc of non-negative arguments: inside
- * the beamlet 2 - erfc(alpha) - erfc(beta), outside erfc(alpha) - erfc(beta),
- * so tails keep their relative accuracy.
+ * is = 1/(sqrt2 sigma): isk = is kErfScale and hko = h isk + kErfMax kErfScale
+ * put both arguments in table coordinates.  The bracket is even in x.
  */
-__device__ inline float edge_pair(const float4 *__restrict__ tab, float ax, float h, float isk)
+__device__ inline float edge_pair(const float4 *__restrict__ tab, float x, float hko, float isk)
 {
-    const float hk = h * isk;
-    const float ea = erfc_lds(tab, fabsf(fmaf(-ax, isk, hk)));
-    const float eb = erfc_lds(tab, fmaf(ax, isk, hk));
-    return (ax <= h ? 2.0f - ea : ea) - eb;
+    return erf_lds(tab, fmaf(-x, isk, hko)) + erf_lds(tab, fmaf(x, isk, hko));
 }
 
 /* Per-beamlet constants of the fill, held in registers. */
@@ -396,24 +401,28 @@ template <int K>
 struct FillConst {
     float sad, tA, inv_step, tau_max, pdd_inv, pdd_max;
     int n_terms;
-    float w4[K], sig0[K], sig1[K], ha[K], hb[K];
+    float w4[K], ha[K], hb[K];
+    float sig0[K], sig1[K];      // sigma law divided by kIsScale: 1/sigma' = isk
 };
+
+// is kErfScale = kIsScale / sigma
+constexpr float kIsScale = 0.70710678118654752f * kErfScale;
+constexpr float kErfOff = kErfMax * kErfScale;
 
 template <int K, bool GUARD>
 __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restrict__ tab,
                                    const float2 *__restrict__ pdd, const float4 *__restrict__ etab,
                                    float s, float U, float V)
 {
-    constexpr float kIsScale = 0.70710678118654752f * (float)kErfcIntervals / kErfcMax;
     const float tp = s + c.tA;                      // t' = |SO'|
     const float g = c.sad * __builtin_amdgcn_rcpf(tp);   // SAD / t'
-    const float au = fabsf(U * g), av = fabsf(V * g);
+    const float u = U * g, v = V * g;
     // radiological depth at O': linear interpolation in the table (last entry has slope 0)
     const float tau = __builtin_amdgcn_fmed3f(s * c.inv_step, 0.0f, c.tau_max);
     const float2 q = tab[(int)tau];
     const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
     // depth dose, held at the last node
-    const float x = fminf(d * c.pdd_inv, c.pdd_max);
+    const float x = __builtin_amdgcn_fmed3f(d * c.pdd_inv, 0.0f, c.pdd_max);
     const float2 qp = pdd[(int)x];
     const float A = fmaf(__builtin_amdgcn_fractf(x), qp.y, qp.x) * g * g;
     // lateral profile, Eq. 3
@@ -421,9 +430,9 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         if (GUARD && i >= c.n_terms) break;
-        const float isk = kIsScale * __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
-        const float eu = edge_pair(etab, au, c.ha[i], isk);
-        const float ev = edge_pair(etab, av, c.hb[i], isk);
+        const float isk = __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
+        const float eu = edge_pair(etab, u, fmaf(c.ha[i], isk, kErfOff), isk);
+        const float ev = edge_pair(etab, v, fmaf(c.hb[i], isk, kErfOff), isk);
         L = fmaf(c.w4[i] * eu, ev, L);
     }
     return A * L;
@@ -444,7 +453,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const int n_tiles = R.n_tiles;
     if (n_tiles == 0) return;
     constexpr int kB = W * kWave;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = lane_id();
 
     // ---- constants into registers
     const int n_table = R.n_table, n_pdd = P.n_pdd, tile0 = R.tile0;
@@ -461,8 +470,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         c.w4[i] = P.w4[i];
-        c.sig0[i] = P.sig0[i];
-        c.sig1[i] = P.sig1[i];
+        c.sig0[i] = P.sig0[i] * (1.0f / kIsScale);
+        c.sig1[i] = P.sig1[i] * (1.0f / kIsScale);
         c.ha[i] = R.ha[i];
         c.hb[i] = R.hb[i];
     }
@@ -474,17 +483,17 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const gptr<int32_t> out_idx = as_global<int32_t>(O.indices);
     const gptr<float> out_val = as_global<float>(O.values);
     const int64_t capacity = O.capacity;
-    const int64_t row_base = O.indptr[j];
+    const int64_t row_base = uniform64(O.indptr[j]);
 
-    // ---- LDS: erfc table, depth table, depth dose, tile prefix
-    float4 *s_erfc = reinterpret_cast<float4 *>(smem);
-    float2 *s_tab = reinterpret_cast<float2 *>(s_erfc + kErfcIntervals);
+    // ---- LDS: erf table, depth table, depth dose, tile prefix
+    float4 *s_erf = reinterpret_cast<float4 *>(smem);
+    float2 *s_tab = reinterpret_cast<float2 *>(s_erf + kErfIntervals);
     float2 *s_pdd = s_tab + P.max_table;
     int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
     __shared__ int wsum[W];
     // surrogate: per-wave h1 tile after the tile prefix, and W2 fragments in registers
     uint16_t *s_h1 = reinterpret_cast<uint16_t *>(
-        smem + ((sizeof(float4) * kErfcIntervals + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
+        smem + ((sizeof(float4) * kErfIntervals + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
                  sizeof(int) * ((size_t)P.max_tiles + 1) + 15) & ~(size_t)15)) + wave * (64 * mlp::kH1Stride);
     mlp::W2Frags wf;
     if (SURR) mlp::load_w2_frags(P.mlp_w2, wf);
@@ -492,8 +501,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const bool mlp_ok = SURR && R.mlp_ok;
 
     {
-        const float4 *et = P.erfc_tab;
-        for (int i = tid; i < kErfcIntervals; i += kB) s_erfc[i] = et[i];
+        const float4 *et = P.erf_tab;
+        for (int i = tid; i < kErfIntervals; i += kB) s_erf[i] = et[i];
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
         for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
@@ -524,7 +533,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
 
     for (int tl = wave; tl < n_tiles; tl += W) {
         if (tile_count[tile0 + tl] == 0) continue;
-        const int64_t out0 = row_base + s_tpre[tl];
+        const int64_t out0 = row_base + __builtin_amdgcn_readfirstlane(s_tpre[tl]);
         // lane = grid row of this tile: its VOI interval and FP32 start values
         const int r = tl * kRowsPerTile + lane;
         int lo = 0, hi = -1, grow = 0;
@@ -546,7 +555,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         const int cnt = hi - lo + 1;
         const int incl = wave_incl_scan(cnt);
         const int excl = incl - cnt;
-        const int total = __shfl(incl, kWave - 1, kWave);
+        const int total = readlane(incl, kWave - 1);   // wave-uniform: the chunk loop stays scalar
         // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
         // rows are walked once, wave-uniformly, as the chunks advance
         int rcur = 0;
@@ -564,16 +573,21 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             const int ix = __shfl(lo, rr, kWave) + k;
             const int gr = __shfl(grow, rr, kWave);
             bool member = false;
-            if (p < total) member = (bits[(uint32_t)(gr * wpr) + ((uint32_t)ix >> 5)] >> (ix & 31)) & 1u;
+            if (p < total) {
+                const uint32_t wo = ((uint32_t)(gr * wpr) + ((uint32_t)ix >> 5)) << 2;   // byte offset
+                member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
+            }
             const uint64_t mask = __ballot(member);
             const uint32_t slot = (uint32_t)mbcnt64(mask);
             const float sl = __shfl(s_lo, rr, kWave);
             const float ul = __shfl(U_lo, rr, kWave);
             const float vl = __shfl(V_lo, rr, kWave);
-            // this chunk's entries go to [written, written + popcount); the base is wave-uniform
-            const gptr<int32_t> ip = out_idx + written;
-            const gptr<float> vp = out_val + written;
-            const bool room = written + kWave <= capacity;
+            // this chunk's entries go to [written, written + popcount); the bases are wave-uniform
+            const gptr<char> ip = (gptr<char>)(out_idx + written);
+            const gptr<char> vp = (gptr<char>)(out_val + written);
+            // slots below `avail` fit in the caller's arrays (scalar: no 64-bit compare per lane)
+            const int64_t left = capacity - written;
+            const uint32_t avail = left >= kWave ? (uint32_t)kWave : (left > 0 ? (uint32_t)left : 0u);
             float D = 0.0f;
             if (SURR) {
                 // the network runs on all 64 lanes (matrix cores need the whole wave)
@@ -590,16 +604,16 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                 if (in_box) mlp::features(d, au, av, a_f, x);
                 const float y = mlp::forward_wave(P.mlp_p, wf, x, s_h1);
                 if (in_box) D = y * g * g;
-                else if (member) D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erfc, sv, Uv, Vv);
+                else if (member) D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
             }
             if (member) {
                 const float kf = (float)k;
                 if (!SURR)
-                    D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erfc, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                    D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
                                              fmaf(kf, V1f, vl));
-                if (room || written + slot < capacity) {
-                    ip[slot] = gr * nx + ix;
-                    vp[slot] = D;
+                if (slot < avail) {
+                    *(gptr<int32_t>)(ip + (slot << 2)) = gr * nx + ix;
+                    *(gptr<float>)(vp + (slot << 2)) = D;
                 } else {
                     *O.overflow = 1;
                 }
@@ -679,42 +693,6 @@ __global__ __launch_bounds__(W * kWave) void kp_fill(const PlanDev *const *__res
     }
 }
 
-/* ------------------------------------------------------------ Eq. 1 */
-
-__global__ __launch_bounds__(kBlock) void k_zero(float *__restrict__ x, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] = 0.0f;
-}
-
-/* dose[i] += w_j D_ij over row j; one wave per row. */
-__global__ __launch_bounds__(kBlock) void k_fluence_dose(const int64_t *__restrict__ indptr,
-                                                         const int32_t *__restrict__ indices,
-                                                         const float *__restrict__ values, int n_rows,
-                                                         const float *__restrict__ w, float *__restrict__ dose)
-{
-    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (j >= n_rows) return;
-    const float wj = w[j];
-    if (wj == 0.0f) return;
-    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave)
-        atomicAdd(dose + indices[e], wj * values[e]);
-}
-
-/* g_j = sum_i D_ij r_i; one wave per row, lane-strided partial sums then a fixed butterfly. */
-__global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__restrict__ indptr,
-                                                             const int32_t *__restrict__ indices,
-                                                             const float *__restrict__ values, int n_rows,
-                                                             const float *__restrict__ r, float *__restrict__ g)
-{
-    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (j >= n_rows) return;
-    float s = 0.0f;
-    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave) s = fmaf(values[e], r[indices[e]], s);
-    s = wave_sum(s);
-    if (lane_id() == 0) g[j] = s;
-}
-
 __global__ void k_reset(int *__restrict__ counters, int n)
 {
     if ((int)threadIdx.x < n) counters[threadIdx.x] = 0;
@@ -762,7 +740,7 @@ hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const Pl
 
 size_t fill_shared_bytes(const PlanDev &h)
 {
-    size_t b = sizeof(float4) * kErfcIntervals + sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) +
+    size_t b = sizeof(float4) * kErfIntervals + sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) +
                sizeof(int) * ((size_t)h.max_tiles + 1);
     if (h.use_mlp) b = ((b + 15) & ~(size_t)15) + sizeof(uint16_t) * 64 * mlp::kH1Stride * kWavesPerBlock;
     return b;
@@ -815,26 +793,6 @@ hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const Ou
     case 3: return launch_kp_fill_k<3>(W, plans, outs, items, n_items, counter, grid, lds, s);
     default: return launch_kp_fill_k<4>(W, plans, outs, items, n_items, counter, grid, lds, s);
     }
-}
-
-hipError_t launch_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
-                               int n_voxels, const float *w, float *dose, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n_voxels, kBlock)), dim3(kBlock), 0, s, dose, (int64_t)n_voxels);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n_rows == 0) return e;
-    hipLaunchKernelGGL(k_fluence_dose, dim3(blocks_for(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
-                       values, n_rows, w, dose);
-    return hipGetLastError();
-}
-
-hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
-                                   const float *r, float *g, hipStream_t s)
-{
-    if (n_rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fluence_gradient, dim3(blocks_for(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr,
-                       indices, values, n_rows, r, g);
-    return hipGetLastError();
 }
 
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)

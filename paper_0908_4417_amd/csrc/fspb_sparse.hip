@@ -1,0 +1,500 @@
+/*
+ * gfx950 kernels for Eq. 1 on the dose-coefficient matrix D_ij.
+ *
+ *   beamlet-row CSR (what the fill writes: row j = beamlet, columns = voxels)
+ *     k_fluence_dose      dose_i += w_j D_ij with FP32 atomics   -- one wave per row
+ *     k_fluence_gradient  g_j = sum_i D_ij r_i, fixed order      -- one wave per row
+ *   voxel-row CSR (row i = voxel, columns = beamlets), built by
+ *     k_expand_rows, k_col_count + scan         row ids of the entries, voxel-row pointers
+ *     k_rs_hist, scan, k_rs_scatter             one pass of a stable LSD radix sort on the
+ *                                               voxel index, 8 bits per pass
+ *     k_voxel_dose        dose_i = sum_j D_ij w_j, fixed order  -- 16 lanes per voxel row
+ *
+ * The radix sort is stable and the input rows are in ascending beamlet order,
+ * so every voxel row lists its beamlets in ascending order: the transpose is
+ * canonical and bit-reproducible.
+ */
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fspb_device.h"
+
+namespace fspb {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;          // digits per pass; one thread per digit
+constexpr int kSortItems = 16;                   // items per thread per tile
+constexpr int kSortTile = kBlock * kSortItems;   // 4096 entries per sort tile
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kBlock * kScanItems;  // 4096 values per scan block
+constexpr int kScanTop = 1024;
+
+static_assert(kRadix == kBlock, "one thread per digit");
+
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ inline int mbcnt64(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ inline T wave_sum(T x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+/* Exclusive scan of one value per thread over the block; *total gets the sum. */
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, uint32_t *total)
+{
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (l >= d) x += y;
+    }
+    if (l == kWave - 1) s_w[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWavesPerBlock; ++k) {
+        const uint32_t t = s_w[k];
+        off += k < w ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+/* ------------------------------------------------------------ Eq. 1 */
+
+__global__ __launch_bounds__(kBlock) void k_zero(float *__restrict__ x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_u32(uint32_t *__restrict__ x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = 0u;
+}
+
+/* dose[i] += w_j D_ij over row j; one wave per row.  Columns outside
+ * [0, n_voxels) are skipped. */
+__global__ __launch_bounds__(kBlock) void k_fluence_dose(const int64_t *__restrict__ indptr,
+                                                         const int32_t *__restrict__ indices,
+                                                         const float *__restrict__ values, int n_rows,
+                                                         int n_voxels, const float *__restrict__ w,
+                                                         float *__restrict__ dose)
+{
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j >= n_rows) return;
+    const float wj = w[j];
+    if (wj == 0.0f) return;
+    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave) {
+        const uint32_t i = (uint32_t)indices[e];
+        if (i < (uint32_t)n_voxels) atomicAdd(dose + i, wj * values[e]);
+    }
+}
+
+/* g_j = sum_i D_ij r_i; one wave per row, lane-strided partial sums then a
+ * fixed butterfly.  Columns outside [0, n_voxels) are skipped. */
+__global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__restrict__ indptr,
+                                                             const int32_t *__restrict__ indices,
+                                                             const float *__restrict__ values, int n_rows,
+                                                             int n_voxels, const float *__restrict__ r,
+                                                             float *__restrict__ g)
+{
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j >= n_rows) return;
+    float s = 0.0f;
+    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave) {
+        const uint32_t i = (uint32_t)indices[e];
+        if (i < (uint32_t)n_voxels) s = fmaf(values[e], r[i], s);
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) g[j] = s;
+}
+
+/* dose_i = sum_j D_ij w_j over voxel row i: 16 lanes per row, lane-strided
+ * partial sums and a fixed 16-lane butterfly.  Beamlets outside [0, n_w) are
+ * skipped. */
+__global__ __launch_bounds__(kBlock) void k_voxel_dose(const int64_t *__restrict__ t_indptr,
+                                                       const int32_t *__restrict__ t_indices,
+                                                       const float *__restrict__ t_values, int n_voxels, int n_w,
+                                                       const float *__restrict__ w, float *__restrict__ dose)
+{
+    const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 4;
+    const int l = threadIdx.x & 15;
+    float s = 0.0f;
+    if (i < n_voxels) {
+        const int64_t e1 = t_indptr[i + 1];
+        for (int64_t e = t_indptr[i] + l; e < e1; e += 16) {
+            const uint32_t j = (uint32_t)t_indices[e];
+            if (j < (uint32_t)n_w) s = fmaf(t_values[e], w[j], s);
+        }
+    }
+#pragma unroll
+    for (int d = 8; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+    if (l == 0 && i < n_voxels) dose[i] = s;
+}
+
+/* ------------------------------------------------------------ transpose */
+
+/* rows[e] = j for every entry e of row j (clamped to [0, nnz)); one wave per row. */
+__global__ __launch_bounds__(kBlock) void k_expand_rows(const int64_t *__restrict__ indptr, int n_rows, int64_t nnz,
+                                                        int32_t *__restrict__ rows)
+{
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j >= n_rows) return;
+    const int64_t e0 = indptr[j] > 0 ? indptr[j] : 0, e1 = indptr[j + 1] < nnz ? indptr[j + 1] : nnz;
+    for (int64_t e = e0 + lane_id(); e < e1; e += kWave) rows[e] = j;
+}
+
+/* Entries per voxel; an index outside [0, n_voxels) raises *bad. */
+__global__ __launch_bounds__(kBlock) void k_col_count(const int32_t *__restrict__ indices, int64_t nnz,
+                                                      int n_voxels, uint32_t *__restrict__ counts,
+                                                      int32_t *__restrict__ bad)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += stride) {
+        const uint32_t i = (uint32_t)indices[e];
+        if (i < (uint32_t)n_voxels) atomicAdd(counts + i, 1u);
+        else *bad = 1;
+    }
+}
+
+/* Scan, phase 1: sum of each kScanChunk-value chunk. */
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                        uint32_t *__restrict__ partial)
+{
+    __shared__ uint32_t s_w[kWavesPerBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v += base + k < n ? in[base + k] : 0u;
+    v = wave_sum(v);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) t += s_w[k];
+        partial[blockIdx.x] = t;
+    }
+}
+
+/* Scan, phase 2: exclusive scan of the chunk sums in place (one workgroup);
+ * partial[nb] = total, also stored to *total64 when given. */
+__global__ __launch_bounds__(kScanTop) void k_scan_top(uint32_t *__restrict__ partial, int nb,
+                                                       int64_t *__restrict__ total64)
+{
+    __shared__ uint32_t s_w[kScanTop / kWave];
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kScanTop) {
+        const int i = b0 + threadIdx.x;
+        const uint32_t v = i < nb ? partial[i] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, kWave);
+            if (l >= d) x += y;
+        }
+        if (l == kWave - 1) s_w[w] = x;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (int k = 0; k < kScanTop / kWave; ++k) {
+            off += k < w ? s_w[k] : 0u;
+            tot += s_w[k];
+        }
+        if (i < nb) partial[i] = carry + off + x - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[nb] = carry;
+        if (total64) *total64 = (int64_t)carry;
+    }
+}
+
+/* Scan, phase 3: exclusive scan within each chunk plus its chunk offset. */
+template <typename OUT>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *__restrict__ in, int64_t n,
+                                                      const uint32_t *__restrict__ partial, OUT *__restrict__ out)
+{
+    __shared__ uint32_t s_w[kWavesPerBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t total;
+    uint32_t run = partial[blockIdx.x] + block_excl_scan(sum, s_w, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = (OUT)run;
+        run += v[k];
+    }
+}
+
+/* Radix pass, phase 1: digit histogram of each kSortTile-entry tile, stored
+ * digit-major (hist[d * n_tiles + tile]) so that one exclusive scan gives every
+ * (digit, tile) its first output slot. */
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                                                    uint32_t *__restrict__ hist, int n_tiles)
+{
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + threadIdx.x;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + (int64_t)r * kBlock;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+/*
+ * Radix pass, phase 2: stable scatter.  A tile is read in kSortItems rounds of
+ * kBlock consecutive entries; in a round, entry order is thread order.  Each
+ * wave groups its lanes by digit with 8 ballots (the lanes holding the same
+ * digit), ranks a lane among its lower peers, and the waves' per-digit counts
+ * in LDS place the groups of lower waves first.  The tile is first sorted by
+ * digit in LDS, then written out in that order, so each digit's run of the
+ * tile goes to consecutive addresses.  keys_out may be NULL (last pass).
+ */
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
+                                                       const int32_t *__restrict__ rows_in,
+                                                       const float *__restrict__ vals_in, int64_t n, int shift,
+                                                       const uint32_t *__restrict__ hist,
+                                                       const uint32_t *__restrict__ offs, int n_tiles,
+                                                       uint32_t *__restrict__ keys_out,
+                                                       int32_t *__restrict__ rows_out,
+                                                       float *__restrict__ vals_out)
+{
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ int32_t s_row[kSortTile];
+    __shared__ float s_val[kSortTile];
+    __shared__ uint32_t run[kRadix];        // next tile-local slot of each digit
+    __shared__ uint32_t goff[kRadix];       // global slot of tile-local slot 0 of each digit's run
+    __shared__ uint32_t wc[kWavesPerBlock][kRadix];
+    __shared__ uint32_t s_w[kWavesPerBlock];
+    const int t = threadIdx.x, wave = t >> 6;
+    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    {
+        const int64_t hidx = (int64_t)t * n_tiles + blockIdx.x;
+        uint32_t total;
+        const uint32_t start = block_excl_scan(hist[hidx], s_w, &total);
+        run[t] = start;
+        goff[t] = offs[hidx] - start;
+    }
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) wc[w][t] = 0u;
+    __syncthreads();
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = tile0 + (int64_t)r * kBlock + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const int32_t row = valid ? rows_in[i] : 0;
+        const float val = valid ? vals_in[i] : 0.0f;
+        const uint32_t d = (key >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)mbcnt64(peers);
+        if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t lp = run[d] + rank;
+#pragma unroll
+            for (int w = 0; w < kWavesPerBlock; ++w) lp += w < wave ? wc[w][d] : 0u;
+            s_key[lp] = key;
+            s_row[lp] = row;
+            s_val[lp] = val;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            tot += wc[w][t];
+            wc[w][t] = 0u;
+        }
+        run[t] += tot;
+        __syncthreads();
+    }
+    const int64_t rem = n - tile0;
+    const int m = rem < kSortTile ? (int)rem : kSortTile;
+    for (int lp = t; lp < m; lp += kBlock) {
+        const uint32_t key = s_key[lp];
+        const uint32_t pos = goff[(key >> shift) & (kRadix - 1)] + (uint32_t)lp;
+        if (keys_out) keys_out[pos] = key;
+        rows_out[pos] = s_row[lp];
+        vals_out[pos] = s_val[lp];
+    }
+}
+
+}  // namespace
+
+static inline unsigned blocks_of(int64_t items, int per_block)
+{
+    return (unsigned)((items + per_block - 1) / per_block);
+}
+
+hipError_t launch_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                               int n_voxels, const float *w, float *dose, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero, dim3(blocks_of(n_voxels, kBlock)), dim3(kBlock), 0, s, dose, (int64_t)n_voxels);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_rows == 0) return e;
+    hipLaunchKernelGGL(k_fluence_dose, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
+                       values, n_rows, n_voxels, w, dose);
+    return hipGetLastError();
+}
+
+hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                                   int n_voxels, const float *r, float *g, hipStream_t s)
+{
+    if (n_rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fluence_gradient, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr,
+                       indices, values, n_rows, n_voxels, r, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values, int n_voxels,
+                             int n_w, const float *w, float *dose, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_voxel_dose, dim3(blocks_of((int64_t)n_voxels * 16, kBlock)), dim3(kBlock), 0, s, t_indptr,
+                       t_indices, t_values, n_voxels, n_w, w, dose);
+    return hipGetLastError();
+}
+
+/* Workspace layout of the transpose (offsets from a 256-byte aligned base). */
+struct TransposeLayout {
+    size_t key[2], row[2], val[2], hist, offs, partial, counts, bad, total;
+};
+
+static TransposeLayout transpose_layout(int64_t nnz, int n_voxels)
+{
+    TransposeLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const int64_t n_tiles = (nnz + kSortTile - 1) / kSortTile;
+    const int64_t n_hist = (int64_t)kRadix * (n_tiles > 0 ? n_tiles : 1);
+    const int64_t n_scan = n_hist > n_voxels ? n_hist : n_voxels;
+    const size_t e = (size_t)(nnz > 0 ? nnz : 1);
+    for (int b = 0; b < 2; ++b) {
+        L.key[b] = take(sizeof(uint32_t) * e);
+        L.row[b] = take(sizeof(int32_t) * e);
+        L.val[b] = take(sizeof(float) * e);
+    }
+    L.hist = take(sizeof(uint32_t) * (size_t)n_hist);
+    L.offs = take(sizeof(uint32_t) * (size_t)n_hist);
+    L.partial = take(sizeof(uint32_t) * (size_t)((n_scan + kScanChunk - 1) / kScanChunk + 1));
+    L.counts = take(sizeof(uint32_t) * (size_t)n_voxels);
+    L.bad = take(sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+size_t transpose_workspace(int64_t nnz, int n_voxels) { return transpose_layout(nnz, n_voxels).total; }
+
+int transpose_passes(int n_voxels)
+{
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n_voxels) ++bits;
+    const int p = (bits + kRadixBits - 1) / kRadixBits;
+    return p > 0 ? p : 1;
+}
+
+/* Exclusive scan of n uint32 values in -> out (OUT = uint32_t or int64_t);
+ * partial[nblocks] receives the total, and *total64 too when given. */
+template <typename OUT>
+static hipError_t scan_excl(const uint32_t *in, int64_t n, uint32_t *partial, OUT *out, int64_t *total64,
+                            hipStream_t s)
+{
+    const unsigned nb = blocks_of(n, kScanChunk);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, partial);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, partial, (int)nb, total64);
+    if (nb > 0) hipLaunchKernelGGL((k_scan_down<OUT>), dim3(nb), dim3(kBlock), 0, s, in, n, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
+                            int n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices, float *t_values,
+                            void *workspace, int32_t *bad_host, hipStream_t s)
+{
+    const TransposeLayout L = transpose_layout(nnz, n_voxels);
+    char *ws = static_cast<char *>(workspace);
+    uint32_t *key[2] = {reinterpret_cast<uint32_t *>(ws + L.key[0]), reinterpret_cast<uint32_t *>(ws + L.key[1])};
+    int32_t *row[2] = {reinterpret_cast<int32_t *>(ws + L.row[0]), reinterpret_cast<int32_t *>(ws + L.row[1])};
+    float *val[2] = {reinterpret_cast<float *>(ws + L.val[0]), reinterpret_cast<float *>(ws + L.val[1])};
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    uint32_t *offs = reinterpret_cast<uint32_t *>(ws + L.offs);
+    uint32_t *partial = reinterpret_cast<uint32_t *>(ws + L.partial);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(ws + L.counts);
+    int32_t *bad = reinterpret_cast<int32_t *>(ws + L.bad);
+    hipError_t e;
+
+    // voxel-row pointers: entries per voxel, exclusive scan, total at t_indptr[n_voxels]
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of(n_voxels, kBlock)), dim3(kBlock), 0, s, counts, (int64_t)n_voxels);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(bad), (int64_t)1);
+    if (nnz > 0) {
+        const int64_t want = (nnz + kBlock - 1) / kBlock;
+        const unsigned g = (unsigned)(want < 65536 ? want : 65536);
+        hipLaunchKernelGGL(k_col_count, dim3(g), dim3(kBlock), 0, s, indices, nnz, n_voxels, counts, bad);
+    }
+    if ((e = scan_excl<int64_t>(counts, n_voxels, partial, t_indptr, t_indptr + n_voxels, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(bad_host, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (*bad || nnz == 0) return hipSuccess;
+
+    // row id of every entry (into row[1], free until the second pass writes it)
+    hipLaunchKernelGGL(k_expand_rows, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, n_rows, nnz,
+                       row[1]);
+    const int n_tiles = (int)blocks_of(nnz, kSortTile);
+    const int passes = transpose_passes(n_voxels);
+    const uint32_t *kin = reinterpret_cast<const uint32_t *>(indices);
+    const int32_t *rin = row[1];
+    const float *vin = values;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kRadixBits;
+        const bool last = p == passes - 1;
+        uint32_t *kout = last ? nullptr : key[p & 1];
+        int32_t *rout = last ? t_indices : row[p & 1];
+        float *vout = last ? t_values : val[p & 1];
+        hipLaunchKernelGGL(k_rs_hist, dim3(n_tiles), dim3(kBlock), 0, s, kin, nnz, shift, hist, n_tiles);
+        if ((e = scan_excl<uint32_t>(hist, (int64_t)kRadix * n_tiles, partial, offs, nullptr, s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(n_tiles), dim3(kBlock), 0, s, kin, rin, vin, nnz, shift, hist, offs,
+                           n_tiles, kout, rout, vout);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        kin = kout;
+        rin = rout;
+        vin = vout;
+    }
+    return hipSuccess;
+}
+
+}  // namespace fspb

@@ -39,8 +39,48 @@ class CSR:
         import torch
         g = torch.empty(self.indptr.numel() - 1, dtype=torch.float32, device=self.values.device)
         L.fspb_fluence_gradient(self.indptr.data_ptr(), self.indices.data_ptr(), self.values.data_ptr(),
-                                self.indptr.numel() - 1, r.data_ptr(), g.data_ptr(), self._s(stream))
+                                self.indptr.numel() - 1, self.n_voxels, r.data_ptr(), g.data_ptr(),
+                                self._s(stream))
         return g
+
+    def transpose(self, stream=None):
+        """Voxel-row form of D (rows = voxels, beamlets ascending in each row)."""
+        import torch
+        dev = self.values.device
+        n_rows, nnz = self.indptr.numel() - 1, self.nnz
+        s = self._s(stream)
+        _, need = L.fspb_csr_transpose(None, None, None, n_rows, self.n_voxels, nnz, None, None, None, None, 0, s)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        wsp = (ws.data_ptr() + 255) // 256 * 256
+        t_indptr = torch.empty(self.n_voxels + 1, dtype=torch.int64, device=dev)
+        t_indices = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+        t_values = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)[:nnz]
+        L.fspb_csr_transpose(self.indptr.data_ptr(), self.indices.data_ptr(), self.values.data_ptr(), n_rows,
+                             self.n_voxels, nnz, t_indptr.data_ptr(), t_indices.data_ptr(), t_values.data_ptr(),
+                             wsp, need, s)
+        return VoxelCSR(t_indptr, t_indices, t_values, n_rows)
+
+
+@dataclass
+class VoxelCSR:
+    """D_ij with rows = voxels, columns = beamlet ids (ascending per row)."""
+    indptr: "torch.Tensor"      # int64 [n_voxels + 1]
+    indices: "torch.Tensor"     # int32 [nnz]
+    values: "torch.Tensor"      # float32 [nnz]
+    n_beamlets: int
+
+    @property
+    def n_voxels(self):
+        return int(self.indptr.numel() - 1)
+
+    def dose(self, w, stream=None):
+        """Eq. 1 by voxel rows: bit-reproducible dose of the beamlet weights w."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.values.device)
+        d = torch.empty(self.n_voxels, dtype=torch.float32, device=self.values.device)
+        L.fspb_voxel_dose(self.indptr.data_ptr(), self.indices.data_ptr(), self.values.data_ptr(), self.n_voxels,
+                          self.n_beamlets, w.data_ptr(), d.data_ptr(), C.c_void_p(s.cuda_stream))
+        return d
 
 
 def _structs(problem, density_ptr):

@@ -1,0 +1,97 @@
+"""Voxel-row transpose of D and the voxel-row dose (Eq. 1) on the GPU.
+
+* seeded random CSR matrices: bit-exact against the oracle's transpose (one,
+  two and three radix passes, several sort tiles with a ragged tail, empty
+  rows and columns, nnz = 0, one column);
+* an out-of-range column is refused;
+* a plan's D: the voxel-row dose against the oracle's FP64 Eq. 1, and the
+  transposed entries against the beamlet-row CSR they came from (same
+  triples, beamlets ascending in every voxel row).
+"""
+import numpy as np
+import pytest
+
+import fspb_inputs as fi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _csr(torch, indptr, indices, values, n_cols):
+    from paper_0908_4417_amd import CSR
+    dev = "cuda:0"
+    return CSR(torch.from_numpy(indptr).to(dev), torch.from_numpy(indices).to(dev),
+               torch.from_numpy(values).to(dev), n_cols)
+
+
+@pytest.mark.parametrize("seed,n_rows,n_cols,mean_row", [
+    (1, 50, 200, 17.0),          # one pass, < one tile
+    (2, 700, 5000, 90.0),        # two passes, ~16 tiles
+    (3, 300, 70000, 400.0),      # three passes, ~30 tiles
+    (4, 64, 1, 0.7),             # a single column
+])
+def test_random_matrix_matches_oracle(torch_gpu, oracle_lib, seed, n_rows, n_cols, mean_row):
+    torch = torch_gpu
+    indptr, indices, values = fi.random_csr(seed, n_rows, n_cols, mean_row)
+    print(f"\n  case seed={seed} rows={n_rows} cols={n_cols} nnz={len(indices)}", flush=True)
+    t = _csr(torch, indptr, indices, values, n_cols).transpose()
+    torch.cuda.synchronize()
+    ep, ei, ev = oracle_lib.csr_transpose(indptr, indices, values, n_cols)
+    np.testing.assert_array_equal(t.indptr.cpu().numpy(), ep)
+    np.testing.assert_array_equal(t.indices.cpu().numpy(), ei)
+    np.testing.assert_array_equal(t.values.cpu().numpy(), ev)
+    # voxel-row dose vs the definition in FP64
+    w = np.random.default_rng(seed).uniform(size=n_rows).astype(np.float32)
+    d = t.dose(torch.from_numpy(w).to("cuda:0")).cpu().numpy().astype(np.float64)
+    vox = np.repeat(np.arange(n_cols), np.diff(ep))
+    ref = np.bincount(vox, weights=ev.astype(np.float64) * w[ei].astype(np.float64), minlength=n_cols)
+    assert np.max(np.abs(d - ref)) <= 4e-6 * max(ref.max(), 1e-30)
+
+
+def test_empty_and_invalid(torch_gpu):
+    torch = torch_gpu
+    import paper_0908_4417_amd as m
+    indptr = np.zeros(6, dtype=np.int64)
+    t = _csr(torch, indptr, np.zeros(0, np.int32), np.zeros(0, np.float32), 9).transpose()
+    assert t.indptr.cpu().numpy().tolist() == [0] * 10 and t.indices.numel() == 0
+    d = t.dose(torch.ones(5, device="cuda:0")).cpu().numpy()
+    assert np.all(d == 0.0)
+    bad = _csr(torch, np.array([0, 2], np.int64), np.array([1, 9], np.int32), np.ones(2, np.float32), 9)
+    with pytest.raises(m.FspbError, match="outside"):
+        bad.transpose()
+
+
+def test_plan_voxel_rows(torch_gpu, oracle_lib):
+    torch = torch_gpu
+    from paper_0908_4417_amd import Plan
+    g = fi.slab_phantom(21, n=(40, 38, 26), spacing=(0.5, 0.5, 0.5), lung_side=(3, 6), bone_side=(1, 2))
+    prob = fi.Problem("vt", g, fi.coplanar_beams(4, (0.11, -0.05, 0.07), 100.0, 1.0, 1.0, 5, 4),
+                      fi.default_kernel(21))
+    plan = Plan(prob, "cuda:0")
+    csr = plan.compute()
+    t = csr.transpose()
+    rng = np.random.default_rng(8)
+    w = rng.uniform(0.0, 2.0, plan.n_beamlets).astype(np.float32)
+    wd = torch.from_numpy(w).to("cuda:0")
+    d = t.dose(wd).cpu().numpy().astype(np.float64)
+    d_atomic = csr.dose(wd).cpu().numpy().astype(np.float64)
+    ref = oracle_lib.OraclePlan(prob).fluence_dose(w.astype(np.float64))
+    assert np.max(np.abs(d - ref)) <= 1e-5 * ref.max()
+    assert np.max(np.abs(d - d_atomic)) <= 1e-6 * ref.max()
+    np.testing.assert_array_equal(t.dose(wd).cpu().numpy(), d.astype(np.float32))   # bit-reproducible
+    # the same (voxel, beamlet, value) triples, beamlets ascending per voxel row
+    ip, ix, vv = csr.indptr.cpu().numpy(), csr.indices.cpu().numpy(), csr.values.cpu().numpy()
+    tp, ti, tv = t.indptr.cpu().numpy(), t.indices.cpu().numpy(), t.values.cpu().numpy()
+    rows = np.repeat(np.arange(plan.n_beamlets), np.diff(ip))
+    vox = np.repeat(np.arange(plan.n_voxels), np.diff(tp))
+    a = np.lexsort((rows, ix))
+    np.testing.assert_array_equal(vox, ix[a])
+    np.testing.assert_array_equal(ti, rows[a])
+    np.testing.assert_array_equal(tv, vv[a])
