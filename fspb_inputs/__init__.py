@@ -67,6 +67,7 @@ class KernelParams:
     cutoff_v: float = 3.0
     table_step: float = 0.0        # <=0: half the smallest voxel spacing
     rho_min: float = 0.0
+    depth: str = "siddon"          # depth table: "siddon" (exact path integral) or "trilinear"
 
     @property
     def n_terms(self):

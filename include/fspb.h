@@ -32,7 +32,9 @@
  *   - the radiological depth d at O' is read by linear interpolation from a
  *     per-beamlet table of n equally spaced points on AB (A, B = entry and
  *     exit of the axis through the grid's bounding box; Sec. 2.2), each
- *     point's depth being the Siddon (1985) path integral of density from A;
+ *     point's depth being the Siddon (1985) path integral of density from A
+ *     (or, with FSPB_DEPTH_TRILINEAR, the trapezoid sum of trilinear density
+ *     samples at the table points, as the paper builds the table);
  *     d = 0 before A and d = depth(B) beyond B.
  *
  * Units: cm, g/cc relative to water, degrees.
@@ -104,8 +106,17 @@ typedef struct {
     double table_step;           /* nominal depth-table element; <= 0 selects half the
                                     smallest voxel spacing (Sec. 3.2) */
     float rho_min;               /* voxels with density <= rho_min are in no VOI */
-    uint32_t flags;              /* must be 0 */
+    uint32_t flags;              /* 0 or FSPB_DEPTH_TRILINEAR */
 } fspb_kernel;
+
+/*
+ * kernel.flags: build the radiological-depth table as Sec. 2.2 describes it,
+ * from densities sampled by trilinear interpolation of the voxel centres at
+ * the n table points (each coordinate held at the outermost centre plane)
+ * and summed by the trapezoid rule, instead of the exact path integral
+ * through the voxels (the default).
+ */
+#define FSPB_DEPTH_TRILINEAR 1u
 
 /* Static description of a created plan. */
 typedef struct {
@@ -138,8 +149,11 @@ fspb_status fspb_plan_create(const fspb_grid *grid, const fspb_beam *beams, int3
  * Radiological-depth tables (Sec. 2.2): for every beamlet, trace its central
  * axis from A to B through the density grid (Siddon; crossing parameters in
  * FP64, path sums in FP32 with compensation) and tabulate the depth at the
- * table points.  Also derives the density mask (density > rho_min) used by
- * the VOI test.  Reads the borrowed density; enqueues work on `stream`.
+ * table points; with FSPB_DEPTH_TRILINEAR the density is instead sampled by
+ * trilinear interpolation at the table points (FP64) and summed by
+ * trapezoids.  Also derives the density mask (density > rho_min) used by the
+ * VOI test.  Reads the borrowed density; enqueues work on `stream`.
+ * Invalidates the row counts of an earlier fspb_dose_coeffs.
  */
 fspb_status fspb_raytrace(fspb_plan *plan, void *stream);
 
@@ -157,6 +171,23 @@ fspb_status fspb_raytrace(fspb_plan *plan, void *stream);
  */
 fspb_status fspb_dose_coeffs(fspb_plan *plan, int64_t *indptr, int32_t *indices, float *values,
                              int64_t capacity, int64_t *nnz_out, void *stream);
+
+/*
+ * Rows j0 .. j1-1 of D only, for callers whose memory holds a part of the
+ * matrix at a time (the paper computes the beams of a plan in turns on a
+ * small card, Sec. 4).  fspb_dose_coeffs must have counted the rows of the
+ * current trace first (NULL indices only count): indptr is the row-pointer
+ * array it wrote (DEVICE, n_beamlets + 1, unchanged since).  Entry e of row j
+ * is written at indptr[j] - indptr[j0] + e of indices / values (DEVICE,
+ * capacity entries each); *nnz_out = indptr[j1] - indptr[j0] (HOST).
+ * Synchronises `stream` once (to read the two row pointers).
+ * Errors: INVALID (bad range or arguments), STATE (rows not counted since the
+ * last fspb_raytrace), CAPACITY (arrays too small; *nnz_out reports the size).
+ * The same plan's calls share one output record: run them in stream order.
+ */
+fspb_status fspb_dose_coeffs_rows(fspb_plan *plan, int32_t j0, int32_t j1, const int64_t *indptr,
+                                  int32_t *indices, float *values, int64_t capacity, int64_t *nnz_out,
+                                  void *stream);
 
 /* Release the plan's host metadata (the workspace stays the caller's). NULL is a no-op. */
 void fspb_plan_destroy(fspb_plan *plan);
@@ -357,7 +388,9 @@ void fspb_surrogate_destroy(fspb_surrogate *sur);
  * added with FP32 atomics, so the rounding of each voxel's sum depends on
  * the order in which rows land (the value itself is the same to FP32
  * precision; fspb_voxel_dose is the bit-reproducible form).  Entries whose
- * column lies outside [0, n_voxels) are skipped.
+ * column lies outside [0, n_voxels) are skipped.  indices and values are
+ * read only where indptr says there are entries (they may be NULL for a
+ * matrix without any).
  */
 fspb_status fspb_fluence_dose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
                               int32_t n_voxels, const float *w, float *dose, void *stream);
@@ -366,7 +399,8 @@ fspb_status fspb_fluence_dose(const int64_t *indptr, const int32_t *indices, con
  * g[j] = sum_i D_ij r[i] (the gradient of sum_i r_i D_i with respect to the
  * beamlet weights).  DEVICE pointers; r has n_voxels entries, g has n_rows
  * and is overwritten.  Each row is summed by one wave in a fixed order:
- * deterministic.  Entries whose column lies outside [0, n_voxels) are skipped.
+ * deterministic.  Entries whose column lies outside [0, n_voxels) are skipped;
+ * indices and values may be NULL for a matrix without entries.
  */
 fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices, const float *values,
                                   int32_t n_rows, int32_t n_voxels, const float *r, float *g, void *stream);
@@ -395,7 +429,7 @@ fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, co
  * each voxel row is summed by 16 lanes in a fixed order (bit-reproducible, no
  * atomics).  DEVICE pointers; w has n_beamlets entries, dose n_voxels and is
  * overwritten.  Entries whose beamlet lies outside [0, n_beamlets) are
- * skipped.
+ * skipped; t_indices and t_values may be NULL for a matrix without entries.
  */
 fspb_status fspb_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values,
                             int32_t n_voxels, int32_t n_beamlets, const float *w, float *dose, void *stream);

@@ -52,13 +52,19 @@ class OBeam(C.Structure):
                 ("nu", C.c_int32), ("nv", C.c_int32)]
 
 
+# how the radiological-depth table is built (Sec. 2.2): the exact path
+# integral through the voxels, or trilinear samples summed by trapezoids
+DEPTH_MODES = {"siddon": 0, "trilinear": 1}
+
+
 class OKernel(C.Structure):
     _fields_ = [("n_terms", C.c_int32), ("n_pdd", C.c_int32),
                 ("weight", C.c_double * 4), ("sigma0", C.c_double * 4),
                 ("sigma_slope", C.c_double * 4), ("width_scale", C.c_double * 4),
                 ("pdd", C.POINTER(C.c_float)), ("pdd_step", C.c_double),
                 ("cutoff_u", C.c_double), ("cutoff_v", C.c_double),
-                ("table_step", C.c_double), ("rho_min", C.c_double)]
+                ("table_step", C.c_double), ("rho_min", C.c_double),
+                ("depth_mode", C.c_int32), ("pad_", C.c_int32)]
 
 
 class OBeamlet(C.Structure):
@@ -66,7 +72,8 @@ class OBeamlet(C.Structure):
                 ("S", C.c_double * 3), ("e", C.c_double * 3), ("eu", C.c_double * 3),
                 ("ev", C.c_double * 3), ("tA", C.c_double), ("tB", C.c_double),
                 ("step", C.c_double), ("sad", C.c_double), ("a", C.c_double), ("b", C.c_double),
-                ("cu", C.c_double), ("cv", C.c_double)]
+                ("cu", C.c_double), ("cv", C.c_double),
+                ("depth_mode", C.c_int32), ("pad_", C.c_int32)]
 
 
 _lib = None
@@ -86,6 +93,7 @@ def lib():
             "ofs_siddon": (i32, [P(OGrid), P(d), P(d), d, d, P(i64), P(d), i32]),
             "ofs_depth_table": (i32, [P(OGrid), P(OBeamlet), P(d)]),
             "ofs_exact_depth": (d, [P(OGrid), P(OBeamlet), d]),
+            "ofs_trilinear_density": (d, [P(OGrid), P(d)]),
             "ofs_table_depth": (d, [P(OBeamlet), P(d), d]),
             "ofs_pdd": (d, [P(OKernel), d]),
             "ofs_edge_pair": (d, [d, d, d]),
@@ -143,7 +151,8 @@ class OraclePlan:
         pad = lambda v: (C.c_double * 4)(*(list(v) + [0.0] * (4 - len(v))))
         self.kernel = OKernel(kp.n_terms, len(self.pdd), pad(kp.weight), pad(kp.sigma0),
                               pad(kp.sigma_slope), pad(kp.width_scale), _ptr(self.pdd, C.c_float),
-                              kp.pdd_step, kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min)
+                              kp.pdd_step, kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min,
+                              DEPTH_MODES[kp.depth], 0)
         self.n_beams = len(problem.beams)
         self.n_beamlets = lib().ofs_count_beamlets(self.beams, self.n_beams)
         self._beamlets = None
@@ -248,6 +257,11 @@ class OraclePlan:
         m = lib().ofs_voi_member(C.byref(self.grid), C.byref(self.kernel), C.byref(self.beamlets[j]),
                                  ix, iy, iz, C.byref(t), C.byref(u), C.byref(v))
         return bool(m), t.value, u.value, v.value
+
+    def trilinear_density(self, p):
+        """Density at point p by trilinear interpolation of the voxel centres."""
+        q = (C.c_double * 3)(*p)
+        return lib().ofs_trilinear_density(C.byref(self.grid), q)
 
     def exact_depth(self, j, t):
         return lib().ofs_exact_depth(C.byref(self.grid), C.byref(self.beamlets[j]), t)

@@ -65,6 +65,8 @@ typedef struct {
     double cutoff_u, cutoff_v; /* VOI half-widths at iso; <= 0 means 3a, 3b */
     double table_step;         /* nominal table element; <= 0 means half the smallest spacing */
     double rho_min;            /* voxels with density <= rho_min are not in any VOI */
+    int32_t depth_mode;        /* 0: exact path integral (Siddon); 1: trilinear samples + trapezoid */
+    int32_t pad_;
 } ofs_kernel;
 
 /* One beamlet: pencil-beam frame of Fig. 1b plus its depth-table layout. */
@@ -76,6 +78,8 @@ typedef struct {
     double tA, tB;             /* distances from S to A and to B */
     double step;               /* spacing of the table points on AB */
     double sad, a, b, cu, cv;
+    int32_t depth_mode;        /* copied from the kernel: how the depth table is built */
+    int32_t pad_;
 } ofs_beamlet;
 
 /* ------------------------------------------------------------ small vecs */
@@ -174,6 +178,7 @@ int32_t ofs_geometry(const ofs_grid *g, const ofs_beam *beams, int32_t n_beams,
                 bl->ev[1] = bl->eu[2] * bl->e[0] - bl->eu[0] * bl->e[2];
                 bl->ev[2] = bl->eu[0] * bl->e[1] - bl->eu[1] * bl->e[0];
                 double tA, tB;
+                bl->depth_mode = K->depth_mode;
                 if (!clip_to_grid(g, bl->S, bl->e, &tA, &tB)) { bl->n = 0; continue; }
                 bl->tA = tA; bl->tB = tB;
                 /* n equally spaced points on AB, both ends included, no further
@@ -273,9 +278,65 @@ static void free_segs(seglist *sl) { free(sl->t0); free(sl->len); free(sl->rho);
  * R(t) = integral of density from A to S + t e, piecewise linear in t.
  * Returns n.
  */
+/*
+ * Density at point p from the voxel-centre values by trilinear interpolation
+ * (the sampling Sec. 2.2 uses to build the depth table).  Along each axis the
+ * position is held at the first / last centre plane, so the half voxel
+ * between a centre plane and the box face takes the boundary voxels' values.
+ */
+double ofs_trilinear_density(const ofs_grid *g, const double p[3])
+{
+    int i0[3], i1[3];
+    double f[3];
+    for (int k = 0; k < 3; ++k) {
+        int n = grid_n(g, k);
+        double c = (p[k] - g->origin[k]) / g->spacing[k];
+        if (c < 0.0) c = 0.0;
+        if (c > n - 1) c = n - 1;
+        int lo = (int)floor(c);
+        if (lo > n - 2) lo = n - 2;
+        if (lo < 0) lo = 0;
+        i0[k] = lo;
+        i1[k] = n > 1 ? lo + 1 : lo;
+        f[k] = n > 1 ? c - lo : 0.0;
+    }
+    double r = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+        int ix = (corner & 1) ? i1[0] : i0[0];
+        int iy = (corner & 2) ? i1[1] : i0[1];
+        int iz = (corner & 4) ? i1[2] : i0[2];
+        double w = ((corner & 1) ? f[0] : 1.0 - f[0]) * ((corner & 2) ? f[1] : 1.0 - f[1]) *
+                   ((corner & 4) ? f[2] : 1.0 - f[2]);
+        r += w * g->density[((int64_t)iz * g->ny + iy) * g->nx + ix];
+    }
+    return r;
+}
+
+/*
+ * Depth table of Sec. 2.2 as the paper builds it: the density is sampled by
+ * trilinear interpolation at the n table points on AB and the depth from A
+ * to point k is the trapezoid sum of the samples over the elements before it.
+ */
+static void depth_table_trilinear(const ofs_grid *g, const ofs_beamlet *bl, double *table)
+{
+    double prev_rho = 0.0, prev_t = bl->tA;
+    for (int32_t k = 0; k < bl->n; ++k) {
+        double t = (k == bl->n - 1) ? bl->tB : bl->tA + k * bl->step;
+        double p[3] = { bl->S[0] + t * bl->e[0], bl->S[1] + t * bl->e[1], bl->S[2] + t * bl->e[2] };
+        double rho = ofs_trilinear_density(g, p);
+        table[k] = k == 0 ? 0.0 : table[k - 1] + 0.5 * (t - prev_t) * (prev_rho + rho);
+        prev_rho = rho;
+        prev_t = t;
+    }
+}
+
 int32_t ofs_depth_table(const ofs_grid *g, const ofs_beamlet *bl, double *table)
 {
     if (bl->n == 0) return 0;
+    if (bl->depth_mode == 1) {
+        depth_table_trilinear(g, bl, table);
+        return bl->n;
+    }
     seglist sl;
     trace_axis(g, bl, &sl);
     int32_t s = 0;

@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 from ._lib import (FSPB_OK, FSPB_ERR_INVALID, FSPB_ERR_STATE, FSPB_ERR_CAPACITY, FSPB_ERR_HIP,
-                   FSPB_ERR_NOMEM, FSPB_ERR_OVERFLOW, FspbError, FspbGrid, FspbBeam, FspbKernel,
+                   FSPB_ERR_NOMEM, FSPB_ERR_OVERFLOW, FSPB_DEPTH_TRILINEAR, FspbError, FspbGrid, FspbBeam, FspbKernel,
                    FspbPlanDesc, FspbTiming, lib, library_path, EXPORTED,
                    fspb_plan_create, fspb_raytrace, fspb_dose_coeffs, fspb_plan_destroy,
                    fspb_plan_info, fspb_plan_get_tables, fspb_plan_set_timing, fspb_plan_get_timing,
@@ -31,7 +31,7 @@ from ._lib import (FspbBatchConfig, fspb_batch_create, fspb_batch_nnz, fspb_batc
                    fspb_surrogate_targets, fspb_surrogate_forward, fspb_surrogate_gradient,
                    fspb_surrogate_train, fspb_surrogate_get_params, fspb_surrogate_set_params,
                    fspb_plan_set_surrogate, fspb_surrogate_destroy, fspb_fluence_dose,
-                   fspb_fluence_gradient, fspb_csr_transpose, fspb_voxel_dose)
+                   fspb_fluence_gradient, fspb_csr_transpose, fspb_voxel_dose, fspb_dose_coeffs_rows)
 
 __all__ = [
     "Plan", "CSR", "VoxelCSR", "Batch", "Surrogate", "FspbError", "FspbBatchConfig", "FspbTrainConfig",
@@ -39,6 +39,7 @@ __all__ = [
     "fspb_surrogate_gradient", "fspb_surrogate_train", "fspb_surrogate_get_params",
     "fspb_surrogate_set_params", "fspb_plan_set_surrogate", "fspb_surrogate_destroy",
     "fspb_fluence_dose", "fspb_fluence_gradient", "fspb_csr_transpose", "fspb_voxel_dose",
+    "fspb_dose_coeffs_rows",
     "fspb_batch_create", "fspb_batch_nnz", "fspb_batch_bind", "fspb_batch_tune", "fspb_batch_get_config",
     "fspb_batch_set_config", "fspb_batch_run", "fspb_batch_check", "fspb_batch_destroy", "lib", "library_path", "EXPORTED",
     "fspb_plan_create", "fspb_raytrace", "fspb_dose_coeffs", "fspb_plan_destroy",

@@ -18,6 +18,7 @@ FSPB_ERR_CAPACITY = -3
 FSPB_ERR_HIP = -4
 FSPB_ERR_NOMEM = -5
 FSPB_ERR_OVERFLOW = -6
+FSPB_DEPTH_TRILINEAR = 1       # fspb_kernel.flags: trilinear-sampled depth table
 
 
 class FspbError(RuntimeError):
@@ -114,6 +115,8 @@ _SIGS = {
     "fspb_surrogate_set_params": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float)]),
     "fspb_plan_set_surrogate": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fspb_surrogate_destroy": (None, [C.c_void_p]),
+    "fspb_dose_coeffs_rows": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_int64, C.POINTER(C.c_int64), C.c_void_p]),
     "fspb_fluence_dose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_fluence_gradient": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
@@ -322,6 +325,15 @@ def fspb_plan_set_surrogate(plan, sur):
 
 def fspb_surrogate_destroy(sur):
     lib().fspb_surrogate_destroy(sur)
+
+
+def fspb_dose_coeffs_rows(h, j0, j1, indptr, indices, values, capacity, stream):
+    """Returns (status, nnz of the rows); CAPACITY is returned, not raised, with the size."""
+    n = C.c_int64(0)
+    st = lib().fspb_dose_coeffs_rows(h, j0, j1, indptr, indices, values, capacity, C.byref(n), stream)
+    if st == FSPB_ERR_CAPACITY:
+        return st, n.value
+    return _check(st), n.value
 
 
 def fspb_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose, stream):

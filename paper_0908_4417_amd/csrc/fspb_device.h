@@ -69,7 +69,7 @@ struct alignas(16) PlanDev {
     int32_t ray_iters;           // bound on the per-interval Siddon loop
     int32_t n_tiles;
     int32_t max_tiles;           // most tiles of any beamlet
-    int32_t pad0;
+    int32_t depth_mode;          // 0: exact path integral; 1: trilinear samples + trapezoids
     const BeamletRec *rec;
     float *tables;
     const int32_t *tile_beamlet; // [n_tiles]
@@ -89,7 +89,8 @@ struct alignas(16) OutDev {
     float *values;               // capacity
     int64_t capacity;
     int32_t *overflow;           // set to 1 if a fill would exceed capacity
-    int64_t pad;
+    int32_t row0;                // first row written: entry positions are relative to indptr[row0]
+    int32_t pad;
 };
 
 /* Launchers (fspb_kernels.hip).  Each returns the launch's hipError_t. */
@@ -98,7 +99,9 @@ hipError_t launch_raytrace(const PlanDev *dplan, const PlanDev &h, hipStream_t s
 hipError_t launch_count(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
 hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h,
                               hipStream_t s);
-hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s);
+/* Fill rows row0 .. row0 + n_rows - 1 (dout->row0 must equal row0). */
+hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, int row0, int n_rows,
+                       hipStream_t s);
 size_t fill_shared_bytes(const PlanDev &h);
 
 /* Eq. 1 and its adjoint on a CSR. */

@@ -90,6 +90,7 @@ struct fspb_plan {
     int64_t table_entries = 0;
     int32_t n_voxels = 0;
     bool traced = false;
+    bool counted = false;         // row counts and pointers of the current trace are known
     // kernel parameters (to check a surrogate against)
     int32_t n_terms = 0;
     double weight[4] = {}, sigma0[4] = {}, sigma_slope[4] = {}, width_scale[4] = {}, pdd_step = 0.0;
@@ -165,7 +166,7 @@ fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams
     if (!finite(K->cutoff_u) || !finite(K->cutoff_v) || !finite(K->table_step))
         return fail(FSPB_ERR_INVALID, "kernel cutoffs and table_step must be finite");
     if (!std::isfinite(K->rho_min)) return fail(FSPB_ERR_INVALID, "kernel.rho_min must be finite");
-    if (K->flags != 0) return fail(FSPB_ERR_INVALID, "kernel.flags must be 0");
+    if (K->flags & ~FSPB_DEPTH_TRILINEAR) return fail(FSPB_ERR_INVALID, "kernel.flags has unknown bits");
     return FSPB_OK;
 }
 
@@ -325,6 +326,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     double hi[3] = {h.lo[0] + g->nx * g->spacing[0], h.lo[1] + g->ny * g->spacing[1], h.lo[2] + g->nz * g->spacing[2]};
     h.density = g->density;
     h.rho_min = K->rho_min;
+    h.depth_mode = (K->flags & FSPB_DEPTH_TRILINEAR) ? 1 : 0;
     h.n_terms = K->n_terms;
     h.n_pdd = K->n_pdd;
     for (int i = 0; i < fspb::kMaxTerms; ++i) {
@@ -539,6 +541,7 @@ fspb_status fspb_raytrace(fspb_plan *p, void *stream)
         p->have_trace_ev = true;
     }
     p->traced = true;
+    p->counted = false;
     return FSPB_OK;
 }
 
@@ -557,6 +560,8 @@ fspb_status fspb_dose_coeffs(fspb_plan *p, int64_t *indptr, int32_t *indices, fl
     p->out.values = values;
     p->out.capacity = (indices && values) ? capacity : 0;
     p->out.overflow = p->d_overflow;
+    p->out.row0 = 0;
+    p->counted = false;
     FSPB_HIP(hipMemcpyAsync(p->d_out, &p->out, sizeof(OutDev), hipMemcpyHostToDevice, s), "upload output record");
     p->have_dose_ev = false;
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[3], s), "record event");
@@ -568,15 +573,48 @@ fspb_status fspb_dose_coeffs(fspb_plan *p, int64_t *indptr, int32_t *indices, fl
     FSPB_HIP(hipMemcpyAsync(&nnz, p->d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read nnz");
     FSPB_HIP(hipStreamSynchronize(s), "synchronise for nnz");
     *nnz_out = nnz;
+    p->counted = true;
     if (!indices || !values || capacity < nnz)
         return fail(FSPB_ERR_CAPACITY, "%lld nonzeros do not fit a capacity of %lld", (long long)nnz,
                     (long long)(indices && values ? capacity : 0));
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[6], s), "record event");
-    FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, s), "launch fill");
+    FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, 0, p->h.n_beamlets, s), "launch fill");
     if (p->timing) {
         FSPB_HIP(hipEventRecord(p->ev[7], s), "record event");
         p->have_dose_ev = true;
     }
+    return FSPB_OK;
+}
+
+fspb_status fspb_dose_coeffs_rows(fspb_plan *p, int32_t j0, int32_t j1, const int64_t *indptr, int32_t *indices,
+                                  float *values, int64_t capacity, int64_t *nnz_out, void *stream)
+{
+    g_last_error.clear();
+    if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
+    if (!indptr || !nnz_out) return fail(FSPB_ERR_INVALID, "indptr or nnz_out is NULL");
+    if (j0 < 0 || j1 < j0 || j1 > p->h.n_beamlets)
+        return fail(FSPB_ERR_INVALID, "row range [%d, %d) outside [0, %d)", j0, j1, p->h.n_beamlets);
+    if (capacity < 0) return fail(FSPB_ERR_INVALID, "capacity must be >= 0");
+    if (!p->counted) return fail(FSPB_ERR_STATE, "fspb_dose_coeffs must count the rows first");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t ends[2] = {0, 0};
+    FSPB_HIP(hipMemcpyAsync(&ends[0], indptr + j0, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read indptr");
+    FSPB_HIP(hipMemcpyAsync(&ends[1], indptr + j1, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read indptr");
+    FSPB_HIP(hipStreamSynchronize(s), "synchronise for the row range");
+    const int64_t nnz = ends[1] - ends[0];
+    if (nnz < 0) return fail(FSPB_ERR_INVALID, "indptr is not the counted row-pointer array");
+    *nnz_out = nnz;
+    if (!indices || !values || capacity < nnz)
+        return fail(FSPB_ERR_CAPACITY, "%lld nonzeros do not fit a capacity of %lld", (long long)nnz,
+                    (long long)(indices && values ? capacity : 0));
+    p->out.indptr = const_cast<int64_t *>(indptr);
+    p->out.indices = indices;
+    p->out.values = values;
+    p->out.capacity = capacity;
+    p->out.overflow = p->d_overflow;
+    p->out.row0 = j0;
+    FSPB_HIP(hipMemcpyAsync(p->d_out, &p->out, sizeof(OutDev), hipMemcpyHostToDevice, s), "upload output record");
+    FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, j0, j1 - j0, s), "launch fill");
     return FSPB_OK;
 }
 
@@ -1303,7 +1341,6 @@ fspb_status fspb_fluence_dose(const int64_t *indptr, const int32_t *indices, con
 {
     g_last_error.clear();
     if (!indptr || !w || !dose || n_rows < 0 || n_voxels < 1) return fail(FSPB_ERR_INVALID, "invalid arguments");
-    if (n_rows > 0 && (!indices || !values)) return fail(FSPB_ERR_INVALID, "indices or values is NULL");
     FSPB_HIP(fspb::launch_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose,
                                        static_cast<hipStream_t>(stream)),
              "launch fluence dose");
@@ -1315,7 +1352,6 @@ fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices,
 {
     g_last_error.clear();
     if (!indptr || !r || !g || n_rows < 0 || n_voxels < 1) return fail(FSPB_ERR_INVALID, "invalid arguments");
-    if (n_rows > 0 && (!indices || !values)) return fail(FSPB_ERR_INVALID, "indices or values is NULL");
     FSPB_HIP(fspb::launch_fluence_gradient(indptr, indices, values, n_rows, n_voxels, r, g,
                                            static_cast<hipStream_t>(stream)),
              "launch fluence gradient");
@@ -1352,7 +1388,6 @@ fspb_status fspb_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, c
 {
     g_last_error.clear();
     if (!t_indptr || !w || !dose || n_voxels < 1 || n_beamlets < 0) return fail(FSPB_ERR_INVALID, "invalid arguments");
-    if (!t_indices || !t_values) return fail(FSPB_ERR_INVALID, "t_indices or t_values is NULL");
     FSPB_HIP(fspb::launch_voxel_dose(t_indptr, t_indices, t_values, n_voxels, n_beamlets, w, dose,
                                      static_cast<hipStream_t>(stream)),
              "launch voxel dose");

@@ -176,6 +176,60 @@ __device__ cpair interval_integral(const PlanDev &P, const BeamletRec &R, int m,
 }
 
 /* Depth table of beamlet j; one wave, lanes over table intervals. */
+/*
+ * Density at S + t e by trilinear interpolation of the voxel centres, each
+ * coordinate held at the first / last centre plane (FP64 position and
+ * weights, eight gathers).
+ */
+__device__ double density_trilinear(const PlanDev &P, const BeamletRec &R, double t)
+{
+    const int nv[3] = {P.nx, P.ny, P.nz};
+    int i0[3], st[3];
+    double f[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int n = nv[k];
+        double c = (R.S[k] + t * R.e[k] - P.org[k]) / P.sp[k];
+        c = fmin(fmax(c, 0.0), (double)(n - 1));
+        const int lo = n > 1 ? min((int)floor(c), n - 2) : 0;
+        i0[k] = lo;
+        st[k] = n > 1 ? 1 : 0;
+        f[k] = n > 1 ? c - lo : 0.0;
+    }
+    const size_t sy = (size_t)P.nx, sz = (size_t)P.nx * P.ny;
+    const float *base = P.density + (size_t)i0[2] * sz + (size_t)i0[1] * sy + i0[0];
+    double r = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const double w = ((c & 1) ? f[0] : 1.0 - f[0]) * ((c & 2) ? f[1] : 1.0 - f[1]) *
+                         ((c & 4) ? f[2] : 1.0 - f[2]);
+        r += w * (double)base[((c & 4) ? st[2] * sz : 0) + ((c & 2) ? st[1] * sy : 0) + ((c & 1) ? st[0] : 0)];
+    }
+    return r;
+}
+
+/* Depth table from trilinear samples at the table points, trapezoid sums in
+ * FP64 (one wave: lane m takes element m -> m + 1, then a wave prefix sum). */
+__device__ void raytrace_trilinear(const PlanDev &P, const BeamletRec &R, float *tab)
+{
+    const int lane = lane_id();
+    const int n = R.n_table;
+    if (lane == 0) tab[0] = 0.0f;
+    double carry = 0.0;
+    for (int m0 = 0; m0 < n - 1; m0 += kWave) {
+        const int m = m0 + lane;
+        double inc = 0.0;
+        if (m < n - 1) {
+            const double t0 = R.tA + (double)m * R.step;
+            const double t1 = (m == n - 2) ? R.tB : R.tA + (double)(m + 1) * R.step;
+            inc = 0.5 * (t1 - t0) * (density_trilinear(P, R, t0) + density_trilinear(P, R, t1));
+        }
+        const double incl = wave_incl_scan(inc);
+        if (m < n - 1) tab[m + 1] = (float)(carry + incl);
+        carry += __shfl(incl, kWave - 1, kWave);
+    }
+}
+
 __device__ void raytrace_beamlet(const PlanDev &P, int j)
 {
     const int lane = lane_id();
@@ -183,6 +237,10 @@ __device__ void raytrace_beamlet(const PlanDev &P, int j)
     const int n = R.n_table;
     if (n == 0) return;
     float *tab = P.tables + R.table_off;
+    if (P.depth_mode == 1) {
+        raytrace_trilinear(P, R, tab);
+        return;
+    }
     if (lane == 0) tab[0] = 0.0f;
     cpair carry = {0.0f, 0.0f};
     for (int m0 = 0; m0 < n - 1; m0 += kWave) {
@@ -483,7 +541,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const gptr<int32_t> out_idx = as_global<int32_t>(O.indices);
     const gptr<float> out_val = as_global<float>(O.values);
     const int64_t capacity = O.capacity;
-    const int64_t row_base = uniform64(O.indptr[j]);
+    const int64_t row_base = uniform64(O.indptr[j] - O.indptr[O.row0]);
 
     // ---- LDS: erf table, depth table, depth dose, tile prefix
     float4 *s_erf = reinterpret_cast<float4 *>(smem);
@@ -628,7 +686,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    fill_beamlet<K, kWavesPerBlock, false, SURR>(plans[0], outs[0], blockIdx.x, smem);
+    fill_beamlet<K, kWavesPerBlock, false, SURR>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
 }
 
 /* ------------------------------------------------------------ batches */
@@ -795,9 +853,12 @@ hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const Ou
     }
 }
 
-hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)
+hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, int row0, int n_rows,
+                       hipStream_t s)
 {
-    const dim3 grid(h.n_beamlets), block(kBlock);
+    (void)row0;   // read by the kernel from the output record
+    if (n_rows <= 0) return hipSuccess;
+    const dim3 grid(n_rows), block(kBlock);
     const size_t lds = fill_shared_bytes(h);
     if (h.use_mlp) {
         switch (h.n_terms) {

@@ -97,8 +97,36 @@ def _structs(problem, density_ptr):
     pad = lambda v: (C.c_double * 4)(*(list(v) + [0.0] * (4 - len(v))))
     kern = L.FspbKernel(kp.n_terms, len(pdd), pad(kp.weight), pad(kp.sigma0), pad(kp.sigma_slope),
                         pad(kp.width_scale), pdd.ctypes.data_as(C.POINTER(C.c_float)), kp.pdd_step,
-                        kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min, 0)
+                        kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min,
+                        L.FSPB_DEPTH_TRILINEAR if kp.depth == "trilinear" else 0)
     return grid, beams, kern, pdd
+
+
+def chunk_ranges(indptr, beam_rows, max_bytes, by_beam=True):
+    """Beamlet ranges [j0, j1) covering all rows whose entries take at most
+    ``max_bytes`` each (8 bytes per entry), given the row pointers.  With
+    ``by_beam`` a range ends at a beam boundary where one fits (the paper
+    computes a plan beam by beam on a small card); otherwise, or inside a beam
+    too large for the budget, at a beamlet.  A single row larger than the
+    budget raises ValueError."""
+    per = np.asarray(indptr, dtype=np.int64)
+    n = len(per) - 1
+    cap = int(max_bytes) // 8
+    rows = np.arange(n + 1)
+    units = np.concatenate([[0], np.cumsum(beam_rows)]).astype(np.int64) if by_beam else rows
+    out = []
+    j0 = 0
+    while j0 < n:
+        limit = per[j0] + cap
+        cand = units[(units > j0) & (per[units] <= limit)]
+        if len(cand) == 0:
+            cand = rows[(rows > j0) & (per[rows] <= limit)]
+            if len(cand) == 0:
+                raise ValueError(f"row {j0} alone needs {8 * int(per[j0 + 1] - per[j0])} bytes")
+        j1 = int(cand.max())
+        out.append((j0, j1))
+        j0 = j1
+    return out
 
 
 class Plan:
@@ -131,6 +159,7 @@ class Plan:
         self.indptr = torch.empty(self.n_beamlets + 1, dtype=torch.int64, device=self.device)
         self.indices = None
         self.values = None
+        self.beam_rows = [int(b.nu) * int(b.nv) for b in problem.beams]
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -168,6 +197,44 @@ class Plan:
         self.raytrace(stream)
         nnz = self.dose_coeffs(stream)
         return CSR(self.indptr, self.indices[:nnz], self.values[:nnz], self.n_voxels)
+
+    def count(self, stream=None):
+        """Trace and count only: fills ``self.indptr`` (all rows) and returns nnz; no entries."""
+        self.raytrace(stream)
+        st, nnz = L.fspb_dose_coeffs(self.handle, self.indptr.data_ptr(), None, None, 0, self._stream(stream))
+        self.nnz = nnz
+        return nnz
+
+    def compute_rows(self, j0, j1, indices=None, values=None, stream=None):
+        """Rows j0..j1-1 of D after ``count``: a CSR whose columns are voxels and
+        whose rows are those beamlets (row pointers start at 0).  ``indices`` /
+        ``values`` may be caller buffers of at least the rows' nnz entries."""
+        s = self._stream(stream)
+        st, n = L.fspb_dose_coeffs_rows(self.handle, j0, j1, self.indptr.data_ptr(), None, None, 0, s)
+        if indices is None or indices.numel() < n:
+            indices = self.torch.empty(max(n, 1), dtype=self.torch.int32, device=self.device)
+            values = self.torch.empty(max(n, 1), dtype=self.torch.float32, device=self.device)
+        L.fspb_dose_coeffs_rows(self.handle, j0, j1, self.indptr.data_ptr(), indices.data_ptr(),
+                                values.data_ptr(), indices.numel(), s)
+        ip = self.indptr[j0:j1 + 1] - self.indptr[j0]
+        return CSR(ip, indices[:n], values[:n], self.n_voxels)
+
+    def row_chunks(self, max_bytes, by_beam=True):
+        """Beamlet ranges of at most ``max_bytes`` of entries, after ``count``
+        (see ``chunk_ranges``)."""
+        return chunk_ranges(self.indptr.cpu().numpy(), self.beam_rows, max_bytes, by_beam)
+
+    def chunks(self, max_bytes, by_beam=True, stream=None):
+        """Yield (j0, j1, CSR) covering D in pieces of at most ``max_bytes`` of
+        entries; the pieces share one buffer, so each is overwritten by the next."""
+        self.count(stream)
+        ranges = self.row_chunks(max_bytes, by_beam)
+        per = self.indptr.cpu().numpy()
+        biggest = max([per[b] - per[a] for a, b in ranges] + [1])
+        idx = self.torch.empty(int(biggest), dtype=self.torch.int32, device=self.device)
+        val = self.torch.empty(int(biggest), dtype=self.torch.float32, device=self.device)
+        for a, b in ranges:
+            yield a, b, self.compute_rows(a, b, idx, val, stream)
 
     def set_surrogate(self, sur):
         """Attach a trained ``Surrogate`` (None: analytic fill)."""

@@ -83,7 +83,7 @@ def test_workspace_query(fspb):
     (lambda g, b, k: k.width_scale.__setitem__(0, 0.0), "width_scale"),
     (lambda g, b, k: setattr(k, "n_pdd", 1), "n_pdd"),
     (lambda g, b, k: setattr(k, "pdd_step", 0.0), "pdd_step"),
-    (lambda g, b, k: setattr(k, "flags", 1), "flags"),
+    (lambda g, b, k: setattr(k, "flags", 2), "flags"),
     (lambda g, b, k: setattr(k, "rho_min", float("inf")), "rho_min"),
 ])
 def test_invalid_arguments_rejected_before_device_work(fspb, mutate, msg):
@@ -173,3 +173,30 @@ def test_surrogate_arguments_rejected(fspb):
     cfg = fspb.FspbTrainConfig(1, 64, 1e-3, 0.0, 0.9, 0.999, 1e-8, 0, 0)
     assert L.fspb_surrogate_train(None, None, None, 0, C.byref(cfg), None, None) == fspb.FSPB_ERR_INVALID
     L.fspb_surrogate_destroy(None)
+
+
+def test_sparse_arguments_rejected(fspb):
+    """Eq. 1 / transpose entry points: size query and argument checks, no device work."""
+    L = fspb.lib()
+    need = C.c_size_t(0)
+    st = L.fspb_csr_transpose(None, None, None, 10, 1000, 5000, None, None, None, None, 0, C.byref(need), None)
+    assert st == fspb.FSPB_ERR_CAPACITY and need.value >= 24 * 5000
+    small = need.value
+    L.fspb_csr_transpose(None, None, None, 10, 1000, 50000, None, None, None, None, 0, C.byref(need), None)
+    assert need.value > small                                   # grows with nnz
+    assert L.fspb_csr_transpose(None, None, None, 10, 0, 5, None, None, None, None, 0, C.byref(need),
+                                None) == fspb.FSPB_ERR_INVALID
+    assert L.fspb_csr_transpose(None, None, None, 10, 5, 1 << 32, None, None, None, None, 0, C.byref(need),
+                                None) == fspb.FSPB_ERR_INVALID
+    assert "2^32" in fspb.fspb_last_error()
+    assert L.fspb_csr_transpose(None, None, None, 10, 5, 7, None, None, None, C.c_void_p(0x1000), 1,
+                                C.byref(need), None) == fspb.FSPB_ERR_CAPACITY
+    assert L.fspb_voxel_dose(None, None, None, 4, 2, None, None, None) == fspb.FSPB_ERR_INVALID
+    assert L.fspb_fluence_dose(None, None, None, 1, 1, None, None, None) == fspb.FSPB_ERR_INVALID
+    assert L.fspb_fluence_gradient(None, None, None, 1, 0, None, None, None) == fspb.FSPB_ERR_INVALID
+
+
+def test_every_entry_point_has_a_binding(fspb):
+    """Each exported C function is reachable from the package (wrapper or raw)."""
+    missing = [n for n in fspb.EXPORTED if not hasattr(fspb, n)]
+    assert not missing, missing
