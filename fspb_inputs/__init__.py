@@ -68,10 +68,24 @@ class KernelParams:
     table_step: float = 0.0        # <=0: half the smallest voxel spacing
     rho_min: float = 0.0
     depth: str = "siddon"          # depth table: "siddon" (exact path integral) or "trilinear"
+    tables: "KernelTables | None" = None   # depth / angle tables of Eq. 2-3 (None: the analytic form)
 
     @property
     def n_terms(self):
-        return len(self.weight)
+        return len(self.weight) if self.tables is None else int(np.shape(self.tables.c1)[0])
+
+
+@dataclass
+class KernelTables:
+    """Eq. 2-3 in their general form: per-term c1(d), c2(d), c3(d) on a depth grid
+    and A(theta, d) on an (angle, depth) grid (theta in radians)."""
+    c1: np.ndarray                 # float32 [n_terms][n_depth]
+    c2: np.ndarray
+    c3: np.ndarray
+    depth_step: float
+    A: np.ndarray                  # float32 [n_theta][n_adepth]
+    theta_step: float
+    adepth_step: float
 
 
 @dataclass
@@ -127,6 +141,46 @@ def default_kernel(seed: int, cutoff: float = 3.0, **kw) -> KernelParams:
         width_scale=[1.0, 1.0],
         pdd=pdd_table(seed), pdd_step=0.1,
         cutoff_u=cutoff, cutoff_v=cutoff, **kw)
+
+
+def analytic_tables(kernel: KernelParams, depth_step: float | None = None, n_theta: int = 1,
+                    theta_step: float = 0.05) -> KernelTables:
+    """A kernel's analytic form written as tables: c1, c2 constant, c3 = sigma0 +
+    slope d sampled at the nodes, A(theta, d) = the depth-dose table for every
+    theta (nodes on the depth dose's own grid unless depth_step is given)."""
+    step = kernel.pdd_step if depth_step is None else depth_step
+    n_depth = int(round((len(kernel.pdd) - 1) * kernel.pdd_step / step)) + 1
+    d = np.arange(n_depth) * step
+    K = kernel.n_terms
+    c1 = np.repeat(np.asarray(kernel.weight, dtype=np.float64)[:, None], n_depth, axis=1)
+    c2 = np.repeat(np.asarray(kernel.width_scale, dtype=np.float64)[:, None], n_depth, axis=1)
+    c3 = np.asarray(kernel.sigma0)[:, None] + np.asarray(kernel.sigma_slope)[:, None] * d[None, :]
+    A = np.repeat(np.asarray(kernel.pdd, dtype=np.float32)[None, :], n_theta, axis=0)
+    f32 = lambda x: np.ascontiguousarray(x, dtype=np.float32).reshape(K, n_depth)
+    return KernelTables(f32(c1), f32(c2), f32(c3), step, A, theta_step, kernel.pdd_step)
+
+
+def synthetic_tables(seed: int, kernel: KernelParams, n_terms: int = 3, depth_step: float = 0.5,
+                     d_end: float = 40.0, n_theta: int = 9, theta_step: float = 0.025) -> KernelTables:
+    """A three-term kernel in the paper's general form (Eq. 3 with depth-dependent
+    c1, c2, c3 and an off-axis A(theta, d)): seeded smooth curves of plausible
+    magnitude, c2 and c3 > 0.  Jiang's fitted values are not printed."""
+    rng = np.random.default_rng(seed)
+    n_depth = int(round(d_end / depth_step)) + 1
+    d = np.arange(n_depth) * depth_step
+    w = np.array([0.8, 0.15, 0.05][:n_terms])
+    c1 = w[:, None] * (1.0 + rng.uniform(-0.15, 0.15, (n_terms, 1)) * np.tanh(d[None, :] / 10.0))
+    c2 = 1.0 + rng.uniform(-0.03, 0.05, (n_terms, 1)) * d[None, :] / d_end
+    s0 = np.array([0.15, 0.4, 1.2][:n_terms])[:, None]
+    s1 = np.array([0.012, 0.03, 0.08][:n_terms])[:, None]
+    c3 = s0 + s1 * d[None, :] + rng.uniform(0.0, 1e-4, (n_terms, 1)) * d[None, :] ** 2
+    n_ad = len(kernel.pdd)
+    ad = np.arange(n_ad) * kernel.pdd_step
+    th = np.arange(n_theta) * theta_step
+    horn = 1.0 + 0.8 * th[:, None] ** 2 * np.exp(-ad[None, :] / 15.0)     # off-axis "horns", fading with depth
+    A = np.asarray(kernel.pdd, dtype=np.float64)[None, :] * horn
+    f32 = lambda x: np.ascontiguousarray(x, dtype=np.float32)
+    return KernelTables(f32(c1), f32(c2), f32(c3), depth_step, f32(A), theta_step, kernel.pdd_step)
 
 
 def coplanar_beams(n_beams, iso, sad, a, b, nu, nv, start_deg=0.0, step_deg=None):

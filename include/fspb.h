@@ -91,6 +91,31 @@ typedef struct {
     int32_t nu, nv;              /* beamlets along eu and ev, each >= 1 */
 } fspb_beam;
 
+/*
+ * Eq. 2-3 in their general form (the paper's C(d) and A(theta, d)): every
+ * term's c1, c2, c3 tabulated against depth, and A(theta, d) against theta,
+ * the angle between a beamlet's axis and its broad beam's central axis (S
+ * towards the isocentre), and depth.  Linear interpolation in each variable,
+ * held at the first and last nodes.  With these tables
+ *   D = A(theta, d) (SAD/t')^2 sum_k c1_k(d)/4 [E_u][E_v],
+ * E_u = erf((c2_k(d) a/2 - u)/(sqrt2 c3_k(d))) + erf((c2_k(d) a/2 + u)/(sqrt2 c3_k(d))),
+ * so the analytic form is the special case of constant c1, c2, c3 linear in
+ * d and A = PDD.  All arrays are HOST memory, COPIED at plan creation.
+ */
+typedef struct {
+    int32_t n_depth;             /* c nodes, >= 2, at depths k * depth_step */
+    int32_t n_theta;             /* A rows, >= 1, at angles k * theta_step */
+    int32_t n_adepth;            /* A columns, >= 2, at depths k * adepth_step */
+    int32_t reserved;            /* must be 0 */
+    double depth_step;           /* > 0 (cm) */
+    double theta_step;           /* > 0 (radians) */
+    double adepth_step;          /* > 0 (cm) */
+    const float *c1;             /* [n_terms][n_depth], finite */
+    const float *c2;             /* [n_terms][n_depth], > 0 */
+    const float *c3;             /* [n_terms][n_depth], > 0 */
+    const float *A;              /* [n_theta][n_adepth], finite */
+} fspb_kernel_tables;
+
 /* FSPB kernel parameters (Eq. 2-3) and VOI / table settings. */
 typedef struct {
     int32_t n_terms;             /* K, 1..4 (Eq. 3 uses 3) */
@@ -107,6 +132,9 @@ typedef struct {
                                     smallest voxel spacing (Sec. 3.2) */
     float rho_min;               /* voxels with density <= rho_min are in no VOI */
     uint32_t flags;              /* 0 or FSPB_DEPTH_TRILINEAR */
+    const fspb_kernel_tables *tables;   /* NULL: the analytic form above (weight, sigma0,
+                                           sigma_slope, width_scale, pdd); else these tables
+                                           replace them (pdd is still validated, unused) */
 } fspb_kernel;
 
 /*

@@ -57,6 +57,13 @@ class OBeam(C.Structure):
 DEPTH_MODES = {"siddon": 0, "trilinear": 1}
 
 
+class OTables(C.Structure):
+    _fields_ = [("n_depth", C.c_int32), ("n_theta", C.c_int32), ("n_adepth", C.c_int32), ("pad_", C.c_int32),
+                ("depth_step", C.c_double), ("theta_step", C.c_double), ("adepth_step", C.c_double),
+                ("c1", C.POINTER(C.c_float)), ("c2", C.POINTER(C.c_float)), ("c3", C.POINTER(C.c_float)),
+                ("A", C.POINTER(C.c_float))]
+
+
 class OKernel(C.Structure):
     _fields_ = [("n_terms", C.c_int32), ("n_pdd", C.c_int32),
                 ("weight", C.c_double * 4), ("sigma0", C.c_double * 4),
@@ -64,7 +71,7 @@ class OKernel(C.Structure):
                 ("pdd", C.POINTER(C.c_float)), ("pdd_step", C.c_double),
                 ("cutoff_u", C.c_double), ("cutoff_v", C.c_double),
                 ("table_step", C.c_double), ("rho_min", C.c_double),
-                ("depth_mode", C.c_int32), ("pad_", C.c_int32)]
+                ("depth_mode", C.c_int32), ("pad_", C.c_int32), ("tables", C.POINTER(OTables))]
 
 
 class OBeamlet(C.Structure):
@@ -73,7 +80,7 @@ class OBeamlet(C.Structure):
                 ("ev", C.c_double * 3), ("tA", C.c_double), ("tB", C.c_double),
                 ("step", C.c_double), ("sad", C.c_double), ("a", C.c_double), ("b", C.c_double),
                 ("cu", C.c_double), ("cv", C.c_double),
-                ("depth_mode", C.c_int32), ("pad_", C.c_int32)]
+                ("depth_mode", C.c_int32), ("pad_", C.c_int32), ("theta", C.c_double)]
 
 
 _lib = None
@@ -152,7 +159,15 @@ class OraclePlan:
         self.kernel = OKernel(kp.n_terms, len(self.pdd), pad(kp.weight), pad(kp.sigma0),
                               pad(kp.sigma_slope), pad(kp.width_scale), _ptr(self.pdd, C.c_float),
                               kp.pdd_step, kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min,
-                              DEPTH_MODES[kp.depth], 0)
+                              DEPTH_MODES[kp.depth], 0, None)
+        kt = getattr(kp, "tables", None)
+        if kt is not None:
+            self._tab_arrays = [np.ascontiguousarray(x, dtype=np.float32) for x in (kt.c1, kt.c2, kt.c3, kt.A)]
+            c1, c2, c3, A = self._tab_arrays
+            self._tables = OTables(c1.shape[1], A.shape[0], A.shape[1], 0, kt.depth_step, kt.theta_step,
+                                   kt.adepth_step, _ptr(c1, C.c_float), _ptr(c2, C.c_float),
+                                   _ptr(c3, C.c_float), _ptr(A, C.c_float))
+            self.kernel.tables = C.pointer(self._tables)
         self.n_beams = len(problem.beams)
         self.n_beamlets = lib().ofs_count_beamlets(self.beams, self.n_beams)
         self._beamlets = None

@@ -54,6 +54,18 @@ typedef struct {
     int32_t nu, nv;
 } ofs_beam;
 
+/*
+ * Eq. 2-3 in their general form: c1, c2, c3 of every term tabulated against
+ * depth, and A(theta, d) against the beamlet's angle to the broad beam's
+ * central axis and depth.  Linear interpolation, held at the last node.
+ */
+typedef struct {
+    int32_t n_depth, n_theta, n_adepth, pad_;
+    double depth_step, theta_step, adepth_step;
+    const float *c1, *c2, *c3;     /* [n_terms][n_depth] */
+    const float *A;                /* [n_theta][n_adepth] */
+} ofs_tables;
+
 typedef struct {
     int32_t n_terms, n_pdd;
     double weight[4];          /* c1 of Eq. 3 */
@@ -67,6 +79,7 @@ typedef struct {
     double rho_min;            /* voxels with density <= rho_min are not in any VOI */
     int32_t depth_mode;        /* 0: exact path integral (Siddon); 1: trilinear samples + trapezoid */
     int32_t pad_;
+    const ofs_tables *tables;  /* NULL: c1, c2 constant, c3 linear in d, A = PDD(d) */
 } ofs_kernel;
 
 /* One beamlet: pencil-beam frame of Fig. 1b plus its depth-table layout. */
@@ -80,6 +93,7 @@ typedef struct {
     double sad, a, b, cu, cv;
     int32_t depth_mode;        /* copied from the kernel: how the depth table is built */
     int32_t pad_;
+    double theta;              /* angle between this axis and the broad beam's central axis */
 } ofs_beamlet;
 
 /* ------------------------------------------------------------ small vecs */
@@ -170,6 +184,13 @@ int32_t ofs_geometry(const ofs_grid *g, const ofs_beam *beams, int32_t n_beams,
                     bl->e[k] = Q[k] - S[k];
                 }
                 normalise3(bl->e);
+                {
+                    /* Fig. 1a: theta is the angle between SS' (S towards the isocentre) and the beamlet axis */
+                    double c0[3] = { bm->iso[0] - S[0], bm->iso[1] - S[1], bm->iso[2] - S[2] };
+                    normalise3(c0);
+                    double ct = dot3(c0, bl->e);
+                    bl->theta = acos(ct > 1.0 ? 1.0 : (ct < -1.0 ? -1.0 : ct));
+                }
                 double pr = dot3(beu, bl->e);
                 for (int k = 0; k < 3; ++k) bl->eu[k] = beu[k] - pr * bl->e[k];
                 normalise3(bl->eu);
@@ -382,6 +403,36 @@ double ofs_table_depth(const ofs_beamlet *bl, const double *table, double t)
 }
 
 /* Depth dose, linear interpolation in the table, held at the last node. */
+/* Linear interpolation of a table of n nodes at x (in node units), held at both ends. */
+static double lerp_table(const float *t, int32_t n, double x)
+{
+    if (x <= 0.0) return (double)t[0];
+    if (x >= n - 1) return (double)t[n - 1];
+    int32_t k = (int32_t)floor(x);
+    double f = x - k;
+    return (1.0 - f) * (double)t[k] + f * (double)t[k + 1];
+}
+
+/* c_m(d) of term i (m = 1, 2, 3) from the tables. */
+double ofs_table_c(const ofs_tables *T, int32_t m, int32_t i, double d)
+{
+    const float *base = m == 1 ? T->c1 : (m == 2 ? T->c2 : T->c3);
+    return lerp_table(base + (int64_t)i * T->n_depth, T->n_depth, d / T->depth_step);
+}
+
+/* A(theta, d): linear in theta between rows, each row linear in d. */
+double ofs_table_A(const ofs_tables *T, double theta, double d)
+{
+    double y = T->n_theta > 1 ? theta / T->theta_step : 0.0;
+    if (y <= 0.0 || T->n_theta == 1) return lerp_table(T->A, T->n_adepth, d / T->adepth_step);
+    if (y >= T->n_theta - 1)
+        return lerp_table(T->A + (int64_t)(T->n_theta - 1) * T->n_adepth, T->n_adepth, d / T->adepth_step);
+    int32_t k = (int32_t)floor(y);
+    double f = y - k;
+    return (1.0 - f) * lerp_table(T->A + (int64_t)k * T->n_adepth, T->n_adepth, d / T->adepth_step) +
+           f * lerp_table(T->A + (int64_t)(k + 1) * T->n_adepth, T->n_adepth, d / T->adepth_step);
+}
+
 double ofs_pdd(const ofs_kernel *K, double d)
 {
     double x = d / K->pdd_step;
@@ -409,18 +460,27 @@ double ofs_lateral(const ofs_kernel *K, double u, double v, double a, double b, 
 {
     double sum = 0.0;
     for (int32_t i = 0; i < K->n_terms; ++i) {
-        double s = K->sigma0[i] + K->sigma_slope[i] * d;
-        sum += 0.25 * K->weight[i] * ofs_edge_pair(u, K->width_scale[i] * a, s)
-                                   * ofs_edge_pair(v, K->width_scale[i] * b, s);
+        double c1, c2, c3;
+        if (K->tables) {
+            c1 = ofs_table_c(K->tables, 1, i, d);
+            c2 = ofs_table_c(K->tables, 2, i, d);
+            c3 = ofs_table_c(K->tables, 3, i, d);
+        } else {
+            c1 = K->weight[i];
+            c2 = K->width_scale[i];
+            c3 = K->sigma0[i] + K->sigma_slope[i] * d;
+        }
+        sum += 0.25 * c1 * ofs_edge_pair(u, c2 * a, c3) * ofs_edge_pair(v, c2 * b, c3);
     }
     return sum;
 }
 
-/* Eq. 2 with A = PDD(d) (SAD/t')^2. */
+/* Eq. 2 with A = PDD(d) (SAD/t')^2, or A(theta, d) (SAD/t')^2 from the tables. */
 double ofs_dose(const ofs_kernel *K, const ofs_beamlet *bl, double d, double tp, double u, double v)
 {
     double m = bl->sad / tp;
-    return ofs_pdd(K, d) * m * m * ofs_lateral(K, u, v, bl->a, bl->b, d);
+    double A = K->tables ? ofs_table_A(K->tables, bl->theta, d) : ofs_pdd(K, d);
+    return A * m * m * ofs_lateral(K, u, v, bl->a, bl->b, d);
 }
 
 /* The learned surrogate's target: PDD(d) F(u, v; a, a, d). */

@@ -44,13 +44,20 @@ class FspbBeam(C.Structure):
                 ("u0", C.c_double), ("v0", C.c_double), ("nu", C.c_int32), ("nv", C.c_int32)]
 
 
+class FspbKernelTables(C.Structure):
+    _fields_ = [("n_depth", C.c_int32), ("n_theta", C.c_int32), ("n_adepth", C.c_int32), ("reserved", C.c_int32),
+                ("depth_step", C.c_double), ("theta_step", C.c_double), ("adepth_step", C.c_double),
+                ("c1", C.POINTER(C.c_float)), ("c2", C.POINTER(C.c_float)), ("c3", C.POINTER(C.c_float)),
+                ("A", C.POINTER(C.c_float))]
+
+
 class FspbKernel(C.Structure):
     _fields_ = [("n_terms", C.c_int32), ("n_pdd", C.c_int32),
                 ("weight", C.c_double * 4), ("sigma0", C.c_double * 4),
                 ("sigma_slope", C.c_double * 4), ("width_scale", C.c_double * 4),
                 ("pdd", C.POINTER(C.c_float)), ("pdd_step", C.c_double),
                 ("cutoff_u", C.c_double), ("cutoff_v", C.c_double), ("table_step", C.c_double),
-                ("rho_min", C.c_float), ("flags", C.c_uint32)]
+                ("rho_min", C.c_float), ("flags", C.c_uint32), ("tables", C.POINTER(FspbKernelTables))]
 
 
 class FspbTiming(C.Structure):

@@ -38,6 +38,8 @@ struct alignas(16) BeamletRec {
     float ha[kMaxTerms], hb[kMaxTerms];   // c2_k a/2, c2_k b/2
     float a_f;                // beamlet side a (the surrogate's fourth input)
     int32_t mlp_ok;           // square beamlet with a inside the surrogate's training box
+    int32_t theta_k;          // general kernel: A row below this beamlet's angle
+    float theta_f;            //   and the fraction towards the next row
     int32_t n_table;      // table points (0: axis misses the grid)
     int32_t table_off;    // first entry in the plan's table array
     int32_t iy0, n_iy;    // bounding rows of the VOI
@@ -64,6 +66,12 @@ struct alignas(16) PlanDev {
     float pdd_inv_step, pdd_max;   // 1/step; n_pdd - 1
     const float *pdd;
     const float4 *erf_tab;       // [kErfIntervals] (c0, c1, c2, 0) on each interval
+    // general kernel form (0: the analytic form above): c tables [3][n_terms][n_cdepth]
+    // (c1, c2, c3), A [n_theta][n_adepth]
+    int32_t gen, n_cdepth, n_theta, n_adepth;
+    float c_inv_step, c_max, a_inv_step, a_max;
+    const float *ctab;
+    const float *atab;
     // beamlets and tables
     int32_t n_beamlets, max_table;
     int32_t ray_iters;           // bound on the per-interval Siddon loop

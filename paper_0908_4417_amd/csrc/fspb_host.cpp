@@ -73,7 +73,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 /* Workspace carve: offsets of every device array. */
 struct Layout {
-    size_t plan, out, scal, rec, tile_beamlet, tile_count, row_nnz, tables, pdd, erf, bits, ext, total;
+    size_t plan, out, scal, rec, tile_beamlet, tile_count, row_nnz, tables, pdd, erf, ctab, atab, bits, ext, total;
 };
 
 }  // namespace
@@ -149,7 +149,7 @@ fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams
     if (!K) return fail(FSPB_ERR_INVALID, "kernel is NULL");
     if (K->n_terms < 1 || K->n_terms > fspb::kMaxTerms)
         return fail(FSPB_ERR_INVALID, "kernel.n_terms must be 1..4 (got %d)", K->n_terms);
-    for (int i = 0; i < K->n_terms; ++i) {
+    for (int i = 0; i < K->n_terms && !K->tables; ++i) {
         if (!finite(K->weight[i])) return fail(FSPB_ERR_INVALID, "kernel.weight[%d] is not finite", i);
         if (!(finite(K->sigma0[i]) && K->sigma0[i] > 0.0))
             return fail(FSPB_ERR_INVALID, "kernel.sigma0[%d] must be > 0", i);
@@ -167,6 +167,25 @@ fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams
         return fail(FSPB_ERR_INVALID, "kernel cutoffs and table_step must be finite");
     if (!std::isfinite(K->rho_min)) return fail(FSPB_ERR_INVALID, "kernel.rho_min must be finite");
     if (K->flags & ~FSPB_DEPTH_TRILINEAR) return fail(FSPB_ERR_INVALID, "kernel.flags has unknown bits");
+    if (const fspb_kernel_tables *T = K->tables) {
+        if (T->n_depth < 2 || T->n_adepth < 2 || T->n_theta < 1 || T->reserved != 0)
+            return fail(FSPB_ERR_INVALID, "kernel.tables: n_depth, n_adepth must be >= 2, n_theta >= 1, reserved 0");
+        if ((int64_t)T->n_depth * K->n_terms > 16384 || (int64_t)T->n_theta * T->n_adepth > (1 << 22))
+            return fail(FSPB_ERR_INVALID, "kernel.tables are too large");
+        if (!(finite(T->depth_step) && T->depth_step > 0.0 && finite(T->adepth_step) && T->adepth_step > 0.0 &&
+              finite(T->theta_step) && T->theta_step > 0.0))
+            return fail(FSPB_ERR_INVALID, "kernel.tables steps must be finite and > 0");
+        if (!T->c1 || !T->c2 || !T->c3 || !T->A) return fail(FSPB_ERR_INVALID, "kernel.tables arrays are NULL");
+        for (int64_t i = 0; i < (int64_t)K->n_terms * T->n_depth; ++i) {
+            if (!std::isfinite(T->c1[i])) return fail(FSPB_ERR_INVALID, "kernel.tables.c1[%lld] is not finite", (long long)i);
+            if (!(std::isfinite(T->c2[i]) && T->c2[i] > 0.0f))
+                return fail(FSPB_ERR_INVALID, "kernel.tables.c2[%lld] must be > 0", (long long)i);
+            if (!(std::isfinite(T->c3[i]) && T->c3[i] > 0.0f))
+                return fail(FSPB_ERR_INVALID, "kernel.tables.c3[%lld] must be > 0", (long long)i);
+        }
+        for (int64_t i = 0; i < (int64_t)T->n_theta * T->n_adepth; ++i)
+            if (!std::isfinite(T->A[i])) return fail(FSPB_ERR_INVALID, "kernel.tables.A[%lld] is not finite", (long long)i);
+    }
     return FSPB_OK;
 }
 
@@ -338,6 +357,16 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     }
     h.pdd_inv_step = (float)(1.0 / K->pdd_step);
     h.pdd_max = (float)(K->n_pdd - 1);
+    if (const fspb_kernel_tables *T = K->tables) {
+        h.gen = 1;
+        h.n_cdepth = T->n_depth;
+        h.n_theta = T->n_theta;
+        h.n_adepth = T->n_adepth;
+        h.c_inv_step = (float)(1.0 / T->depth_step);
+        h.c_max = (float)(T->n_depth - 1);
+        h.a_inv_step = (float)(1.0 / T->adepth_step);
+        h.a_max = (float)(T->n_adepth - 1);
+    }
     p->n_terms = K->n_terms;
     for (int i = 0; i < K->n_terms; ++i) {
         p->weight[i] = K->weight[i];
@@ -407,6 +436,20 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
                 R.U1_f = (float)(g->spacing[0] * eu.x);
                 R.V1_f = (float)(g->spacing[0] * ev.x);
                 R.a_f = (float)B.beamlet_a;
+                if (const fspb_kernel_tables *T = K->tables) {
+                    // Fig. 1a: theta between SS' (S towards the isocentre) and the beamlet axis
+                    const double ct = dot(unit(iso - S), e);
+                    const double theta = std::acos(std::max(-1.0, std::min(1.0, ct)));
+                    if (T->n_theta == 1) {
+                        R.theta_k = 0;
+                        R.theta_f = 0.0f;
+                    } else {
+                        const double y = std::min(theta / T->theta_step, (double)(T->n_theta - 1));
+                        const int32_t k = std::min((int32_t)std::floor(y), T->n_theta - 2);
+                        R.theta_k = k;
+                        R.theta_f = (float)(y - k);
+                    }
+                }
                 R.mlp_ok = (B.beamlet_a == B.beamlet_b && B.beamlet_a >= fspb::kMlpAMin &&
                             B.beamlet_a <= fspb::kMlpAMax) ? 1 : 0;
                 for (int i = 0; i < fspb::kMaxTerms; ++i) {
@@ -467,6 +510,10 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     L.tables = take(sizeof(float) * (size_t)std::max<int64_t>(table_off, 1));
     L.pdd = take(sizeof(float) * (size_t)K->n_pdd);
     L.erf = take(sizeof(float4) * fspb::kErfIntervals);
+    if (K->tables) {
+        L.ctab = take(sizeof(float) * 3 * (size_t)K->n_terms * K->tables->n_depth);
+        L.atab = take(sizeof(float) * (size_t)K->tables->n_theta * K->tables->n_adepth);
+    }
     L.bits = take(sizeof(uint32_t) * (size_t)grow * h.wpr);
     L.ext = take(sizeof(int2) * (size_t)grow);
     L.total = off;
@@ -501,6 +548,10 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     h.tables = reinterpret_cast<float *>(ws + L.tables);
     h.pdd = reinterpret_cast<float *>(ws + L.pdd);
     h.erf_tab = reinterpret_cast<float4 *>(ws + L.erf);
+    if (K->tables) {
+        h.ctab = reinterpret_cast<float *>(ws + L.ctab);
+        h.atab = reinterpret_cast<float *>(ws + L.atab);
+    }
     h.bits = reinterpret_cast<uint32_t *>(ws + L.bits);
     h.ext = reinterpret_cast<int2 *>(ws + L.ext);
     h.nnz = p->d_nnz;
@@ -515,6 +566,16 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
                  "upload tile map");
     FSPB_HIP(hipMemcpy((void *)h.pdd, K->pdd, sizeof(float) * (size_t)K->n_pdd, hipMemcpyHostToDevice),
              "upload depth dose");
+    if (const fspb_kernel_tables *T = K->tables) {
+        const size_t nc = (size_t)K->n_terms * T->n_depth;
+        const float *src[3] = {T->c1, T->c2, T->c3};
+        for (int m = 0; m < 3; ++m)
+            FSPB_HIP(hipMemcpy((void *)(h.ctab + m * nc), src[m], sizeof(float) * nc, hipMemcpyHostToDevice),
+                     "upload kernel tables");
+        FSPB_HIP(hipMemcpy((void *)h.atab, T->A, sizeof(float) * (size_t)T->n_theta * T->n_adepth,
+                           hipMemcpyHostToDevice),
+                 "upload A table");
+    }
     {
         std::vector<float4> et;
         erf_table(et);
@@ -820,6 +881,7 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
     if (n_plans > 4096) return fail(FSPB_ERR_INVALID, "at most 4096 plans per batch");
     for (int i = 0; i < n_plans; ++i) {
         if (!plans[i]) return fail(FSPB_ERR_INVALID, "plans[%d] is NULL", i);
+        if (plans[i]->h.gen) return fail(FSPB_ERR_INVALID, "plans[%d] uses kernel tables (not batched)", i);
         for (int k = 0; k < i; ++k)
             if (plans[k] == plans[i]) return fail(FSPB_ERR_INVALID, "plan %d appears twice", i);
     }
@@ -1312,6 +1374,8 @@ fspb_status fspb_plan_set_surrogate(fspb_plan *p, const fspb_surrogate *s)
 {
     g_last_error.clear();
     if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
+    if (s && p->h.gen)
+        return fail(FSPB_ERR_INVALID, "the surrogate models the analytic kernel; this plan uses kernel tables");
     if (s) {
         bool same = s->n_terms == p->n_terms && s->pdd_step == p->pdd_step && s->pdd == p->pdd;
         for (int i = 0; same && i < p->n_terms; ++i)

@@ -431,17 +431,20 @@ __device__ inline gptr<T> as_global(T *p)
 
 /*
  * erf(z) at the table coordinate x = (z + kErfMax) kErfScale: piecewise
- * quadratic from LDS, held at the ends of [-kErfMax, kErfMax].
+ * quadratic from LDS, held at the ends of [-kErfMax, kErfMax].  The LDS copy
+ * packs each interval's (c0, c1, c2) in 12 bytes: a 3-dword stride spreads
+ * the lanes' random intervals over the banks better than a 4-dword one.
  */
 constexpr float kErfScale = (float)kErfIntervals / (2.0f * kErfMax);
+constexpr int kErfLdsFloats = 3 * kErfIntervals;
 
-__device__ inline float erf_lds(const float4 *__restrict__ tab, float x)
+__device__ inline float erf_lds(const float *__restrict__ tab, float x)
 {
     const float xc = __builtin_amdgcn_fmed3f(x, 0.0f, (float)kErfIntervals - 1.0f / 1024.0f);
     const int k = (int)xc;
     const float f = __builtin_amdgcn_fractf(xc);
-    const float4 c = tab[k];
-    return fmaf(fmaf(c.z, f, c.y), f, c.x);
+    const float c0 = tab[3 * k], c1 = tab[3 * k + 1], c2 = tab[3 * k + 2];
+    return fmaf(fmaf(c2, f, c1), f, c0);
 }
 
 /*
@@ -449,7 +452,7 @@ __device__ inline float erf_lds(const float4 *__restrict__ tab, float x)
  * is = 1/(sqrt2 sigma): isk = is kErfScale and hko = h isk + kErfMax kErfScale
  * put both arguments in table coordinates.  The bracket is even in x.
  */
-__device__ inline float edge_pair(const float4 *__restrict__ tab, float x, float hko, float isk)
+__device__ inline float edge_pair(const float *__restrict__ tab, float x, float hko, float isk)
 {
     return erf_lds(tab, fmaf(-x, isk, hko)) + erf_lds(tab, fmaf(x, isk, hko));
 }
@@ -461,6 +464,9 @@ struct FillConst {
     int n_terms;
     float w4[K], ha[K], hb[K];
     float sig0[K], sig1[K];      // sigma law divided by kIsScale: 1/sigma' = isk
+    // general form (tables): A and c grids, beamlet half sides
+    float a_inv, a_max, c_inv, c_max, half_a, half_b;
+    int nc;
 };
 
 // is kErfScale = kIsScale / sigma
@@ -469,7 +475,7 @@ constexpr float kErfOff = kErfMax * kErfScale;
 
 template <int K, bool GUARD>
 __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restrict__ tab,
-                                   const float2 *__restrict__ pdd, const float4 *__restrict__ etab,
+                                   const float2 *__restrict__ pdd, const float *__restrict__ etab,
                                    float s, float U, float V)
 {
     const float tp = s + c.tA;                      // t' = |SO'|
@@ -496,6 +502,48 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
     return A * L;
 }
 
+/*
+ * Eq. 2-3 in their general form: A(theta_j, d) from the beamlet's LDS row
+ * (already interpolated in theta), c1, c2, c3 of each term from LDS depth
+ * tables (value, slope) laid out [c][term][node].
+ */
+template <int K>
+__device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__restrict__ tab,
+                                       const float2 *__restrict__ sA, const float2 *__restrict__ sc,
+                                       const float *__restrict__ etab, float s, float U, float V)
+{
+    const float tp = s + c.tA;
+    const float g = c.sad * __builtin_amdgcn_rcpf(tp);
+    const float u = U * g, v = V * g;
+    const float tau = __builtin_amdgcn_fmed3f(s * c.inv_step, 0.0f, c.tau_max);
+    const float2 q = tab[(int)tau];
+    const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
+    const float xa = __builtin_amdgcn_fmed3f(d * c.a_inv, 0.0f, c.a_max);
+    const float2 qa = sA[(int)xa];
+    const float A = fmaf(__builtin_amdgcn_fractf(xa), qa.y, qa.x) * g * g;
+    const float xc = __builtin_amdgcn_fmed3f(d * c.c_inv, 0.0f, c.c_max);
+    const int kc = (int)xc;
+    const float fc = __builtin_amdgcn_fractf(xc);
+    float L = 0.0f;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const float2 q1 = sc[i * c.nc + kc], q2 = sc[(K + i) * c.nc + kc], q3 = sc[(2 * K + i) * c.nc + kc];
+        const float c1 = fmaf(fc, q1.y, q1.x), c2 = fmaf(fc, q2.y, q2.x), c3 = fmaf(fc, q3.y, q3.x);
+        const float isk = kIsScale * __builtin_amdgcn_rcpf(c3);
+        const float eu = edge_pair(etab, u, fmaf(c2 * c.half_a, isk, kErfOff), isk);
+        const float ev = edge_pair(etab, v, fmaf(c2 * c.half_b, isk, kErfOff), isk);
+        L = fmaf(0.25f * c1 * eu, ev, L);
+    }
+    return A * L;
+}
+
+/* Entries of the depth-dose region of the fill's LDS: the PDD, or the general
+ * form's A row and c tables. */
+__host__ __device__ inline int lds_pdd_pairs(const PlanDev &P)
+{
+    return P.gen ? P.n_adepth + 3 * P.n_terms * P.n_cdepth : P.n_pdd;
+}
+
 __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
 /*
@@ -504,7 +552,7 @@ __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readla
  * are flattened across its rows, 64 per chunk, members compacted by ballot.
  * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K).
  */
-template <int K, int W, bool GUARD, bool SURR>
+template <int K, int W, bool GUARD, bool SURR, bool GEN = false>
 __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem)
 {
     const BeamletRec &R = P.rec[j];
@@ -514,7 +562,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = lane_id();
 
     // ---- constants into registers
-    const int n_table = R.n_table, n_pdd = P.n_pdd, tile0 = R.tile0;
+    const int n_table = R.n_table, n_pdd = lds_pdd_pairs(P), tile0 = R.tile0;
     const int iy0 = R.iy0, n_iy = R.n_iy, iz0 = R.iz0, n_rows = R.n_iy * R.n_iz;
     const int nx = P.nx, ny = P.ny, wpr = P.wpr;
     FillConst<K> c;
@@ -533,6 +581,15 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         c.ha[i] = R.ha[i];
         c.hb[i] = R.hb[i];
     }
+    if (GEN) {
+        c.a_inv = P.a_inv_step;
+        c.a_max = P.a_max;
+        c.c_inv = P.c_inv_step;
+        c.c_max = P.c_max;
+        c.half_a = R.half_a;
+        c.half_b = R.half_b;
+        c.nc = P.n_cdepth;
+    }
     const double tA = R.tA;
     const double t1 = P.sp[0] * R.e[0], u1 = P.sp[0] * R.eu[0], v1 = P.sp[0] * R.ev[0];
     const float t1f = R.t1_f, U1f = R.U1_f, V1f = R.V1_f;
@@ -544,14 +601,14 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const int64_t row_base = uniform64(O.indptr[j] - O.indptr[O.row0]);
 
     // ---- LDS: erf table, depth table, depth dose, tile prefix
-    float4 *s_erf = reinterpret_cast<float4 *>(smem);
-    float2 *s_tab = reinterpret_cast<float2 *>(s_erf + kErfIntervals);
+    float *s_erf = reinterpret_cast<float *>(smem);
+    float2 *s_tab = reinterpret_cast<float2 *>(s_erf + kErfLdsFloats);
     float2 *s_pdd = s_tab + P.max_table;
     int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
     __shared__ int wsum[W];
     // surrogate: per-wave h1 tile after the tile prefix, and W2 fragments in registers
     uint16_t *s_h1 = reinterpret_cast<uint16_t *>(
-        smem + ((sizeof(float4) * kErfIntervals + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
+        smem + ((sizeof(float) * kErfLdsFloats + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
                  sizeof(int) * ((size_t)P.max_tiles + 1) + 15) & ~(size_t)15)) + wave * (64 * mlp::kH1Stride);
     mlp::W2Frags wf;
     if (SURR) mlp::load_w2_frags(P.mlp_w2, wf);
@@ -560,16 +617,41 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
 
     {
         const float4 *et = P.erf_tab;
-        for (int i = tid; i < kErfIntervals; i += kB) s_erf[i] = et[i];
+        for (int i = tid; i < kErfIntervals; i += kB) {
+            const float4 q = et[i];
+            s_erf[3 * i] = q.x;
+            s_erf[3 * i + 1] = q.y;
+            s_erf[3 * i + 2] = q.z;
+        }
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
         for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
             s_tab[i] = make_float2(d0, (i + 1 < n_table ? tab[i + 1] : d0) - d0);
         }
-        const gptr<const float> pd = as_global<const float>(P.pdd);
-        for (int i = tid; i < n_pdd; i += kB) {
-            const float p0 = pd[i];
-            s_pdd[i] = make_float2(p0, (i + 1 < n_pdd ? pd[i + 1] : p0) - p0);
+        if (GEN) {
+            // this beamlet's A row (interpolated in theta), then the c tables
+            const int na = P.n_adepth, k0 = R.theta_k, k1 = min(R.theta_k + 1, P.n_theta - 1);
+            const float ft = R.theta_f;
+            const gptr<const float> a0 = as_global<const float>(P.atab + (size_t)k0 * na);
+            const gptr<const float> a1 = as_global<const float>(P.atab + (size_t)k1 * na);
+            for (int i = tid; i < na; i += kB) {
+                const float v0 = fmaf(ft, a1[i] - a0[i], a0[i]);
+                const float v1 = i + 1 < na ? fmaf(ft, a1[i + 1] - a0[i + 1], a0[i + 1]) : v0;
+                s_pdd[i] = make_float2(v0, v1 - v0);
+            }
+            const int nc = P.n_cdepth, ntab = 3 * P.n_terms * nc;
+            const gptr<const float> ct = as_global<const float>(P.ctab);
+            for (int i = tid; i < ntab; i += kB) {
+                const int node = i % nc;
+                const float v0 = ct[i];
+                s_pdd[na + i] = make_float2(v0, (node + 1 < nc ? ct[i + 1] : v0) - v0);
+            }
+        } else {
+            const gptr<const float> pd = as_global<const float>(P.pdd);
+            for (int i = tid; i < n_pdd; i += kB) {
+                const float p0 = pd[i];
+                s_pdd[i] = make_float2(p0, (i + 1 < n_pdd ? pd[i + 1] : p0) - p0);
+            }
         }
     }
     // exclusive scan of this beamlet's tile counts
@@ -666,7 +748,10 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             }
             if (member) {
                 const float kf = (float)k;
-                if (!SURR)
+                if (GEN)
+                    D = dose_value_gen<K>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                                          fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
+                else if (!SURR)
                     D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
                                              fmaf(kf, V1f, vl));
                 if (slot < avail) {
@@ -681,12 +766,12 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     }
 }
 
-template <int K, bool SURR>
+template <int K, bool SURR, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    fill_beamlet<K, kWavesPerBlock, false, SURR>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
+    fill_beamlet<K, kWavesPerBlock, false, SURR, GEN>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
 }
 
 /* ------------------------------------------------------------ batches */
@@ -798,7 +883,7 @@ hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const Pl
 
 size_t fill_shared_bytes(const PlanDev &h)
 {
-    size_t b = sizeof(float4) * kErfIntervals + sizeof(float2) * ((size_t)h.max_table + (size_t)h.n_pdd) +
+    size_t b = sizeof(float) * kErfLdsFloats + sizeof(float2) * ((size_t)h.max_table + (size_t)lds_pdd_pairs(h)) +
                sizeof(int) * ((size_t)h.max_tiles + 1);
     if (h.use_mlp) b = ((b + 15) & ~(size_t)15) + sizeof(uint16_t) * 64 * mlp::kH1Stride * kWavesPerBlock;
     return b;
@@ -860,19 +945,26 @@ hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &
     if (n_rows <= 0) return hipSuccess;
     const dim3 grid(n_rows), block(kBlock);
     const size_t lds = fill_shared_bytes(h);
-    if (h.use_mlp) {
+    if (h.gen) {
         switch (h.n_terms) {
-        case 1: hipLaunchKernelGGL((k_fill<1, true>), grid, block, lds, s, dplan, dout); break;
-        case 2: hipLaunchKernelGGL((k_fill<2, true>), grid, block, lds, s, dplan, dout); break;
-        case 3: hipLaunchKernelGGL((k_fill<3, true>), grid, block, lds, s, dplan, dout); break;
-        default: hipLaunchKernelGGL((k_fill<4, true>), grid, block, lds, s, dplan, dout); break;
+        case 1: hipLaunchKernelGGL((k_fill<1, false, true>), grid, block, lds, s, dplan, dout); break;
+        case 2: hipLaunchKernelGGL((k_fill<2, false, true>), grid, block, lds, s, dplan, dout); break;
+        case 3: hipLaunchKernelGGL((k_fill<3, false, true>), grid, block, lds, s, dplan, dout); break;
+        default: hipLaunchKernelGGL((k_fill<4, false, true>), grid, block, lds, s, dplan, dout); break;
+        }
+    } else if (h.use_mlp) {
+        switch (h.n_terms) {
+        case 1: hipLaunchKernelGGL((k_fill<1, true, false>), grid, block, lds, s, dplan, dout); break;
+        case 2: hipLaunchKernelGGL((k_fill<2, true, false>), grid, block, lds, s, dplan, dout); break;
+        case 3: hipLaunchKernelGGL((k_fill<3, true, false>), grid, block, lds, s, dplan, dout); break;
+        default: hipLaunchKernelGGL((k_fill<4, true, false>), grid, block, lds, s, dplan, dout); break;
         }
     } else {
         switch (h.n_terms) {
-        case 1: hipLaunchKernelGGL((k_fill<1, false>), grid, block, lds, s, dplan, dout); break;
-        case 2: hipLaunchKernelGGL((k_fill<2, false>), grid, block, lds, s, dplan, dout); break;
-        case 3: hipLaunchKernelGGL((k_fill<3, false>), grid, block, lds, s, dplan, dout); break;
-        default: hipLaunchKernelGGL((k_fill<4, false>), grid, block, lds, s, dplan, dout); break;
+        case 1: hipLaunchKernelGGL((k_fill<1, false, false>), grid, block, lds, s, dplan, dout); break;
+        case 2: hipLaunchKernelGGL((k_fill<2, false, false>), grid, block, lds, s, dplan, dout); break;
+        case 3: hipLaunchKernelGGL((k_fill<3, false, false>), grid, block, lds, s, dplan, dout); break;
+        default: hipLaunchKernelGGL((k_fill<4, false, false>), grid, block, lds, s, dplan, dout); break;
         }
     }
     return hipGetLastError();

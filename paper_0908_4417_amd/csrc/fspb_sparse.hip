@@ -100,7 +100,22 @@ __global__ __launch_bounds__(kBlock) void k_fluence_dose(const int64_t *__restri
     if (j >= n_rows) return;
     const float wj = w[j];
     if (wj == 0.0f) return;
-    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave) {
+    const int64_t e1 = indptr[j + 1];
+    int64_t e = indptr[j] + lane_id();
+    // four entries per lane in flight, then the tail
+    for (; e + 3 * kWave < e1; e += 4 * kWave) {
+        uint32_t i[4];
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            i[k] = (uint32_t)indices[e + k * kWave];
+            v[k] = values[e + k * kWave];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i[k] < (uint32_t)n_voxels) atomicAdd(dose + i[k], wj * v[k]);
+    }
+    for (; e < e1; e += kWave) {
         const uint32_t i = (uint32_t)indices[e];
         if (i < (uint32_t)n_voxels) atomicAdd(dose + i, wj * values[e]);
     }
@@ -116,11 +131,23 @@ __global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__re
 {
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
-    float s = 0.0f;
-    for (int64_t e = indptr[j] + lane_id(); e < indptr[j + 1]; e += kWave) {
-        const uint32_t i = (uint32_t)indices[e];
-        if (i < (uint32_t)n_voxels) s = fmaf(values[e], r[i], s);
+    const int64_t e1 = indptr[j + 1];
+    int64_t e = indptr[j] + lane_id();
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // four independent partial sums per lane (entries e + k * 64), then the tail into the first
+    for (; e + 3 * kWave < e1; e += 4 * kWave) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = (uint32_t)indices[e + k * kWave];
+            const float v = values[e + k * kWave];
+            if (i < (uint32_t)n_voxels) acc[k] = fmaf(v, r[i], acc[k]);
+        }
     }
+    for (; e < e1; e += kWave) {
+        const uint32_t i = (uint32_t)indices[e];
+        if (i < (uint32_t)n_voxels) acc[0] = fmaf(values[e], r[i], acc[0]);
+    }
+    float s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     s = wave_sum(s);
     if (lane_id() == 0) g[j] = s;
 }
@@ -135,14 +162,25 @@ __global__ __launch_bounds__(kBlock) void k_voxel_dose(const int64_t *__restrict
 {
     const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 4;
     const int l = threadIdx.x & 15;
-    float s = 0.0f;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (i < n_voxels) {
         const int64_t e1 = t_indptr[i + 1];
-        for (int64_t e = t_indptr[i] + l; e < e1; e += 16) {
+        int64_t e = t_indptr[i] + l;
+        // four independent partial sums per lane (entries e + 16 k), then the tail into the first
+        for (; e + 48 < e1; e += 64) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t j = (uint32_t)t_indices[e + 16 * k];
+                const float v = t_values[e + 16 * k];
+                if (j < (uint32_t)n_w) acc[k] = fmaf(v, w[j], acc[k]);
+            }
+        }
+        for (; e < e1; e += 16) {
             const uint32_t j = (uint32_t)t_indices[e];
-            if (j < (uint32_t)n_w) s = fmaf(t_values[e], w[j], s);
+            if (j < (uint32_t)n_w) acc[0] = fmaf(t_values[e], w[j], acc[0]);
         }
     }
+    float s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
     for (int d = 8; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
     if (l == 0 && i < n_voxels) dose[i] = s;

@@ -99,6 +99,15 @@ def _structs(problem, density_ptr):
                         pad(kp.width_scale), pdd.ctypes.data_as(C.POINTER(C.c_float)), kp.pdd_step,
                         kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min,
                         L.FSPB_DEPTH_TRILINEAR if kp.depth == "trilinear" else 0)
+    kt = getattr(kp, "tables", None)
+    if kt is not None:
+        arrs = [np.ascontiguousarray(x, dtype=np.float32) for x in (kt.c1, kt.c2, kt.c3, kt.A)]
+        f = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
+        tabs = L.FspbKernelTables(arrs[0].shape[1], arrs[3].shape[0], arrs[3].shape[1], 0, kt.depth_step,
+                                  kt.theta_step, kt.adepth_step, f(arrs[0]), f(arrs[1]), f(arrs[2]), f(arrs[3]))
+        tabs._keep = arrs                      # the host arrays must outlive the create call
+        kern.tables = C.pointer(tabs)
+        kern._keep = tabs
     return grid, beams, kern, pdd
 
 
