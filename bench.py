@@ -47,6 +47,8 @@ def parse():
                     help="target duration of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eq1", action="store_true", help="skip the Eq. 1 (dose, gradient, transpose) timings")
+    ap.add_argument("--table1", action="store_true",
+                    help="the paper's water-phantom study (Table 1, cases 1-7): one JSON line, context only")
     ap.add_argument("--surrogate-epochs", type=int, default=None,
                     help="training epochs of the kernel surrogate compared with the analytic "
                          "fill on the pelvis workload (0 skips it; default: 800 beside the default workload)")
@@ -201,6 +203,41 @@ def eq1_timings(indptr, indices, values, n_voxels, n_beamlets, reps=5):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
 
+# Table 1 of the paper (Tesla C1060, single precision): N'_voxel and T_GPU in seconds, context only
+PAPER_TABLE1 = {1: (0.864e7, 0.06), 2: (1.80e7, 0.10), 3: (3.23e7, 0.18), 4: (5.27e7, 0.30),
+                5: (4.97e7, 0.29), 6: (4.70e7, 0.27), 7: (4.39e7, 0.24)}
+
+
+def bench_table1(args):
+    """The seven water-phantom cases of Table 1 (30 cm cube, 5 beams, 10 x 10 cm field):
+    coefficients and device time per plan on this GPU beside the paper's figures."""
+    import torch
+    import fspb_inputs as fi
+    import paper_0908_4417_amd as m
+    from paper_0908_4417_amd import Plan
+    rows = []
+    for case in range(1, 8):
+        plan = Plan(fi.table1_case(case), "cuda:0")
+        m.fspb_plan_set_timing(plan.handle, 1)
+        times, walls = [], []
+        for _ in range(max(args.steps, 3)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            csr = plan.compute()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            t = m.fspb_plan_get_timing(plan.handle)
+            times.append(t.prep_ms + t.raytrace_ms + t.count_ms + t.scan_ms + t.fill_ms)
+        n_ref, t_ref = PAPER_TABLE1[case]
+        rows.append({"case": case, "nnz": csr.nnz, "paper_nnz": n_ref, "device_ms": round(min(times[1:]), 4),
+                     "wall_ms": round(1e3 * min(walls[1:]), 4), "paper_gpu_ms": 1e3 * t_ref,
+                     "nnz_per_s": round(csr.nnz / (min(times[1:]) * 1e-3), 1)})
+        del csr, plan
+    print(json.dumps({"metric": "Table 1 water phantom: coefficients and device time per plan",
+                      "data": "synthetic", "context": "paper: Tesla C1060, single precision", "cases": rows}),
+          flush=True)
+
+
 def bench_batch(args):
     """32 plans of uneven size, computed by one graph launch per step."""
     import torch
@@ -255,6 +292,9 @@ def main():
         sys.exit(2)
     if args.workload == 3:
         bench_batch(args)
+        return
+    if args.table1:
+        bench_table1(args)
         return
     import torch
     import fspb_inputs as fi

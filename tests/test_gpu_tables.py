@@ -82,3 +82,50 @@ def test_tables_refused_by_batch_and_surrogate(torch_gpu):
     sur = Surrogate(k, fi.surrogate_init(1), max_batch=1024)
     with pytest.raises(m.FspbError, match="tables"):
         plan.set_surrogate(sur)
+
+
+@pytest.mark.parametrize("n_terms,n_theta,n_depth", [(1, 1, 2), (4, 3, 17)])
+def test_tabulated_kernel_shapes(torch_gpu, oracle_lib, n_terms, n_theta, n_depth):
+    """One and four terms, a single A row, the shortest c table."""
+    from paper_0908_4417_amd import Plan
+    k = fi.default_kernel(74)
+    rng = np.random.default_rng(n_terms)
+    d_end = 30.0
+    step = d_end / (n_depth - 1)
+    d = np.arange(n_depth) * step
+    c1 = (rng.uniform(0.2, 1.0, (n_terms, 1)) * (1.0 + 0.01 * d[None, :])).astype(np.float32)
+    c2 = np.full((n_terms, n_depth), 1.0, dtype=np.float32) + rng.uniform(0, 0.1, (n_terms, 1)).astype(np.float32)
+    c3 = (rng.uniform(0.15, 1.0, (n_terms, 1)) + 0.02 * d[None, :]).astype(np.float32)
+    A = np.repeat(np.asarray(k.pdd, dtype=np.float32)[None, :], n_theta, axis=0) * \
+        np.linspace(1.0, 1.1, n_theta, dtype=np.float32)[:, None]
+    tabs = fi.KernelTables(c1, c2, c3, step, A, 0.02, k.pdd_step)
+    kt = dataclasses.replace(k, weight=[0.0] * n_terms, sigma0=[1.0] * n_terms, sigma_slope=[0.0] * n_terms,
+                             width_scale=[1.0] * n_terms, tables=tabs)
+    g = fi.slab_phantom(75, n=(31, 27, 19), spacing=(0.5, 0.5, 0.5), lung_side=(2, 5), bone_side=(1, 2))
+    prob = fi.Problem("shapes", g, fi.coplanar_beams(2, (0.1, -0.05, 0.07), 100.0, 0.8, 0.6, 6, 4), kt)
+    plan = Plan(prob, "cuda:0")
+    csr = plan.compute()
+    ora = oracle_lib.OraclePlan(prob)
+    off, oidx, oval = ora.full()
+    rows = list(range(ora.n_beamlets))
+    r = compare_rows(ora, rows, gpu_rows_from_csr(csr, rows),
+                     [(oidx[off[j]:off[j + 1]], oval[off[j]:off[j + 1]]) for j in rows])
+    print(f"\n  K={n_terms} n_theta={n_theta} n_depth={n_depth}: nnz={csr.nnz} max_rel={r['max_rel']:.2e}",
+          flush=True)
+
+
+def test_tables_rejected_when_invalid(torch_gpu):
+    import paper_0908_4417_amd as m
+    from paper_0908_4417_amd import Plan
+    k = fi.default_kernel(76)
+    base = fi.analytic_tables(k)
+    g = fi.water_phantom((12, 10, 8), (0.5, 0.5, 0.5))
+    beams = fi.coplanar_beams(1, (0, 0, 0), 100.0, 1.0, 1.0, 2, 2)
+    bad_c3 = base.c3.copy()
+    bad_c3[1, 5] = 0.0
+    for tabs, msg in [(dataclasses.replace(base, c3=bad_c3), "c3"),
+                      (dataclasses.replace(base, depth_step=0.0), "steps"),
+                      (dataclasses.replace(base, c1=base.c1[:, :1], c2=base.c2[:, :1], c3=base.c3[:, :1]),
+                       "n_depth")]:
+        with pytest.raises(m.FspbError, match=msg):
+            Plan(fi.Problem("bad", g, beams, dataclasses.replace(k, tables=tabs)), "cuda:0")

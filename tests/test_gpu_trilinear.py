@@ -80,3 +80,26 @@ def test_element_length_study(torch_gpu):
     # the table converges as the element shrinks (sharp bone / lung edges make the coarse
     # element visible here, unlike the paper's prostate case)
     assert changes[0] > changes[1] > changes[2] > 0.0
+
+
+def test_trilinear_on_thin_grids(torch_gpu, oracle_lib):
+    """Grids one voxel thick along an axis (the sampler holds that coordinate)."""
+    from paper_0908_4417_amd import Plan
+    for n in [(30, 26, 1), (1, 24, 20), (28, 1, 18)]:
+        g = fi.slab_phantom(52, n=n, spacing=(0.5, 0.5, 0.5), lung_side=(1, 3), bone_side=(1, 2))
+        k = fi.default_kernel(52)
+        k.depth = "trilinear"
+        prob = fi.Problem("thin", g, fi.coplanar_beams(3, (0.07, 0.03, 0.0), 100.0, 0.5, 0.5, 4, 1,
+                                                       start_deg=20.0), k)
+        plan = Plan(prob, "cuda:0")
+        csr = plan.compute()
+        tab, off = plan.tables()
+        ora = oracle_lib.OraclePlan(prob)
+        otab, ooff = ora.tables()
+        np.testing.assert_array_equal(off, ooff)
+        assert np.abs(tab.astype(np.float64) - otab).max() <= 1e-5
+        offs, oidx, oval = ora.full()
+        rows = list(range(ora.n_beamlets))
+        r = compare_rows(ora, rows, gpu_rows_from_csr(csr, rows),
+                         [(oidx[offs[j]:offs[j + 1]], oval[offs[j]:offs[j + 1]]) for j in rows])
+        print(f"\n  grid {n}: nnz={csr.nnz} max_rel={r['max_rel']:.2e}", flush=True)
