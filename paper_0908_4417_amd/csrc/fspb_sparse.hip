@@ -307,18 +307,20 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *__restrict__
 }
 
 /*
- * Radix pass, phase 2: stable scatter.  A tile is read in kSortItems rounds of
- * kBlock consecutive entries; in a round, entry order is thread order.  Each
- * wave groups its lanes by digit with 8 ballots (the lanes holding the same
- * digit), ranks a lane among its lower peers, and the waves' per-digit counts
- * in LDS place the groups of lower waves first.  The tile is first sorted by
- * digit in LDS, then written out in that order, so each digit's run of the
- * tile goes to consecutive addresses.  keys_out may be NULL (last pass).
+ * Radix pass, phase 2: stable scatter.  Wave w of a block owns the w-th
+ * quarter of the tile (kSortItems rounds of 64 consecutive entries) and
+ * ranks it on its own: in a round, ballots on the 8 digit bits group the
+ * lanes holding the same digit, a lane's rank is the number of lower peers,
+ * and the wave's per-digit counter in LDS (read by the group, advanced by its
+ * lowest lane) orders the rounds.  The entries stay in registers; one block
+ * scan turns the waves' counts into tile-local slots (digit-major, lower
+ * waves first), the tile is sorted by digit in LDS and written out in that
+ * order, so each digit's run goes to consecutive addresses.  keys_out may be
+ * NULL (last pass).
  */
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
                                                        const int32_t *__restrict__ rows_in,
                                                        const float *__restrict__ vals_in, int64_t n, int shift,
-                                                       const uint32_t *__restrict__ hist,
                                                        const uint32_t *__restrict__ offs, int n_tiles,
                                                        uint32_t *__restrict__ keys_out,
                                                        int32_t *__restrict__ rows_out,
@@ -327,29 +329,28 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
     __shared__ uint32_t s_key[kSortTile];
     __shared__ int32_t s_row[kSortTile];
     __shared__ float s_val[kSortTile];
-    __shared__ uint32_t run[kRadix];        // next tile-local slot of each digit
-    __shared__ uint32_t goff[kRadix];       // global slot of tile-local slot 0 of each digit's run
-    __shared__ uint32_t wc[kWavesPerBlock][kRadix];
+    __shared__ uint32_t cnt[kWavesPerBlock][kRadix];   // per wave: digit counts, then first tile-local slot
+    __shared__ uint32_t goff[kRadix];                  // global slot of tile-local slot 0 of each digit's run
     __shared__ uint32_t s_w[kWavesPerBlock];
-    const int t = threadIdx.x, wave = t >> 6;
+    constexpr int kSub = kSortTile / kWavesPerBlock;    // entries per wave
+    const int t = threadIdx.x, wave = t >> 6, lane = t & (kWave - 1);
     const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
-    {
-        const int64_t hidx = (int64_t)t * n_tiles + blockIdx.x;
-        uint32_t total;
-        const uint32_t start = block_excl_scan(hist[hidx], s_w, &total);
-        run[t] = start;
-        goff[t] = offs[hidx] - start;
-    }
+    const int64_t sub0 = tile0 + (int64_t)wave * kSub;
 #pragma unroll
-    for (int w = 0; w < kWavesPerBlock; ++w) wc[w][t] = 0u;
+    for (int w = 0; w < kWavesPerBlock; ++w) cnt[w][t] = 0u;
     __syncthreads();
+
+    uint32_t key[kSortItems], pos[kSortItems];
+    int32_t row[kSortItems];
+    float val[kSortItems];
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        const int64_t i = tile0 + (int64_t)r * kBlock + t;
+        const int64_t i = sub0 + (int64_t)r * kWave + lane;
         const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
-        const int32_t row = valid ? rows_in[i] : 0;
-        const float val = valid ? vals_in[i] : 0.0f;
-        const uint32_t d = (key >> shift) & (kRadix - 1);
+        key[r] = valid ? keys_in[i] : 0u;
+        row[r] = valid ? rows_in[i] : 0;
+        val[r] = valid ? vals_in[i] : 0.0f;
+        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -358,34 +359,50 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = (uint32_t)mbcnt64(peers);
-        if (valid && rank == 0) wc[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t lp = run[d] + rank;
-#pragma unroll
-            for (int w = 0; w < kWavesPerBlock; ++w) lp += w < wave ? wc[w][d] : 0u;
-            s_key[lp] = key;
-            s_row[lp] = row;
-            s_val[lp] = val;
-        }
-        __syncthreads();
-        uint32_t tot = 0;
+        uint32_t before = 0u;
+        if (valid) before = cnt[wave][d];                 // every lane of the group reads the old count
+        if (valid && rank == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
+        pos[r] = before + rank;
+    }
+    __syncthreads();
+    {
+        // thread t = digit t: tile-local start of the digit, then of each wave's part of it
+        uint32_t c[kWavesPerBlock], tot = 0;
 #pragma unroll
         for (int w = 0; w < kWavesPerBlock; ++w) {
-            tot += wc[w][t];
-            wc[w][t] = 0u;
+            c[w] = cnt[w][t];
+            tot += c[w];
         }
-        run[t] += tot;
-        __syncthreads();
+        uint32_t total;
+        const uint32_t start = block_excl_scan(tot, s_w, &total);
+        uint32_t b = start;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            cnt[w][t] = b;
+            b += c[w];
+        }
+        goff[t] = offs[(int64_t)t * n_tiles + blockIdx.x] - start;
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = sub0 + (int64_t)r * kWave + lane;
+        if (i < n) {
+            const uint32_t lp = cnt[wave][(key[r] >> shift) & (kRadix - 1)] + pos[r];
+            s_key[lp] = key[r];
+            s_row[lp] = row[r];
+            s_val[lp] = val[r];
+        }
+    }
+    __syncthreads();
     const int64_t rem = n - tile0;
     const int m = rem < kSortTile ? (int)rem : kSortTile;
     for (int lp = t; lp < m; lp += kBlock) {
-        const uint32_t key = s_key[lp];
-        const uint32_t pos = goff[(key >> shift) & (kRadix - 1)] + (uint32_t)lp;
-        if (keys_out) keys_out[pos] = key;
-        rows_out[pos] = s_row[lp];
-        vals_out[pos] = s_val[lp];
+        const uint32_t key_ = s_key[lp];
+        const uint32_t p = goff[(key_ >> shift) & (kRadix - 1)] + (uint32_t)lp;
+        if (keys_out) keys_out[p] = key_;
+        rows_out[p] = s_row[lp];
+        vals_out[p] = s_val[lp];
     }
 }
 
@@ -525,8 +542,8 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
         hipLaunchKernelGGL(k_rs_hist, dim3(n_tiles), dim3(kBlock), 0, s, kin, nnz, shift, hist, n_tiles);
         if ((e = scan_excl<uint32_t>(hist, (int64_t)kRadix * n_tiles, partial, offs, nullptr, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_rs_scatter, dim3(n_tiles), dim3(kBlock), 0, s, kin, rin, vin, nnz, shift, hist, offs,
-                           n_tiles, kout, rout, vout);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(n_tiles), dim3(kBlock), 0, s, kin, rin, vin, nnz, shift, offs, n_tiles,
+                           kout, rout, vout);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         kin = kout;
         rin = rout;
