@@ -286,9 +286,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the dose-coefficient path "
-              f"shards by beamlet rows across GPUs but this build measures a single MI355X.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the rows of D would shard by "
+              f"beamlet across GPUs, but only the single-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
     if args.workload == 3:
         bench_batch(args)

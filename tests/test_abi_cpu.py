@@ -200,3 +200,11 @@ def test_every_entry_point_has_a_binding(fspb):
     """Each exported C function is reachable from the package (wrapper or raw)."""
     missing = [n for n in fspb.EXPORTED if not hasattr(fspb, n)]
     assert not missing, missing
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "4"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
