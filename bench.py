@@ -346,7 +346,7 @@ def main():
     # per-kernel device times (HIP events on the launch stream), separate pass
     times = [step(True) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    kt = {k: float(np.mean([getattr(t, k) for t in times]))
+    kt = {k: float(np.median([getattr(t, k) for t in times]))
           for k in ("prep_ms", "raytrace_ms", "count_ms", "scan_ms", "fill_ms")}
     fill_s = kt["fill_ms"] * 1e-3
     alg_bytes = 8.0 * nnz                     # FP32 value + int32 column per nonzero
@@ -374,7 +374,9 @@ def main():
                    "beamlets": desc.n_beamlets, "nnz": nnz},
         "roofline": roofline,
         "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
+        # device time of fspb_raytrace + fspb_dose_coeffs (per-kernel medians), as the paper's T_GPU
         "device_ms_per_plan": round(sum(kt.values()), 4),
+        "device_nnz_per_s": round(nnz / (sum(kt.values()) * 1e-3), 1),
     }
     if not args.no_eq1:
         out["eq1"] = eq1_timings(indptr, indices, values, int(np.prod(prob.grid.shape_xyz)), desc.n_beamlets)
