@@ -47,6 +47,8 @@ def parse():
                     help="target duration of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eq1", action="store_true", help="skip the Eq. 1 (dose, gradient, transpose) timings")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the trilinear-table, tabulated-kernel and chunked-computation timings")
     ap.add_argument("--table1", action="store_true",
                     help="the paper's water-phantom study (Table 1, cases 1-7): one JSON line, context only")
     ap.add_argument("--surrogate-epochs", type=int, default=None,
@@ -201,6 +203,70 @@ def eq1_timings(indptr, indices, values, n_voxels, n_beamlets, reps=5):
         out[k + "_GBps"] = round(8.0 * nnz / (out[k + "_ms"] * 1e-3) / 1e9, 1)
     del t
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+
+
+def next_rows_timings(prob, reps=5):
+    """Device times of the rows beyond the plain path on the same workload.
+
+    trilinear: the paper's trilinear-sampled depth table (raytrace and fill);
+    tables: the general form of Eq. 2-3 (three terms, depth-tabulated c and A(theta, d));
+    chunks: D computed beam by beam under a one-beam memory budget (wall clock,
+    including the one count pass), against one-shot computation.
+    """
+    import dataclasses
+    import torch
+    import fspb_inputs as fi
+    import paper_0908_4417_amd as m
+    from paper_0908_4417_amd import Plan
+
+    def timed_plan(problem):
+        plan = Plan(problem, "cuda:0")
+        m.fspb_plan_set_timing(plan.handle, 1)
+        ts = []
+        for _ in range(reps + 1):
+            csr = plan.compute()
+            ts.append(m.fspb_plan_get_timing(plan.handle))
+        torch.cuda.synchronize()
+        med = lambda k: float(np.median([getattr(t, k) for t in ts[1:]]))
+        out = {"nnz": csr.nnz, "raytrace_ms": round(med("raytrace_ms"), 4), "fill_ms": round(med("fill_ms"), 4),
+               "device_ms": round(sum(med(k) for k in ("prep_ms", "raytrace_ms", "count_ms", "scan_ms", "fill_ms")), 4)}
+        del csr, plan
+        torch.cuda.empty_cache()
+        return out
+
+    k = prob.kernel
+    res = {"trilinear": timed_plan(dataclasses.replace(prob, kernel=dataclasses.replace(k, depth="trilinear")))}
+    kt = dataclasses.replace(k, weight=[0.0] * 3, sigma0=[1.0] * 3, sigma_slope=[0.0] * 3, width_scale=[1.0] * 3,
+                             tables=fi.synthetic_tables(71, k))
+    res["tables_3_terms"] = timed_plan(dataclasses.replace(prob, kernel=kt))
+    plan = Plan(prob, "cuda:0")
+    plan.compute()
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.compute()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    one_shot = min(walls)
+    nnz = plan.nnz
+    budget = int(8 * nnz / len(prob.beams) * 1.05)
+    walls = []
+    pieces = 0
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pieces = 0
+        for _j0, _j1, _c in plan.chunks(budget):
+            pieces += 1
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    res["chunks"] = {"budget_bytes": budget, "pieces": pieces, "wall_ms": round(1e3 * min(walls), 4),
+                     "one_shot_wall_ms": round(1e3 * one_shot, 4)}
+    del plan
+    torch.cuda.empty_cache()
+    return res
 
 
 # Table 1 of the paper (Tesla C1060, single precision): N'_voxel and T_GPU in seconds, context only
@@ -380,10 +446,13 @@ def main():
     }
     if not args.no_eq1:
         out["eq1"] = eq1_timings(indptr, indices, values, int(np.prod(prob.grid.shape_xyz)), desc.n_beamlets)
+    del indices, values, ws                         # free the workload's CSR before the side studies
+    torch.cuda.empty_cache()
+    if not args.no_next:
+        out["next_rows"] = next_rows_timings(prob)
     if args.surrogate_epochs is None:                # by default only beside the headline workload
         args.surrogate_epochs = fi.SURROGATE_EPOCHS if args.workload == 1 else 0
     if args.surrogate_epochs > 0:
-        del indices, values, ws
         out["surrogate"] = surrogate_comparison(args.surrogate_epochs)
     if not args.no_cpu_baseline and args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, desc.n_beamlets)
