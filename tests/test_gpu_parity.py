@@ -132,6 +132,32 @@ def test_full_size_workloads_sampled(torch_gpu, oracle_lib, k):
     assert csr.nnz > 1e8
 
 
+def test_more_than_2_31_nonzeros(torch_gpu, oracle_lib):
+    """One plan whose CSR has 2.9e9 entries (23 GB): 64-bit row pointers and write offsets.
+
+    200^3 voxels at 2.5 mm, 9 beams of 30 x 30 beamlets of 0.5 cm, 5 cm cutoff; rows
+    past entry 2^31 are compared with the oracle, and the row pointers with its counts.
+    """
+    import torch
+    g = fi.slab_phantom(81, n=(200, 200, 200), spacing=(0.25, 0.25, 0.25), lung_side=(4, 10), bone_side=(1, 3))
+    prob = fi.Problem("big", g, fi.coplanar_beams(9, (0.11, -0.07, 0.13), 100.0, 0.5, 0.5, 30, 30),
+                      fi.default_kernel(81, cutoff=5.0))
+    _say("parity: 2.9e9-entry plan")
+    plan, csr = _run(prob)
+    ind = csr.indptr.cpu().numpy()
+    assert csr.nnz > 2 ** 31 and ind[-1] == csr.nnz and np.all(np.diff(ind) >= 0)
+    ora = oracle_lib.OraclePlan(prob)
+    counts = ora.counts()
+    np.testing.assert_array_equal(np.diff(ind), counts)
+    late = [int(j) for j in np.nonzero(ind[:-1] > 2 ** 31)[0]]
+    rng = np.random.default_rng(81)
+    rows = sorted(rng.choice(late, 8, replace=False).tolist()) + [ora.n_beamlets - 1]
+    r = compare_rows(ora, rows, gpu_rows_from_csr(csr, rows))
+    _say(f"  nnz={csr.nnz} rows from {ind[rows[0]]} on: max_rel={r['max_rel']:.2e} band={r['band_mismatches']}")
+    del csr, plan
+    torch.cuda.empty_cache()
+
+
 def test_edge_cases(torch_gpu, oracle_lib):
     from paper_0908_4417_amd import Plan
     # a beam whose outer beamlets miss the grid entirely (empty rows)
