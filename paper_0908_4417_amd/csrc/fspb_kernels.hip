@@ -700,15 +700,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         // rows are walked once, wave-uniformly, as the chunks advance
         int rcur = 0;
         int64_t written = out0;
-        for (int c0 = 0; c0 < total; c0 += kWave) {
-            while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
-            const int p = c0 + lane;
-            int rr = rcur;
-            for (int q = rcur + 1; q < kWave; ++q) {
-                const int eq = readlane(excl, q);
-                if (eq > c0 + kWave - 1) break;
-                if (p >= eq) rr = q;
-            }
+        // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
+        auto chunk = [&](const int p, const int rr) {
             const int k = p - __shfl(excl, rr, kWave);
             const int ix = __shfl(lo, rr, kWave) + k;
             const int gr = __shfl(grow, rr, kWave);
@@ -762,6 +755,34 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                 }
             }
             written += __popcll(mask);
+        };
+        if (!SURR) {
+            // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane
+            for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
+                while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
+                const int p1 = c0 + lane, p2 = p1 + kWave;
+                int r1 = rcur, r2 = rcur;
+                for (int q = rcur + 1; q < kWave; ++q) {
+                    const int eq = readlane(excl, q);
+                    if (eq > c0 + 2 * kWave - 1) break;
+                    if (p1 >= eq) r1 = q;
+                    if (p2 >= eq) r2 = q;
+                }
+                chunk(p1, r1);
+                chunk(p2, r2);
+            }
+        } else {
+            for (int c0 = 0; c0 < total; c0 += kWave) {
+                while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
+                const int p = c0 + lane;
+                int rr = rcur;
+                for (int q = rcur + 1; q < kWave; ++q) {
+                    const int eq = readlane(excl, q);
+                    if (eq > c0 + kWave - 1) break;
+                    if (p >= eq) rr = q;
+                }
+                chunk(p, rr);
+            }
         }
     }
 }
