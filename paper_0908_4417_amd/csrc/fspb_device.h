@@ -16,8 +16,9 @@ constexpr int kMaxTerms = 4;
 // (training targets of the kernel surrogate)
 constexpr int kErfcIntervals = 512;
 constexpr float kErfcMax = 4.0f;
-// erf on [-kErfMax, kErfMax] by piecewise quadratics on kErfIntervals equal
-// intervals (the fill); both tables have 128 intervals per unit of argument
+// erf on [0, kErfMax] by linear interpolation between kErfIntervals + 1 equally
+// spaced nodes, 256 per unit of argument (the fill; negative arguments by odd
+// symmetry, held at +-erf(kErfMax) beyond the last node)
 constexpr int kErfIntervals = 1024;
 constexpr float kErfMax = 4.0f;
 
@@ -65,7 +66,7 @@ struct alignas(16) PlanDev {
     float c2[kMaxTerms];
     float pdd_inv_step, pdd_max;   // 1/step; n_pdd - 1
     const float *pdd;
-    const float4 *erf_tab;       // [kErfIntervals] (c0, c1, c2, 0) on each interval
+    const float2 *erf_tab;       // [kErfIntervals] (erf at node k, erf at node k+1 minus it)
     // general kernel form (0: the analytic form above): c tables [3][n_terms][n_cdepth]
     // (c1, c2, c3), A [n_theta][n_adepth]
     int32_t gen, n_cdepth, n_theta, n_adepth;

@@ -277,19 +277,19 @@ void erfc_table(std::vector<float4> &t)
 }
 
 /*
- * Piecewise-quadratic erf used by the fill kernel, the same construction on
- * [-kErfMax, kErfMax] (kErfIntervals intervals of width w = 1/128): on each
- * interval the quadratic through erf at both ends and the midpoint.
+ * Piecewise-linear erf used by the fill kernel on [0, kErfMax] (kErfIntervals
+ * intervals of width w = 1/256): node k holds erf(k w) rounded to FP32 and the
+ * difference to erf((k + 1) w) taken from that rounded value, so that the
+ * interpolant is continuous to FP32 rounding at every node.
  */
-void erf_table(std::vector<float4> &t)
+void erf_table(std::vector<float2> &t)
 {
     const int n = fspb::kErfIntervals;
-    const double w = 2.0 * (double)fspb::kErfMax / n;
+    const double w = (double)fspb::kErfMax / n;
     t.resize(n);
     for (int k = 0; k < n; ++k) {
-        const double z = -(double)fspb::kErfMax + k * w;
-        const double y0 = std::erf(z), ym = std::erf(z + 0.5 * w), y1 = std::erf(z + w);
-        t[k] = make_float4((float)y0, (float)(4.0 * ym - 3.0 * y0 - y1), (float)(2.0 * (y1 + y0 - 2.0 * ym)), 0.0f);
+        const float y0 = (float)std::erf(k * w);
+        t[k] = make_float2(y0, (float)(std::erf((k + 1) * w) - (double)y0));
     }
 }
 
@@ -509,7 +509,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     L.row_nnz = take(sizeof(int64_t) * (size_t)nbl);
     L.tables = take(sizeof(float) * (size_t)std::max<int64_t>(table_off, 1));
     L.pdd = take(sizeof(float) * (size_t)K->n_pdd);
-    L.erf = take(sizeof(float4) * fspb::kErfIntervals);
+    L.erf = take(sizeof(float2) * fspb::kErfIntervals);
     if (K->tables) {
         L.ctab = take(sizeof(float) * 3 * (size_t)K->n_terms * K->tables->n_depth);
         L.atab = take(sizeof(float) * (size_t)K->tables->n_theta * K->tables->n_adepth);
@@ -547,7 +547,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     h.row_nnz = reinterpret_cast<int64_t *>(ws + L.row_nnz);
     h.tables = reinterpret_cast<float *>(ws + L.tables);
     h.pdd = reinterpret_cast<float *>(ws + L.pdd);
-    h.erf_tab = reinterpret_cast<float4 *>(ws + L.erf);
+    h.erf_tab = reinterpret_cast<float2 *>(ws + L.erf);
     if (K->tables) {
         h.ctab = reinterpret_cast<float *>(ws + L.ctab);
         h.atab = reinterpret_cast<float *>(ws + L.atab);
@@ -577,9 +577,9 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
                  "upload A table");
     }
     {
-        std::vector<float4> et;
+        std::vector<float2> et;
         erf_table(et);
-        FSPB_HIP(hipMemcpy((void *)h.erf_tab, et.data(), sizeof(float4) * et.size(), hipMemcpyHostToDevice),
+        FSPB_HIP(hipMemcpy((void *)h.erf_tab, et.data(), sizeof(float2) * et.size(), hipMemcpyHostToDevice),
                  "upload erf table");
     }
     FSPB_HIP(hipMemset(p->d_overflow, 0, sizeof(int32_t)), "clear overflow flag");

@@ -430,31 +430,32 @@ __device__ inline gptr<T> as_global(T *p)
 }
 
 /*
- * erf(z) at the table coordinate x = (z + kErfMax) kErfScale: piecewise
- * quadratic from LDS, held at the ends of [-kErfMax, kErfMax].  The LDS copy
- * packs each interval's (c0, c1, c2) in 12 bytes: a 3-dword stride spreads
- * the lanes' random intervals over the banks better than a 4-dword one.
+ * erf(z) at the table coordinate x = z kErfScale: linear interpolation in the
+ * LDS copy of the table on [0, kErfMax] (one 8-byte (value, difference) read),
+ * sign restored by odd symmetry, held at +-erf(kErfMax) beyond the table.
+ * Halving the table this way (8 KB) keeps the fill's LDS per workgroup small
+ * enough for six workgroups per CU on the largest plans.
  */
-constexpr float kErfScale = (float)kErfIntervals / (2.0f * kErfMax);
-constexpr int kErfLdsFloats = 3 * kErfIntervals;
+constexpr float kErfScale = (float)kErfIntervals / kErfMax;
+constexpr int kErfLdsFloats = 2 * kErfIntervals;
 
 __device__ inline float erf_lds(const float *__restrict__ tab, float x)
 {
-    const float xc = __builtin_amdgcn_fmed3f(x, 0.0f, (float)kErfIntervals - 1.0f / 1024.0f);
+    const float xc = fminf(fabsf(x), (float)kErfIntervals - 1.0f / 1024.0f);
     const int k = (int)xc;
     const float f = __builtin_amdgcn_fractf(xc);
-    const float c0 = tab[3 * k], c1 = tab[3 * k + 1], c2 = tab[3 * k + 2];
-    return fmaf(fmaf(c2, f, c1), f, c0);
+    const float2 q = reinterpret_cast<const float2 *>(tab)[k];
+    return copysignf(fmaf(q.y, f, q.x), x);
 }
 
 /*
  * One bracket of Eq. 3, erf((h - x) is) + erf((h + x) is), with
- * is = 1/(sqrt2 sigma): isk = is kErfScale and hko = h isk + kErfMax kErfScale
- * put both arguments in table coordinates.  The bracket is even in x.
+ * is = 1/(sqrt2 sigma): isk = is kErfScale and hk = h isk put both arguments
+ * in table coordinates.  The bracket is even in x.
  */
-__device__ inline float edge_pair(const float *__restrict__ tab, float x, float hko, float isk)
+__device__ inline float edge_pair(const float *__restrict__ tab, float x, float hk, float isk)
 {
-    return erf_lds(tab, fmaf(-x, isk, hko)) + erf_lds(tab, fmaf(x, isk, hko));
+    return erf_lds(tab, fmaf(-x, isk, hk)) + erf_lds(tab, fmaf(x, isk, hk));
 }
 
 /* Per-beamlet constants of the fill, held in registers. */
@@ -471,7 +472,6 @@ struct FillConst {
 
 // is kErfScale = kIsScale / sigma
 constexpr float kIsScale = 0.70710678118654752f * kErfScale;
-constexpr float kErfOff = kErfMax * kErfScale;
 
 template <int K, bool GUARD>
 __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restrict__ tab,
@@ -495,8 +495,8 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
     for (int i = 0; i < K; ++i) {
         if (GUARD && i >= c.n_terms) break;
         const float isk = __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
-        const float eu = edge_pair(etab, u, fmaf(c.ha[i], isk, kErfOff), isk);
-        const float ev = edge_pair(etab, v, fmaf(c.hb[i], isk, kErfOff), isk);
+        const float eu = edge_pair(etab, u, c.ha[i] * isk, isk);
+        const float ev = edge_pair(etab, v, c.hb[i] * isk, isk);
         L = fmaf(c.w4[i] * eu, ev, L);
     }
     return A * L;
@@ -530,8 +530,8 @@ __device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__re
         const float2 q1 = sc[i * c.nc + kc], q2 = sc[(K + i) * c.nc + kc], q3 = sc[(2 * K + i) * c.nc + kc];
         const float c1 = fmaf(fc, q1.y, q1.x), c2 = fmaf(fc, q2.y, q2.x), c3 = fmaf(fc, q3.y, q3.x);
         const float isk = kIsScale * __builtin_amdgcn_rcpf(c3);
-        const float eu = edge_pair(etab, u, fmaf(c2 * c.half_a, isk, kErfOff), isk);
-        const float ev = edge_pair(etab, v, fmaf(c2 * c.half_b, isk, kErfOff), isk);
+        const float eu = edge_pair(etab, u, c2 * c.half_a * isk, isk);
+        const float ev = edge_pair(etab, v, c2 * c.half_b * isk, isk);
         L = fmaf(0.25f * c1 * eu, ev, L);
     }
     return A * L;
@@ -616,13 +616,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const bool mlp_ok = SURR && R.mlp_ok;
 
     {
-        const float4 *et = P.erf_tab;
-        for (int i = tid; i < kErfIntervals; i += kB) {
-            const float4 q = et[i];
-            s_erf[3 * i] = q.x;
-            s_erf[3 * i + 1] = q.y;
-            s_erf[3 * i + 2] = q.z;
-        }
+        const float2 *et = P.erf_tab;
+        for (int i = tid; i < kErfIntervals; i += kB) reinterpret_cast<float2 *>(s_erf)[i] = et[i];
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
         for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
