@@ -159,7 +159,13 @@ typedef struct {
 /*
  * Create a plan: validate, compute the FP64 beamlet geometry (Fig. 1) on the
  * host, carve the caller's device workspace and upload the beamlet records
- * and the depth-dose table.
+ * and the depth-dose table.  The upload is one asynchronous copy on the null
+ * stream from a pinned staging buffer of the library (pooled per device, at
+ * most eight, kept until the process ends); the call does not wait for the
+ * device, and fspb_raytrace and fspb_batch_create order their stream after
+ * the copy.  Like all null-stream work the copy starts after earlier work on
+ * blocking streams; work on non-blocking streams that still uses this
+ * workspace must have completed before the call.
  *
  * workspace        DEVICE pointer of workspace_bytes bytes (256-byte aligned), owned by
  *                  the caller, kept for the plan's life.  NULL: only *workspace_needed is

@@ -71,10 +71,42 @@ constexpr double kPi = 3.14159265358979323846;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-/* Workspace carve: offsets of every device array. */
+/* Workspace carve: offsets of every device array.  The arrays the host
+ * writes come first, so that one copy of [0, upload) uploads all of them. */
 struct Layout {
-    size_t plan, out, scal, rec, tile_beamlet, tile_count, row_nnz, tables, pdd, erf, ctab, atab, bits, ext, total;
+    size_t plan, scal, rec, tile_beamlet, pdd, erf, ctab, atab, upload;
+    size_t out, tile_count, row_nnz, tables, bits, ext, total;
 };
+
+/*
+ * Pinned host buffers for plan uploads.  fspb_plan_create writes a plan's
+ * upload image into one of them and sends it with a single asynchronous copy
+ * on the null stream, so the host does not wait for the device (which may
+ * still be busy with an earlier plan in the same workspace).  A buffer is
+ * reused once the event recorded after its copy has completed; at most
+ * kStagingPerDevice buffers exist per device (beyond that, creation waits for
+ * the oldest copy), and they are kept until the process ends.
+ */
+struct Staging {
+    void *host = nullptr;
+    size_t cap = 0;
+    int device = -1;
+    bool claimed = false;
+    hipEvent_t done = nullptr;
+};
+constexpr int kStagingPerDevice = 8;
+std::mutex g_stage_mu;
+std::vector<std::unique_ptr<Staging>> g_stage;
+
+bool stage_idle(Staging &b)
+{
+    const hipError_t e = hipEventQuery(b.done);
+    if (e == hipErrorNotReady) (void)hipGetLastError();   // not an error: clear it
+    return e != hipErrorNotReady;
+}
+
+/* erf table of the fill (built once). */
+const std::vector<float2> &fill_erf_table();
 
 }  // namespace
 
@@ -99,10 +131,12 @@ struct fspb_plan {
     bool timing = false;
     hipEvent_t ev[8] = {};
     bool have_trace_ev = false, have_dose_ev = false;
+    hipEvent_t upload_done = nullptr;   // recorded after the plan's upload (null stream)
     ~fspb_plan()
     {
         for (hipEvent_t &e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (upload_done) (void)hipEventDestroy(upload_done);
     }
 };
 
@@ -292,6 +326,75 @@ void erf_table(std::vector<float2> &t)
         t[k] = make_float2(y0, (float)(std::erf((k + 1) * w) - (double)y0));
     }
 }
+
+const std::vector<float2> &fill_erf_table()
+{
+    static const std::vector<float2> t = [] {
+        std::vector<float2> v;
+        erf_table(v);
+        return v;
+    }();
+    return t;
+}
+
+/* A staging buffer of at least `bytes` on `device`, claimed for the caller. */
+fspb_status stage_acquire(size_t bytes, int device, Staging **out)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    int on_device = 0;
+    Staging *reuse = nullptr;
+    for (auto &b : g_stage) {
+        if (b->device != device) continue;
+        ++on_device;
+        if (b->claimed) continue;
+        if (b->cap >= bytes && stage_idle(*b)) {
+            b->claimed = true;
+            *out = b.get();
+            return FSPB_OK;
+        }
+        if (!reuse) reuse = b.get();
+    }
+    if (on_device >= kStagingPerDevice && reuse) {
+        // every buffer is busy or small: wait for one, grow it if needed
+        FSPB_HIP(hipEventSynchronize(reuse->done), "wait for an earlier upload");
+        if (reuse->cap < bytes) {
+            FSPB_HIP(hipHostFree(reuse->host), "free staging buffer");
+            reuse->host = nullptr;
+            reuse->cap = 0;
+            const size_t cap = align_up(bytes, (size_t)1 << 20);
+            FSPB_HIP(hipHostMalloc(&reuse->host, cap, hipHostMallocDefault), "allocate staging buffer");
+            reuse->cap = cap;
+        }
+        reuse->claimed = true;
+        *out = reuse;
+        return FSPB_OK;
+    }
+    std::unique_ptr<Staging> b(new (std::nothrow) Staging);
+    if (!b) return fail(FSPB_ERR_NOMEM, "cannot allocate a staging record");
+    b->device = device;
+    FSPB_HIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming), "create staging event");
+    const size_t cap = align_up(bytes, (size_t)1 << 20);
+    hipError_t e = hipHostMalloc(&b->host, cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(b->done);
+        return hip_fail(e, "allocate staging buffer");
+    }
+    b->cap = cap;
+    b->claimed = true;
+    *out = b.get();
+    g_stage.push_back(std::move(b));
+    return FSPB_OK;
+}
+
+/* Releases a claimed staging buffer when it goes out of scope. */
+struct StageClaim {
+    Staging *b;
+    ~StageClaim()
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        b->claimed = false;
+    }
+};
 
 }  // namespace
 
@@ -501,19 +604,20 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     };
     const int64_t grow = (int64_t)g->ny * g->nz;
     L.plan = take(sizeof(PlanDev));
-    L.out = take(sizeof(OutDev));
     L.scal = take(64);
     L.rec = take(sizeof(BeamletRec) * (size_t)nbl);
     L.tile_beamlet = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
-    L.tile_count = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
-    L.row_nnz = take(sizeof(int64_t) * (size_t)nbl);
-    L.tables = take(sizeof(float) * (size_t)std::max<int64_t>(table_off, 1));
     L.pdd = take(sizeof(float) * (size_t)K->n_pdd);
     L.erf = take(sizeof(float2) * fspb::kErfIntervals);
     if (K->tables) {
         L.ctab = take(sizeof(float) * 3 * (size_t)K->n_terms * K->tables->n_depth);
         L.atab = take(sizeof(float) * (size_t)K->tables->n_theta * K->tables->n_adepth);
     }
+    L.upload = off;
+    L.out = take(sizeof(OutDev));
+    L.tile_count = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
+    L.row_nnz = take(sizeof(int64_t) * (size_t)nbl);
+    L.tables = take(sizeof(float) * (size_t)std::max<int64_t>(table_off, 1));
     L.bits = take(sizeof(uint32_t) * (size_t)grow * h.wpr);
     L.ext = take(sizeof(int2) * (size_t)grow);
     L.total = off;
@@ -556,33 +660,35 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     h.ext = reinterpret_cast<int2 *>(ws + L.ext);
     h.nnz = p->d_nnz;
 
-    FSPB_HIP(hipMemcpy(p->d_plan, &h, sizeof(PlanDev), hipMemcpyHostToDevice), "upload plan record");
-    if (nbl > 0)
-        FSPB_HIP(hipMemcpy((void *)h.rec, p->recs.data(), sizeof(BeamletRec) * (size_t)nbl, hipMemcpyHostToDevice),
-                 "upload beamlet records");
-    if (tile_off > 0)
-        FSPB_HIP(hipMemcpy((void *)h.tile_beamlet, p->tile_beamlet.data(), sizeof(int32_t) * (size_t)tile_off,
-                           hipMemcpyHostToDevice),
-                 "upload tile map");
-    FSPB_HIP(hipMemcpy((void *)h.pdd, K->pdd, sizeof(float) * (size_t)K->n_pdd, hipMemcpyHostToDevice),
-             "upload depth dose");
-    if (const fspb_kernel_tables *T = K->tables) {
-        const size_t nc = (size_t)K->n_terms * T->n_depth;
-        const float *src[3] = {T->c1, T->c2, T->c3};
-        for (int m = 0; m < 3; ++m)
-            FSPB_HIP(hipMemcpy((void *)(h.ctab + m * nc), src[m], sizeof(float) * nc, hipMemcpyHostToDevice),
-                     "upload kernel tables");
-        FSPB_HIP(hipMemcpy((void *)h.atab, T->A, sizeof(float) * (size_t)T->n_theta * T->n_adepth,
-                           hipMemcpyHostToDevice),
-                 "upload A table");
-    }
+    // ---- every host-written array in one asynchronous copy of [0, L.upload) on the null
+    // stream, from a pinned image; fspb_raytrace and fspb_batch_create wait for its event
+    int dev = 0;
+    FSPB_HIP(hipGetDevice(&dev), "get device");
+    FSPB_HIP(hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming), "create upload event");
+    Staging *sb = nullptr;
+    st = stage_acquire(L.upload, dev, &sb);
+    if (st != FSPB_OK) return st;
     {
-        std::vector<float2> et;
-        erf_table(et);
-        FSPB_HIP(hipMemcpy((void *)h.erf_tab, et.data(), sizeof(float2) * et.size(), hipMemcpyHostToDevice),
-                 "upload erf table");
+        StageClaim claim{sb};
+        char *img = static_cast<char *>(sb->host);
+        std::memcpy(img + L.plan, &h, sizeof(PlanDev));
+        std::memset(img + L.scal, 0, 64);   // nonzero count and overflow flag start at zero
+        if (nbl > 0) std::memcpy(img + L.rec, p->recs.data(), sizeof(BeamletRec) * (size_t)nbl);
+        if (tile_off > 0)
+            std::memcpy(img + L.tile_beamlet, p->tile_beamlet.data(), sizeof(int32_t) * (size_t)tile_off);
+        std::memcpy(img + L.pdd, K->pdd, sizeof(float) * (size_t)K->n_pdd);
+        const std::vector<float2> &et = fill_erf_table();
+        std::memcpy(img + L.erf, et.data(), sizeof(float2) * et.size());
+        if (const fspb_kernel_tables *T = K->tables) {
+            const size_t nc = (size_t)K->n_terms * T->n_depth;
+            const float *src[3] = {T->c1, T->c2, T->c3};
+            for (int m = 0; m < 3; ++m) std::memcpy(img + L.ctab + sizeof(float) * m * nc, src[m], sizeof(float) * nc);
+            std::memcpy(img + L.atab, T->A, sizeof(float) * (size_t)T->n_theta * T->n_adepth);
+        }
+        FSPB_HIP(hipMemcpyAsync(ws, img, L.upload, hipMemcpyHostToDevice, nullptr), "upload plan");
+        FSPB_HIP(hipEventRecord(sb->done, nullptr), "record upload");
+        FSPB_HIP(hipEventRecord(p->upload_done, nullptr), "record upload");
     }
-    FSPB_HIP(hipMemset(p->d_overflow, 0, sizeof(int32_t)), "clear overflow flag");
     guard.p = nullptr;
     *out = p;
     return FSPB_OK;
@@ -593,6 +699,7 @@ fspb_status fspb_raytrace(fspb_plan *p, void *stream)
     g_last_error.clear();
     if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    FSPB_HIP(hipStreamWaitEvent(s, p->upload_done, 0), "wait for the plan upload");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[0], s), "record event");
     FSPB_HIP(fspb::launch_prep(p->d_plan, p->h, s), "launch prep");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[1], s), "record event");
@@ -953,6 +1060,8 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
 
     // sizing pass: mask, tables, counts, row sums
     hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n_plans; ++i)
+        FSPB_HIP(hipStreamWaitEvent(s, plans[i]->upload_done, 0), "wait for a plan upload");
     FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
     for (int st = 0; st < 4; ++st)
         if (b->total[st] > 0)
