@@ -200,8 +200,10 @@ fspb_status fspb_raytrace(fspb_plan *plan, void *stream);
  * values   DEVICE, capacity floats.
  * nnz_out  HOST out: number of nonzeros.
  * Returns CAPACITY (after writing indptr and *nnz_out, no values) when indices
- * or values is NULL or capacity < nnz.  The call synchronises `stream` once to
- * read the count; the fill is then enqueued without waiting.
+ * or values is NULL or capacity < nnz.  The fill is enqueued right behind the
+ * count (it checks the total against capacity on the device and writes
+ * nothing if it does not fit); the call then waits for the count only, not
+ * for the fill.
  */
 fspb_status fspb_dose_coeffs(fspb_plan *plan, int64_t *indptr, int32_t *indices, float *values,
                              int64_t capacity, int64_t *nnz_out, void *stream);

@@ -99,7 +99,7 @@ struct alignas(16) OutDev {
     int64_t capacity;
     int32_t *overflow;           // set to 1 if a fill would exceed capacity
     int32_t row0;                // first row written: entry positions are relative to indptr[row0]
-    int32_t pad;
+    int32_t check_nnz;           // whole-plan fill: write nothing when PlanDev::nnz > capacity
 };
 
 /* Launchers (fspb_kernels.hip).  Each returns the launch's hipError_t. */

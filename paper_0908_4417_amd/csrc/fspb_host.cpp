@@ -108,6 +108,39 @@ bool stage_idle(Staging &b)
 /* erf table of the fill (built once). */
 const std::vector<float2> &fill_erf_table();
 
+/*
+ * Pinned 64-byte host slots, one per plan, that a plan's nonzero count is
+ * copied back into: an asynchronous copy into pinned memory lets
+ * fspb_dose_coeffs queue the fill before it waits for the count.  Slots are
+ * carved from pinned pages and recycled; the pages are kept until the process
+ * ends.
+ */
+std::mutex g_slot_mu;
+std::vector<void *> g_slot_pages;
+std::vector<int64_t *> g_slot_free;
+constexpr size_t kSlotBytes = 64, kSlotPage = 64 * 1024;
+
+fspb_status slot_acquire(int64_t **out)
+{
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    if (g_slot_free.empty()) {
+        void *page = nullptr;
+        FSPB_HIP(hipHostMalloc(&page, kSlotPage, hipHostMallocDefault), "allocate pinned slots");
+        g_slot_pages.push_back(page);
+        for (size_t o = kSlotPage; o >= kSlotBytes; o -= kSlotBytes)
+            g_slot_free.push_back(reinterpret_cast<int64_t *>(static_cast<char *>(page) + o - kSlotBytes));
+    }
+    *out = g_slot_free.back();
+    g_slot_free.pop_back();
+    return FSPB_OK;
+}
+
+void slot_release(int64_t *slot)
+{
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    g_slot_free.push_back(slot);
+}
+
 }  // namespace
 
 struct fspb_plan {
@@ -132,11 +165,15 @@ struct fspb_plan {
     hipEvent_t ev[8] = {};
     bool have_trace_ev = false, have_dose_ev = false;
     hipEvent_t upload_done = nullptr;   // recorded after the plan's upload (null stream)
+    int64_t *nnz_host = nullptr;        // pinned slot the nonzero count is read into
+    hipEvent_t nnz_ready = nullptr;     // recorded after that read
     ~fspb_plan()
     {
         for (hipEvent_t &e : ev)
             if (e) (void)hipEventDestroy(e);
         if (upload_done) (void)hipEventDestroy(upload_done);
+        if (nnz_ready) (void)hipEventDestroy(nnz_ready);
+        if (nnz_host) slot_release(nnz_host);
     }
 };
 
@@ -665,6 +702,9 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     int dev = 0;
     FSPB_HIP(hipGetDevice(&dev), "get device");
     FSPB_HIP(hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming), "create upload event");
+    FSPB_HIP(hipEventCreateWithFlags(&p->nnz_ready, hipEventDisableTiming), "create count event");
+    st = slot_acquire(&p->nnz_host);
+    if (st != FSPB_OK) return st;
     Staging *sb = nullptr;
     st = stage_acquire(L.upload, dev, &sb);
     if (st != FSPB_OK) return st;
@@ -729,6 +769,7 @@ fspb_status fspb_dose_coeffs(fspb_plan *p, int64_t *indptr, int32_t *indices, fl
     p->out.capacity = (indices && values) ? capacity : 0;
     p->out.overflow = p->d_overflow;
     p->out.row0 = 0;
+    p->out.check_nnz = 1;
     p->counted = false;
     FSPB_HIP(hipMemcpyAsync(p->d_out, &p->out, sizeof(OutDev), hipMemcpyHostToDevice, s), "upload output record");
     p->have_dose_ev = false;
@@ -737,20 +778,23 @@ fspb_status fspb_dose_coeffs(fspb_plan *p, int64_t *indptr, int32_t *indices, fl
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[4], s), "record event");
     FSPB_HIP(fspb::launch_rowsum_scan(p->d_plan, p->d_out, p->h, s), "launch scan");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[5], s), "record event");
-    int64_t nnz = 0;
-    FSPB_HIP(hipMemcpyAsync(&nnz, p->d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read nnz");
-    FSPB_HIP(hipStreamSynchronize(s), "synchronise for nnz");
+    FSPB_HIP(hipMemcpyAsync(p->nnz_host, p->d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read nnz");
+    FSPB_HIP(hipEventRecord(p->nnz_ready, s), "record count event");
+    // the fill is queued before the count is known; it writes nothing unless the total fits
+    const bool fill = indices && values && capacity > 0;
+    if (fill) {
+        if (p->timing) FSPB_HIP(hipEventRecord(p->ev[6], s), "record event");
+        FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, 0, p->h.n_beamlets, s), "launch fill");
+        if (p->timing) FSPB_HIP(hipEventRecord(p->ev[7], s), "record event");
+    }
+    FSPB_HIP(hipEventSynchronize(p->nnz_ready), "wait for nnz");
+    const int64_t nnz = *p->nnz_host;
     *nnz_out = nnz;
     p->counted = true;
-    if (!indices || !values || capacity < nnz)
+    if (!fill || capacity < nnz)
         return fail(FSPB_ERR_CAPACITY, "%lld nonzeros do not fit a capacity of %lld", (long long)nnz,
-                    (long long)(indices && values ? capacity : 0));
-    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[6], s), "record event");
-    FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, 0, p->h.n_beamlets, s), "launch fill");
-    if (p->timing) {
-        FSPB_HIP(hipEventRecord(p->ev[7], s), "record event");
-        p->have_dose_ev = true;
-    }
+                    (long long)(fill ? capacity : 0));
+    p->have_dose_ev = p->timing;
     return FSPB_OK;
 }
 
@@ -781,6 +825,7 @@ fspb_status fspb_dose_coeffs_rows(fspb_plan *p, int32_t j0, int32_t j1, const in
     p->out.capacity = capacity;
     p->out.overflow = p->d_overflow;
     p->out.row0 = j0;
+    p->out.check_nnz = 0;   // the range's size was checked above
     FSPB_HIP(hipMemcpyAsync(p->d_out, &p->out, sizeof(OutDev), hipMemcpyHostToDevice, s), "upload output record");
     FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, j0, j1 - j0, s), "launch fill");
     return FSPB_OK;

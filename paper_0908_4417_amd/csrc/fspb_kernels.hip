@@ -448,14 +448,26 @@ __device__ inline float erf_lds(const float *__restrict__ tab, float x)
     return copysignf(fmaf(q.y, f, q.x), x);
 }
 
+/* erf_lds for an argument known to be >= 0 (no sign to restore). */
+__device__ inline float erf_lds_pos(const float *__restrict__ tab, float x)
+{
+    const float xc = fminf(x, (float)kErfIntervals - 1.0f / 1024.0f);
+    const int k = (int)xc;
+    const float f = __builtin_amdgcn_fractf(xc);
+    const float2 q = reinterpret_cast<const float2 *>(tab)[k];
+    return fmaf(q.y, f, q.x);
+}
+
 /*
  * One bracket of Eq. 3, erf((h - x) is) + erf((h + x) is), with
  * is = 1/(sqrt2 sigma): isk = is kErfScale and hk = h isk put both arguments
- * in table coordinates.  The bracket is even in x.
+ * in table coordinates.  The bracket is even in x, so it is evaluated at |x|,
+ * where the second argument is never negative (h > 0).
  */
 __device__ inline float edge_pair(const float *__restrict__ tab, float x, float hk, float isk)
 {
-    return erf_lds(tab, fmaf(-x, isk, hk)) + erf_lds(tab, fmaf(x, isk, hk));
+    const float ax = fabsf(x);
+    return erf_lds(tab, fmaf(-ax, isk, hk)) + erf_lds_pos(tab, fmaf(ax, isk, hk));
 }
 
 /* Per-beamlet constants of the fill, held in registers. */
@@ -787,6 +799,8 @@ __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ pla
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    // launched before the host has read the plan's total: write nothing if it does not fit
+    if (outs[0].check_nnz && *plans[0].nnz > outs[0].capacity) return;
     fill_beamlet<K, kWavesPerBlock, false, SURR, GEN>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
 }
 

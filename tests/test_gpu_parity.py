@@ -195,11 +195,22 @@ def test_state_and_capacity_errors(torch_gpu):
     plan.raytrace()
     st, nnz = m.fspb_dose_coeffs(plan.handle, plan.indptr.data_ptr(), None, None, 0, s)
     assert st == m.FSPB_ERR_CAPACITY and nnz > 0
-    small_i = torch.empty(nnz - 1, dtype=torch.int32, device="cuda:0")
-    small_v = torch.empty(nnz - 1, dtype=torch.float32, device="cuda:0")
+    small_i = torch.full((nnz - 1,), -7, dtype=torch.int32, device="cuda:0")
+    small_v = torch.full((nnz - 1,), -7.0, dtype=torch.float32, device="cuda:0")
     st, nnz2 = m.fspb_dose_coeffs(plan.handle, plan.indptr.data_ptr(), small_i.data_ptr(),
                                   small_v.data_ptr(), nnz - 1, s)
     assert st == m.FSPB_ERR_CAPACITY and nnz2 == nnz
+    # the fill was queued before the count was known: it must have written nothing
+    torch.cuda.synchronize()
+    assert bool((small_i == -7).all()) and bool((small_v == -7.0).all())
+    # a fitting capacity afterwards gives the full matrix
+    full_i = torch.empty(nnz, dtype=torch.int32, device="cuda:0")
+    full_v = torch.empty(nnz, dtype=torch.float32, device="cuda:0")
+    st, nnz3 = m.fspb_dose_coeffs(plan.handle, plan.indptr.data_ptr(), full_i.data_ptr(),
+                                  full_v.data_ptr(), nnz, s)
+    assert st == m.FSPB_OK and nnz3 == nnz
+    torch.cuda.synchronize()
+    assert bool((full_v >= 0).all()) and bool((full_i >= 0).all())
 
 
 def test_determinism_and_density_update(torch_gpu, oracle_lib):
