@@ -3,12 +3,16 @@
 
 One step = the whole plain path for one plan of the 128^3 slab workload
 (9 coplanar beams 40 deg apart, 30 x 30 beamlets of 0.5 cm, 8100 rows):
-  fspb_plan_create  (FP64 beamlet geometry, VOI row bounds, record upload)
-  fspb_raytrace     (density mask + radiological-depth tables)
-  fspb_dose_coeffs  (count, scan, 8-byte nnz read, fill)
+  fspb_plan_create  (FP64 beamlet geometry, VOI row bounds, pinned record image)
+  fspb_raytrace     (record upload, density mask + radiological-depth tables)
+  fspb_dose_coeffs  (count, scan, fill queued behind them, 8-byte nnz read)
   fspb_plan_destroy
-The density grid, the output buffers and the workspace are resident in HBM
-before the timed region.  `value` = nonzeros produced per second of
+The density grid, the output buffers and the workspaces are resident in HBM
+before the timed region.  Consecutive steps alternate between two streams,
+each with its own workspace and CSR arrays (--pipeline 2), so that one
+plan's upload, trace and count overlap the previous plan's fill, as a caller
+computing plan after plan would run them; `ms_per_step_one_stream` is the
+same loop on one stream.  `value` = nonzeros produced per second of
 wall-clock over the K timed steps.
 
 Printed as one JSON line.  Besides the contract fields it carries
@@ -46,6 +50,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target duration of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pipeline", type=int, default=2, choices=[1, 2, 3],
+                    help="plans in flight: step k runs on stream k mod P with its own workspace and "
+                         "outputs, so one plan's trace and count overlap another's fill")
     ap.add_argument("--no-eq1", action="store_true", help="skip the Eq. 1 (dose, gradient, transpose) timings")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the trilinear-table, tabulated-kernel and chunked-computation timings")
@@ -372,45 +379,55 @@ def main():
     density = torch.from_numpy(prob.grid.density).to(dev)
     grid, beams, kern, _pdd = _structs(prob, density.data_ptr())
     nb = len(prob.beams)
-    stream = torch.cuda.current_stream(dev)
-    s = C.c_void_p(stream.cuda_stream)
+    # step k runs on streams[k % P] with workspace, row pointers and CSR arrays of its own
+    P = args.pipeline
+    streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in range(P - 1)]
+    sp = [C.c_void_p(x.cuda_stream) for x in streams]
+    s = sp[0]
 
     # sizes (outside the timed region)
     st, _, need = m.fspb_plan_create(grid, beams, nb, kern, None, 0)
-    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
-    wsp = (ws.data_ptr() + 255) // 256 * 256
-    st, h, _ = m.fspb_plan_create(grid, beams, nb, kern, wsp, need)
+    wss = [torch.empty(need + 256, dtype=torch.uint8, device=dev) for _ in range(P)]
+    wsp = [(w.data_ptr() + 255) // 256 * 256 for w in wss]
+    st, h, _ = m.fspb_plan_create(grid, beams, nb, kern, wsp[0], need)
     desc = m.fspb_plan_info(h)
-    indptr = torch.empty(desc.n_beamlets + 1, dtype=torch.int64, device=dev)
+    indptrs = [torch.empty(desc.n_beamlets + 1, dtype=torch.int64, device=dev) for _ in range(P)]
     m.fspb_raytrace(h, s)
-    st, nnz = m.fspb_dose_coeffs(h, indptr.data_ptr(), None, None, 0, s)
+    st, nnz = m.fspb_dose_coeffs(h, indptrs[0].data_ptr(), None, None, 0, s)
     m.fspb_plan_destroy(h)
-    indices = torch.empty(nnz, dtype=torch.int32, device=dev)
-    values = torch.empty(nnz, dtype=torch.float32, device=dev)
+    indices_l = [torch.empty(nnz, dtype=torch.int32, device=dev) for _ in range(P)]
+    values_l = [torch.empty(nnz, dtype=torch.float32, device=dev) for _ in range(P)]
+    indptr, indices, values = indptrs[0], indices_l[0], values_l[0]
 
-    def step(timed):
-        st_, hh, _ = m.fspb_plan_create(grid, beams, nb, kern, wsp, need)
+    def step(k, timed, P=P):
+        i = k % P
+        st_, hh, _ = m.fspb_plan_create(grid, beams, nb, kern, wsp[i], need)
         if timed:
             m.fspb_plan_set_timing(hh, 1)
-        m.fspb_raytrace(hh, s)
-        st_, n_ = m.fspb_dose_coeffs(hh, indptr.data_ptr(), indices.data_ptr(), values.data_ptr(), nnz, s)
+        m.fspb_raytrace(hh, sp[i])
+        st_, n_ = m.fspb_dose_coeffs(hh, indptrs[i].data_ptr(), indices_l[i].data_ptr(),
+                                     values_l[i].data_ptr(), nnz, sp[i])
         assert st_ == m.FSPB_OK and n_ == nnz
         t = m.fspb_plan_get_timing(hh) if timed else None
         m.fspb_plan_destroy(hh)
         return t
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(False)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
+    def timed_steps(P):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(k, False, P)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
-    # per-kernel device times (HIP events on the launch stream), separate pass
-    times = [step(True) for _ in range(args.steps)]
+    for k in range(args.warmup):
+        step(k, False)
+    wall = timed_steps(P)
+    ms_step = 1e3 * wall / args.steps
+    ms_step_serial = 1e3 * timed_steps(1) / args.steps if P > 1 else ms_step
+
+    # per-kernel device times (HIP events on the launch stream), separate serial pass
+    times = [step(0, True, 1) for _ in range(args.steps)]
     torch.cuda.synchronize()
     kt = {k: float(np.median([getattr(t, k) for t in times]))
           for k in ("prep_ms", "raytrace_ms", "count_ms", "scan_ms", "fill_ms")}
@@ -437,7 +454,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "grid": list(prob.grid.shape_xyz), "beams": nb,
-                   "beamlets": desc.n_beamlets, "nnz": nnz},
+                   "beamlets": desc.n_beamlets, "nnz": nnz, "plans_in_flight": P},
+        "ms_per_step_one_stream": round(ms_step_serial, 4),
         "roofline": roofline,
         "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
         # device time of fspb_raytrace + fspb_dose_coeffs (per-kernel medians), as the paper's T_GPU
@@ -446,7 +464,7 @@ def main():
     }
     if not args.no_eq1:
         out["eq1"] = eq1_timings(indptr, indices, values, int(np.prod(prob.grid.shape_xyz)), desc.n_beamlets)
-    del indices, values, ws                         # free the workload's CSR before the side studies
+    del indices, values, indices_l, values_l, wss   # free the workloads' CSR before the side studies
     torch.cuda.empty_cache()
     if not args.no_next:
         out["next_rows"] = next_rows_timings(prob)

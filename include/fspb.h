@@ -159,13 +159,12 @@ typedef struct {
 /*
  * Create a plan: validate, compute the FP64 beamlet geometry (Fig. 1) on the
  * host, carve the caller's device workspace and upload the beamlet records
- * and the depth-dose table.  The upload is one asynchronous copy on the null
- * stream from a pinned staging buffer of the library (pooled per device, at
- * most eight, kept until the process ends); the call does not wait for the
- * device, and fspb_raytrace and fspb_batch_create order their stream after
- * the copy.  Like all null-stream work the copy starts after earlier work on
- * blocking streams; work on non-blocking streams that still uses this
- * workspace must have completed before the call.
+ * and the depth-dose table.  Nothing is sent to the device here: the
+ * host-written part of the workspace is assembled in a pinned staging buffer
+ * of the library (pooled per device, kept until the process ends), which the
+ * plan holds until its first fspb_raytrace or fspb_batch_create copies it
+ * (one asynchronous copy, on that call's stream, so ordered like the rest of
+ * the plan's work).
  *
  * workspace        DEVICE pointer of workspace_bytes bytes (256-byte aligned), owned by
  *                  the caller, kept for the plan's life.  NULL: only *workspace_needed is
@@ -186,7 +185,8 @@ fspb_status fspb_plan_create(const fspb_grid *grid, const fspb_beam *beams, int3
  * table points; with FSPB_DEPTH_TRILINEAR the density is instead sampled by
  * trilinear interpolation at the table points (FP64) and summed by
  * trapezoids.  Also derives the density mask (density > rho_min) used by the
- * VOI test.  Reads the borrowed density; enqueues work on `stream`.
+ * VOI test.  Reads the borrowed density; enqueues work on `stream` (on the
+ * plan's first call, after the copy of the plan's records into the workspace).
  * Invalidates the row counts of an earlier fspb_dose_coeffs.
  */
 fspb_status fspb_raytrace(fspb_plan *plan, void *stream);
@@ -406,6 +406,8 @@ fspb_status fspb_surrogate_set_params(fspb_surrogate *sur, const float *params);
  * Attach a surrogate to a plan (NULL detaches it: analytic fill).  The plan's
  * kernel parameters must equal the surrogate's (same terms, widths, sigma
  * law and depth-dose table); the surrogate must outlive the attachment.
+ * After the plan's first fspb_raytrace this waits for all device work, then
+ * replaces the device copy of the plan record.
  */
 fspb_status fspb_plan_set_surrogate(fspb_plan *plan, const fspb_surrogate *sur);
 

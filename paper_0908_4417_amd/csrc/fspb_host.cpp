@@ -80,12 +80,13 @@ struct Layout {
 
 /*
  * Pinned host buffers for plan uploads.  fspb_plan_create writes a plan's
- * upload image into one of them and sends it with a single asynchronous copy
- * on the null stream, so the host does not wait for the device (which may
- * still be busy with an earlier plan in the same workspace).  A buffer is
- * reused once the event recorded after its copy has completed; at most
- * kStagingPerDevice buffers exist per device (beyond that, creation waits for
- * the oldest copy), and they are kept until the process ends.
+ * upload image into one of them and keeps it claimed; the plan's first
+ * fspb_raytrace (or fspb_batch_create) sends it with a single asynchronous
+ * copy on that call's stream and releases the claim.  A released buffer is
+ * reused once the event recorded after its copy has completed.  When
+ * kStagingPerDevice buffers exist on a device, creation waits for a released
+ * one rather than allocating (unless every buffer is claimed by a plan whose
+ * upload is still pending); buffers are kept until the process ends.
  */
 struct Staging {
     void *host = nullptr;
@@ -103,6 +104,12 @@ bool stage_idle(Staging &b)
     const hipError_t e = hipEventQuery(b.done);
     if (e == hipErrorNotReady) (void)hipGetLastError();   // not an error: clear it
     return e != hipErrorNotReady;
+}
+
+void stage_release(Staging *b)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    b->claimed = false;
 }
 
 /* erf table of the fill (built once). */
@@ -164,20 +171,34 @@ struct fspb_plan {
     bool timing = false;
     hipEvent_t ev[8] = {};
     bool have_trace_ev = false, have_dose_ev = false;
-    hipEvent_t upload_done = nullptr;   // recorded after the plan's upload (null stream)
+    Staging *upload = nullptr;          // claimed staging buffer of a pending upload
+    size_t upload_bytes = 0;            // its length: workspace bytes [0, upload_bytes)
     int64_t *nnz_host = nullptr;        // pinned slot the nonzero count is read into
     hipEvent_t nnz_ready = nullptr;     // recorded after that read
     ~fspb_plan()
     {
         for (hipEvent_t &e : ev)
             if (e) (void)hipEventDestroy(e);
-        if (upload_done) (void)hipEventDestroy(upload_done);
         if (nnz_ready) (void)hipEventDestroy(nnz_ready);
         if (nnz_host) slot_release(nnz_host);
+        if (upload) stage_release(upload);
     }
 };
 
 namespace {
+
+/* Enqueue a plan's pending upload (its pinned image) on `s`, then release the image. */
+fspb_status plan_upload(fspb_plan *p, hipStream_t s)
+{
+    if (!p->upload) return FSPB_OK;
+    FSPB_HIP(hipMemcpyAsync(static_cast<void *>(p->d_plan), p->upload->host, p->upload_bytes,
+                            hipMemcpyHostToDevice, s),
+             "upload plan");
+    FSPB_HIP(hipEventRecord(p->upload->done, s), "record upload");
+    stage_release(p->upload);
+    p->upload = nullptr;
+    return FSPB_OK;
+}
 
 fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams, const fspb_kernel *K)
 {
@@ -423,15 +444,6 @@ fspb_status stage_acquire(size_t bytes, int device, Staging **out)
     return FSPB_OK;
 }
 
-/* Releases a claimed staging buffer when it goes out of scope. */
-struct StageClaim {
-    Staging *b;
-    ~StageClaim()
-    {
-        std::lock_guard<std::mutex> lk(g_stage_mu);
-        b->claimed = false;
-    }
-};
 
 }  // namespace
 
@@ -697,20 +709,18 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     h.ext = reinterpret_cast<int2 *>(ws + L.ext);
     h.nnz = p->d_nnz;
 
-    // ---- every host-written array in one asynchronous copy of [0, L.upload) on the null
-    // stream, from a pinned image; fspb_raytrace and fspb_batch_create wait for its event
+    // ---- every host-written array goes into one pinned image of [0, L.upload); the first
+    // fspb_raytrace or fspb_batch_create copies it on its stream
     int dev = 0;
     FSPB_HIP(hipGetDevice(&dev), "get device");
-    FSPB_HIP(hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming), "create upload event");
     FSPB_HIP(hipEventCreateWithFlags(&p->nnz_ready, hipEventDisableTiming), "create count event");
     st = slot_acquire(&p->nnz_host);
     if (st != FSPB_OK) return st;
-    Staging *sb = nullptr;
-    st = stage_acquire(L.upload, dev, &sb);
+    st = stage_acquire(L.upload, dev, &p->upload);
     if (st != FSPB_OK) return st;
+    p->upload_bytes = L.upload;
     {
-        StageClaim claim{sb};
-        char *img = static_cast<char *>(sb->host);
+        char *img = static_cast<char *>(p->upload->host);
         std::memcpy(img + L.plan, &h, sizeof(PlanDev));
         std::memset(img + L.scal, 0, 64);   // nonzero count and overflow flag start at zero
         if (nbl > 0) std::memcpy(img + L.rec, p->recs.data(), sizeof(BeamletRec) * (size_t)nbl);
@@ -725,9 +735,6 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
             for (int m = 0; m < 3; ++m) std::memcpy(img + L.ctab + sizeof(float) * m * nc, src[m], sizeof(float) * nc);
             std::memcpy(img + L.atab, T->A, sizeof(float) * (size_t)T->n_theta * T->n_adepth);
         }
-        FSPB_HIP(hipMemcpyAsync(ws, img, L.upload, hipMemcpyHostToDevice, nullptr), "upload plan");
-        FSPB_HIP(hipEventRecord(sb->done, nullptr), "record upload");
-        FSPB_HIP(hipEventRecord(p->upload_done, nullptr), "record upload");
     }
     guard.p = nullptr;
     *out = p;
@@ -739,7 +746,8 @@ fspb_status fspb_raytrace(fspb_plan *p, void *stream)
     g_last_error.clear();
     if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    FSPB_HIP(hipStreamWaitEvent(s, p->upload_done, 0), "wait for the plan upload");
+    fspb_status us = plan_upload(p, s);
+    if (us != FSPB_OK) return us;
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[0], s), "record event");
     FSPB_HIP(fspb::launch_prep(p->d_plan, p->h, s), "launch prep");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[1], s), "record event");
@@ -1105,8 +1113,10 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
 
     // sizing pass: mask, tables, counts, row sums
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < n_plans; ++i)
-        FSPB_HIP(hipStreamWaitEvent(s, plans[i]->upload_done, 0), "wait for a plan upload");
+    for (int i = 0; i < n_plans; ++i) {
+        fspb_status us = plan_upload(plans[i], s);
+        if (us != FSPB_OK) return us;
+    }
     FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
     for (int st = 0; st < 4; ++st)
         if (b->total[st] > 0)
@@ -1540,7 +1550,13 @@ fspb_status fspb_plan_set_surrogate(fspb_plan *p, const fspb_surrogate *s)
     p->h.mlp_p = s ? s->params : nullptr;
     p->h.mlp_w2 = s ? s->w2 : nullptr;
     p->h.use_mlp = s ? 1 : 0;
-    FSPB_HIP(hipMemcpy(p->d_plan, &p->h, sizeof(PlanDev), hipMemcpyHostToDevice), "upload plan record");
+    if (p->upload) {   // not uploaded yet: the record goes with the rest of the image
+        std::memcpy(p->upload->host, &p->h, sizeof(PlanDev));
+    } else {
+        // the upload or a fill may still be in flight on any stream
+        FSPB_HIP(hipDeviceSynchronize(), "synchronise before replacing the plan record");
+        FSPB_HIP(hipMemcpy(p->d_plan, &p->h, sizeof(PlanDev), hipMemcpyHostToDevice), "upload plan record");
+    }
     return FSPB_OK;
 }
 

@@ -1,10 +1,11 @@
-"""Plan uploads: one asynchronous copy on the null stream from a pooled pinned
-buffer, which fspb_raytrace orders its stream after.
+"""Plan uploads: the host-written part of a plan's workspace is assembled in a
+pooled pinned buffer at creation and copied by the plan's first ray trace, on
+that call's stream.
 
 Plans created back to back while the default stream is still busy (more
-plans than pooled buffers, so creation also waits for an earlier copy), then
-traced and filled on a non-blocking stream, must give bit-identical D to the
-same plans created and run one at a time.
+pending plans than the pool keeps, so the pool must grow), then traced and
+filled on a non-blocking stream, must give bit-identical D to the same plans
+created and run one at a time.
 """
 import numpy as np
 import pytest
