@@ -106,8 +106,7 @@ struct alignas(16) OutDev {
 hipError_t launch_prep(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
 hipError_t launch_raytrace(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
 hipError_t launch_count(const PlanDev *dplan, const PlanDev &h, hipStream_t s);
-hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h,
-                              hipStream_t s);
+hipError_t launch_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s);
 /* Fill rows row0 .. row0 + n_rows - 1 (dout->row0 must equal row0). */
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, int row0, int n_rows,
                        hipStream_t s);
@@ -131,7 +130,7 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
 
 /* Batched launches over n_plans plans (persistent grids). */
 hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,
-                             int grid, hipStream_t s);   // stage 0 prep, 1 raytrace, 2 count, 3 rowsum
+                             int grid, hipStream_t s);   // stage 0 prep, 1 raytrace, 2 count
 hipError_t launch_batch_scan(const PlanDev *const *plans, const OutDev *outs, int n_plans, hipStream_t s);
 hipError_t launch_batch_reset(int *counters, int n, hipStream_t s);
 hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const OutDev *outs, const int2 *items,

@@ -784,7 +784,7 @@ fspb_status fspb_dose_coeffs(fspb_plan *p, int64_t *indptr, int32_t *indices, fl
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[3], s), "record event");
     FSPB_HIP(fspb::launch_count(p->d_plan, p->h, s), "launch count");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[4], s), "record event");
-    FSPB_HIP(fspb::launch_rowsum_scan(p->d_plan, p->d_out, p->h, s), "launch scan");
+    FSPB_HIP(fspb::launch_scan(p->d_plan, p->d_out, p->h, s), "launch scan");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[5], s), "record event");
     FSPB_HIP(hipMemcpyAsync(p->nnz_host, p->d_nnz, sizeof(int64_t), hipMemcpyDeviceToHost, s), "read nnz");
     FSPB_HIP(hipEventRecord(p->nnz_ready, s), "record count event");
@@ -938,17 +938,20 @@ int64_t two_digits(int64_t v)
 
 }  // namespace
 
+// wave stages of a batch before the scan: mask rows, ray traces, counts
+constexpr int kWaveStages = 3;
+
 struct fspb_batch {
     std::vector<fspb_plan *> plans;
     int32_t n = 0;
     // device arrays (caller workspace)
     const PlanDev **d_plans = nullptr;
     OutDev *d_outs = nullptr;
-    int64_t *d_start[4] = {};     // item prefix per wave stage: rows, beamlets, tiles, beamlets
+    int64_t *d_start[kWaveStages] = {};   // item prefix per wave stage: rows, beamlets, beamlets
     int2 *d_items[2] = {};        // fill items: longest first, plan order
     int *d_counter = nullptr;
     int32_t n_items = 0;
-    int64_t total[4] = {};
+    int64_t total[kWaveStages] = {};
     std::vector<int64_t> nnz;
     std::vector<OutDev> outs;
     std::vector<bool> bound;
@@ -986,7 +989,7 @@ int wave_grid(const fspb_batch *b, int64_t items)
 fspb_status enqueue_stages(fspb_batch *b, hipStream_t s, bool with_fill)
 {
     FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
-    for (int st = 0; st < 4; ++st) {
+    for (int st = 0; st < kWaveStages; ++st) {
         if (b->total[st] == 0) continue;
         FSPB_HIP(fspb::launch_batch_wave(st, b->d_plans, b->d_start[st], b->n, wave_grid(b, b->total[st]), s),
                  "launch batch stage");
@@ -1062,8 +1065,8 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
     };
     const size_t o_plans = take(sizeof(PlanDev *) * n_plans);
     const size_t o_outs = take(sizeof(OutDev) * n_plans);
-    size_t o_start[4];
-    for (int st = 0; st < 4; ++st) o_start[st] = take(sizeof(int64_t) * (n_plans + 1));
+    size_t o_start[kWaveStages];
+    for (int st = 0; st < kWaveStages; ++st) o_start[st] = take(sizeof(int64_t) * (n_plans + 1));
     const size_t o_items0 = take(sizeof(int2) * (size_t)std::max<int64_t>(beamlets, 1));
     const size_t o_items1 = take(sizeof(int2) * (size_t)std::max<int64_t>(beamlets, 1));
     const size_t o_counter = take(64);
@@ -1081,7 +1084,7 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
     char *ws = static_cast<char *>(workspace);
     b->d_plans = reinterpret_cast<const PlanDev **>(ws + o_plans);
     b->d_outs = reinterpret_cast<OutDev *>(ws + o_outs);
-    for (int st = 0; st < 4; ++st) b->d_start[st] = reinterpret_cast<int64_t *>(ws + o_start[st]);
+    for (int st = 0; st < kWaveStages; ++st) b->d_start[st] = reinterpret_cast<int64_t *>(ws + o_start[st]);
     b->d_items[0] = reinterpret_cast<int2 *>(ws + o_items0);
     b->d_items[1] = reinterpret_cast<int2 *>(ws + o_items1);
     b->d_counter = reinterpret_cast<int *>(ws + o_counter);
@@ -1090,8 +1093,8 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
     FSPB_HIP(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev), "query compute units");
 
     std::vector<const PlanDev *> pp(n_plans);
-    std::vector<int64_t> start[4];
-    for (int st = 0; st < 4; ++st) start[st].assign(n_plans + 1, 0);
+    std::vector<int64_t> start[kWaveStages];
+    for (int st = 0; st < kWaveStages; ++st) start[st].assign(n_plans + 1, 0);
     b->outs.assign(n_plans, OutDev{});
     b->bound.assign(n_plans, false);
     for (int i = 0; i < n_plans; ++i) {
@@ -1099,15 +1102,14 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
         pp[i] = plans[i]->d_plan;
         start[0][i + 1] = start[0][i] + (int64_t)h.ny * h.nz;
         start[1][i + 1] = start[1][i] + h.n_beamlets;
-        start[2][i + 1] = start[2][i] + h.n_tiles;
-        start[3][i + 1] = start[3][i] + h.n_beamlets;
+        start[2][i + 1] = start[2][i] + h.n_beamlets;
         b->max_terms = std::max(b->max_terms, h.n_terms);
         b->lds = std::max(b->lds, fspb::fill_shared_bytes(h));
         b->outs[i].overflow = plans[i]->d_overflow;
     }
-    for (int st = 0; st < 4; ++st) b->total[st] = start[st][n_plans];
+    for (int st = 0; st < kWaveStages; ++st) b->total[st] = start[st][n_plans];
     FSPB_HIP(hipMemcpy(b->d_plans, pp.data(), sizeof(PlanDev *) * n_plans, hipMemcpyHostToDevice), "upload plan table");
-    for (int st = 0; st < 4; ++st)
+    for (int st = 0; st < kWaveStages; ++st)
         FSPB_HIP(hipMemcpy(b->d_start[st], start[st].data(), sizeof(int64_t) * (n_plans + 1), hipMemcpyHostToDevice),
                  "upload item ranges");
 
@@ -1118,7 +1120,7 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
         if (us != FSPB_OK) return us;
     }
     FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
-    for (int st = 0; st < 4; ++st)
+    for (int st = 0; st < kWaveStages; ++st)
         if (b->total[st] > 0)
             FSPB_HIP(fspb::launch_batch_wave(st, b->d_plans, b->d_start[st], n_plans, wave_grid(b, b->total[st]), s),
                      "launch batch stage");

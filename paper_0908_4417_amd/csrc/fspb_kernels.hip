@@ -5,9 +5,8 @@
  *               voxels above rho_min                          -- one wave per grid row
  *   k_raytrace  radiological-depth table of every beamlet (Sec. 2.2): Siddon
  *               crossings in FP64, compensated FP32 path sums  -- one wave per beamlet
- *   k_count     VOI members per tile of 64 grid rows (Sec. 2.1 VOI rule)
- *                                                              -- one wave per tile
- *   k_rowsum    nonzeros per beamlet row                       -- one wave per beamlet
+ *   k_count     VOI members per tile of 64 grid rows (Sec. 2.1 VOI rule) and
+ *               per beamlet row                                -- one wave per beamlet
  *   k_scan      exclusive scan -> CSR row pointers              -- one workgroup
  *   k_fill      Eq. 2-3 at every VOI voxel, compacted with wave ballots into
  *               ascending CSR columns                          -- one workgroup per beamlet
@@ -284,28 +283,44 @@ __device__ inline RowAffine row_affine(const PlanDev &P, const BeamletRec &R, in
 }
 
 /*
+ * The VOI of a beamlet as four inequalities c0 + c1 x <= 0 in the column x
+ * of a grid row: c1 (and 1/c1) are the same for every row of the beamlet.
+ */
+struct RowSolver { double c1[4], r1[4]; };
+
+__device__ inline RowSolver row_solver(const PlanDev &P, const BeamletRec &R)
+{
+    const double t1 = P.sp[0] * R.e[0];
+    const double U1 = P.sp[0] * R.eu[0];
+    const double V1 = P.sp[0] * R.ev[0];
+    RowSolver q;
+    q.c1[0] = U1 - R.cu_sad * t1;
+    q.c1[1] = -U1 - R.cu_sad * t1;
+    q.c1[2] = V1 - R.cv_sad * t1;
+    q.c1[3] = -V1 - R.cv_sad * t1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q.r1[c] = q.c1[c] != 0.0 ? 1.0 / q.c1[c] : 0.0;
+    return q;
+}
+
+/*
  * Columns [lo, hi] of grid row (iy, iz) whose centres satisfy
  * |U| <= (cu/SAD) t' and |V| <= (cv/SAD) t' (the VOI, which is convex, so an
  * interval), intersected with the row's extent of voxels above rho_min.
  * Solved in FP64 from the four linear inequalities.  Returns false if empty.
  */
-__device__ inline bool row_span(const PlanDev &P, const BeamletRec &R, int iy, int iz, int &lo, int &hi,
-                                RowAffine &a)
+__device__ inline bool row_span(const PlanDev &P, const BeamletRec &R, const RowSolver &q, int iy, int iz,
+                                int &lo, int &hi, RowAffine &a)
 {
     a = row_affine(P, R, iy, iz);
-    const double t1 = P.sp[0] * R.e[0];
-    const double U1 = P.sp[0] * R.eu[0];
-    const double V1 = P.sp[0] * R.ev[0];
     const double c0[4] = {a.U0 - R.cu_sad * a.t0, -a.U0 - R.cu_sad * a.t0,
                           a.V0 - R.cv_sad * a.t0, -a.V0 - R.cv_sad * a.t0};
-    const double c1[4] = {U1 - R.cu_sad * t1, -U1 - R.cu_sad * t1,
-                          V1 - R.cv_sad * t1, -V1 - R.cv_sad * t1};
     double xlo = -1.0, xhi = (double)P.nx;          // already clipped to the grid
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {                   // c0 + c1 x <= 0
-        if (c1[c] > 0.0) xhi = fmin(xhi, -c0[c] / c1[c]);
-        else if (c1[c] < 0.0) xlo = fmax(xlo, -c0[c] / c1[c]);
+        if (q.c1[c] > 0.0) xhi = fmin(xhi, -c0[c] * q.r1[c]);
+        else if (q.c1[c] < 0.0) xlo = fmax(xlo, -c0[c] * q.r1[c]);
         else ok = ok && !(c0[c] > 0.0);
     }
     const int2 ext = P.ext[iz * P.ny + iy];
@@ -329,49 +344,50 @@ __device__ inline int popcount_range(const uint32_t *row, int lo, int hi)
     return c;
 }
 
-/* VOI members of tile t (64 grid rows of one beamlet); one wave. */
-__device__ void count_tile(const PlanDev &P, int t)
+/* VOI members of grid row r (of n_rows) of a beamlet: lane work of count_beamlet. */
+__device__ inline int count_row(const PlanDev &P, const BeamletRec &R, const RowSolver &q, int r, int n_rows)
+{
+    if (r >= n_rows) return 0;
+    const int iy = R.iy0 + r % R.n_iy, iz = R.iz0 + r / R.n_iy;
+    int lo, hi;
+    RowAffine a;
+    if (!row_span(P, R, q, iy, iz, lo, hi, a)) return 0;
+    return popcount_range(P.bits + (size_t)(iz * P.ny + iy) * P.wpr, lo, hi);
+}
+
+/*
+ * VOI members of every tile of beamlet j (64 grid rows each, lane = row) and
+ * of its whole row of D; one wave, two tiles per step so that the loads of
+ * both are in flight together.
+ */
+__device__ void count_beamlet(const PlanDev &P, int j)
 {
     const int lane = lane_id();
-    const BeamletRec &R = P.rec[P.tile_beamlet[t]];
-    const int r = (t - R.tile0) * kRowsPerTile + lane;
-    int cnt = 0;
-    if (r < R.n_iy * R.n_iz) {
-        const int iy = R.iy0 + r % R.n_iy, iz = R.iz0 + r / R.n_iy;
-        int lo, hi;
-        RowAffine a;
-        if (row_span(P, R, iy, iz, lo, hi, a))
-            cnt = popcount_range(P.bits + (size_t)(iz * P.ny + iy) * P.wpr, lo, hi);
+    const BeamletRec &R = P.rec[j];
+    const RowSolver q = row_solver(P, R);
+    const int n_rows = R.n_iy * R.n_iz, n_tiles = R.n_tiles;
+    int64_t total = 0;
+    for (int t = 0; t < n_tiles; t += 2) {
+        const int r = t * kRowsPerTile + lane;
+        const int c0 = wave_sum(count_row(P, R, q, r, n_rows));
+        const int c1 = wave_sum(count_row(P, R, q, r + kRowsPerTile, n_rows));
+        if (lane == 0) {
+            P.tile_count[R.tile0 + t] = c0;
+            if (t + 1 < n_tiles) P.tile_count[R.tile0 + t + 1] = c1;
+        }
+        total += c0 + c1;
     }
-    cnt = wave_sum(cnt);
-    if (lane == 0) P.tile_count[t] = cnt;
+    if (lane == 0) P.row_nnz[j] = total;
 }
 
 __global__ __launch_bounds__(kBlock) void k_count(const PlanDev *__restrict__ plans)
 {
     const PlanDev &P = plans[0];
-    const int t = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (t < P.n_tiles) count_tile(P, t);
+    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (j < P.n_beamlets) count_beamlet(P, j);
 }
 
 /* ---------------------------------------------------------------- scan */
-
-/* Nonzeros of beamlet row j from its tile counts; one wave. */
-__device__ void rowsum_beamlet(const PlanDev &P, int j)
-{
-    const BeamletRec &R = P.rec[j];
-    int64_t s = 0;
-    for (int k = lane_id(); k < R.n_tiles; k += kWave) s += P.tile_count[R.tile0 + k];
-    s = wave_sum(s);
-    if (lane_id() == 0) P.row_nnz[j] = s;
-}
-
-__global__ __launch_bounds__(kBlock) void k_rowsum(const PlanDev *__restrict__ plans)
-{
-    const PlanDev &P = plans[0];
-    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (j < P.n_beamlets) rowsum_beamlet(P, j);
-}
 
 constexpr int kScanBlock = 1024;
 
@@ -688,7 +704,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         if (r < n_rows) {
             const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
             RowAffine a;
-            if (row_span(P, R, iy, iz, lo, hi, a)) {
+            const RowSolver q = row_solver(P, R);
+            if (row_span(P, R, q, iy, iz, lo, hi, a)) {
                 grow = iz * ny + iy;
                 const double x = (double)lo;
                 s_lo = (float)(a.t0 + x * t1 - tA);
@@ -835,8 +852,7 @@ __global__ __launch_bounds__(kBlock) void kp_wave(const PlanDev *const *__restri
         const int i = (int)(w - start[p]);
         if (STAGE == 0) prep_row(P, i);
         else if (STAGE == 1) raytrace_beamlet(P, i);
-        else if (STAGE == 2) count_tile(P, i);
-        else rowsum_beamlet(P, i);
+        else count_beamlet(P, i);
     }
 }
 
@@ -896,17 +912,13 @@ hipError_t launch_raytrace(const PlanDev *dplan, const PlanDev &h, hipStream_t s
 
 hipError_t launch_count(const PlanDev *dplan, const PlanDev &h, hipStream_t s)
 {
-    if (h.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count, dim3(blocks_for(h.n_tiles, kWavesPerBlock)), dim3(kBlock), 0, s, dplan);
+    if (h.n_beamlets == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count, dim3(blocks_for(h.n_beamlets, kWavesPerBlock)), dim3(kBlock), 0, s, dplan);
     return hipGetLastError();
 }
 
-hipError_t launch_rowsum_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)
+hipError_t launch_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rowsum, dim3(blocks_for(h.n_beamlets, kWavesPerBlock)), dim3(kBlock), 0, s,
-                       dplan);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, dplan, dout);
     return hipGetLastError();
 }
@@ -926,8 +938,7 @@ hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64
     switch (stage) {
     case 0: hipLaunchKernelGGL(kp_wave<0>, g, b, 0, s, plans, start, n_plans); break;
     case 1: hipLaunchKernelGGL(kp_wave<1>, g, b, 0, s, plans, start, n_plans); break;
-    case 2: hipLaunchKernelGGL(kp_wave<2>, g, b, 0, s, plans, start, n_plans); break;
-    default: hipLaunchKernelGGL(kp_wave<3>, g, b, 0, s, plans, start, n_plans); break;
+    default: hipLaunchKernelGGL(kp_wave<2>, g, b, 0, s, plans, start, n_plans); break;
     }
     return hipGetLastError();
 }
