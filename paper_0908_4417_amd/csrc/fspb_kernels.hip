@@ -270,37 +270,57 @@ __global__ __launch_bounds__(kBlock) void k_raytrace(const PlanDev *__restrict__
 /* FP64 affine coefficients of t', U = (P-S).eu', V = (P-S).ev' along a grid row. */
 struct RowAffine { double t0, U0, V0; };
 
-__device__ inline RowAffine row_affine(const PlanDev &P, const BeamletRec &R, int iy, int iz)
-{
-    const double wx = P.org[0] - R.S[0];
-    const double wy = P.org[1] + iy * P.sp[1] - R.S[1];
-    const double wz = P.org[2] + iz * P.sp[2] - R.S[2];
-    RowAffine a;
-    a.t0 = wx * R.e[0] + wy * R.e[1] + wz * R.e[2];
-    a.U0 = wx * R.eu[0] + wy * R.eu[1] + wz * R.eu[2];
-    a.V0 = wx * R.ev[0] + wy * R.ev[1] + wz * R.ev[2];
-    return a;
-}
-
 /*
- * The VOI of a beamlet as four inequalities c0 + c1 x <= 0 in the column x
- * of a grid row: c1 (and 1/c1) are the same for every row of the beamlet.
+ * The FP64 beamlet and grid quantities the VOI row interval needs, read once
+ * per beamlet (or tile) into registers, and the four inequalities
+ * c0 + c1 x <= 0 in the column x of a grid row: c1 (and 1/c1) are the same for
+ * every row of the beamlet.
  */
-struct RowSolver { double c1[4], r1[4]; };
+struct RowGeom {
+    double wx, oy, oz, sy, sz, Sy, Sz;    // org0 - S0; org1, org2; spacing y, z; S1, S2
+    double e[3], eu[3], ev[3], cu, cv;
+    double c1[4], r1[4];
+};
 
-__device__ inline RowSolver row_solver(const PlanDev &P, const BeamletRec &R)
+__device__ inline RowGeom row_geom(const PlanDev &P, const BeamletRec &R)
 {
+    RowGeom G;
+    G.wx = P.org[0] - R.S[0];
+    G.oy = P.org[1];
+    G.oz = P.org[2];
+    G.sy = P.sp[1];
+    G.sz = P.sp[2];
+    G.Sy = R.S[1];
+    G.Sz = R.S[2];
+    for (int k = 0; k < 3; ++k) {
+        G.e[k] = R.e[k];
+        G.eu[k] = R.eu[k];
+        G.ev[k] = R.ev[k];
+    }
+    G.cu = R.cu_sad;
+    G.cv = R.cv_sad;
     const double t1 = P.sp[0] * R.e[0];
     const double U1 = P.sp[0] * R.eu[0];
     const double V1 = P.sp[0] * R.ev[0];
-    RowSolver q;
-    q.c1[0] = U1 - R.cu_sad * t1;
-    q.c1[1] = -U1 - R.cu_sad * t1;
-    q.c1[2] = V1 - R.cv_sad * t1;
-    q.c1[3] = -V1 - R.cv_sad * t1;
+    G.c1[0] = U1 - G.cu * t1;
+    G.c1[1] = -U1 - G.cu * t1;
+    G.c1[2] = V1 - G.cv * t1;
+    G.c1[3] = -V1 - G.cv * t1;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) q.r1[c] = q.c1[c] != 0.0 ? 1.0 / q.c1[c] : 0.0;
-    return q;
+    for (int c = 0; c < 4; ++c) G.r1[c] = G.c1[c] != 0.0 ? 1.0 / G.c1[c] : 0.0;
+    return G;
+}
+
+__device__ inline RowAffine row_affine(const RowGeom &G, int iy, int iz)
+{
+    const double wx = G.wx;
+    const double wy = fma((double)iy, G.sy, G.oy) - G.Sy;
+    const double wz = fma((double)iz, G.sz, G.oz) - G.Sz;
+    RowAffine a;
+    a.t0 = wx * G.e[0] + wy * G.e[1] + wz * G.e[2];
+    a.U0 = wx * G.eu[0] + wy * G.eu[1] + wz * G.eu[2];
+    a.V0 = wx * G.ev[0] + wy * G.ev[1] + wz * G.ev[2];
+    return a;
 }
 
 /*
@@ -309,25 +329,25 @@ __device__ inline RowSolver row_solver(const PlanDev &P, const BeamletRec &R)
  * interval), intersected with the row's extent of voxels above rho_min.
  * Solved in FP64 from the four linear inequalities.  Returns false if empty.
  */
-__device__ inline bool row_span(const PlanDev &P, const BeamletRec &R, const RowSolver &q, int iy, int iz,
-                                int &lo, int &hi, RowAffine &a)
+__device__ inline bool row_span(const RowGeom &G, const int2 *__restrict__ ext_rows, int nx, int ny, int iy,
+                                int iz, int &lo, int &hi, RowAffine &a)
 {
-    a = row_affine(P, R, iy, iz);
-    const double c0[4] = {a.U0 - R.cu_sad * a.t0, -a.U0 - R.cu_sad * a.t0,
-                          a.V0 - R.cv_sad * a.t0, -a.V0 - R.cv_sad * a.t0};
-    double xlo = -1.0, xhi = (double)P.nx;          // already clipped to the grid
+    a = row_affine(G, iy, iz);
+    const double c0[4] = {a.U0 - G.cu * a.t0, -a.U0 - G.cu * a.t0,
+                          a.V0 - G.cv * a.t0, -a.V0 - G.cv * a.t0};
+    double xlo = -1.0, xhi = (double)nx;            // already clipped to the grid
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {                   // c0 + c1 x <= 0
-        if (q.c1[c] > 0.0) xhi = fmin(xhi, -c0[c] * q.r1[c]);
-        else if (q.c1[c] < 0.0) xlo = fmax(xlo, -c0[c] * q.r1[c]);
+        if (G.c1[c] > 0.0) xhi = fmin(xhi, -c0[c] * G.r1[c]);
+        else if (G.c1[c] < 0.0) xlo = fmax(xlo, -c0[c] * G.r1[c]);
         else ok = ok && !(c0[c] > 0.0);
     }
-    const int2 ext = P.ext[iz * P.ny + iy];
-    xlo = fmin(xlo, (double)P.nx);                  // both bounds now in [-1, nx]
+    const int2 ext = ext_rows[iz * ny + iy];
+    xlo = fmin(xlo, (double)nx);                    // both bounds now in [-1, nx]
     xhi = fmax(xhi, -1.0);
     lo = max((int)ceil(xlo), max(ext.x, 0));
-    hi = min((int)floor(xhi), min(ext.y, P.nx - 1));
+    hi = min((int)floor(xhi), min(ext.y, nx - 1));
     return ok && lo <= hi;
 }
 
@@ -344,38 +364,67 @@ __device__ inline int popcount_range(const uint32_t *row, int lo, int hi)
     return c;
 }
 
-/* VOI members of grid row r (of n_rows) of a beamlet: lane work of count_beamlet. */
-__device__ inline int count_row(const PlanDev &P, const BeamletRec &R, const RowSolver &q, int r, int n_rows)
+/* Grid-row cursor (iy, iz) of row r of a beamlet's n_iy-wide row block, stepped by a fixed count. */
+struct RowCursor {
+    int iy, iz;
+    __device__ void step(int dy, int dz, int n_iy)
+    {
+        iy += dy;
+        iz += dz;
+        if (iy >= n_iy) {
+            iy -= n_iy;
+            ++iz;
+        }
+    }
+};
+
+/* VOI members of grid row (iy0 + c.iy, iz0 + c.iz), or 0 when r >= n_rows: lane work of count_beamlet. */
+__device__ inline int count_row(const RowGeom &G, const uint32_t *__restrict__ bits,
+                                const int2 *__restrict__ ext, int nx, int ny, int wpr, int iy0, int iz0,
+                                const RowCursor &c, bool in)
 {
-    if (r >= n_rows) return 0;
-    const int iy = R.iy0 + r % R.n_iy, iz = R.iz0 + r / R.n_iy;
+    if (!in) return 0;
+    const int iy = iy0 + c.iy, iz = iz0 + c.iz;
     int lo, hi;
     RowAffine a;
-    if (!row_span(P, R, q, iy, iz, lo, hi, a)) return 0;
-    return popcount_range(P.bits + (size_t)(iz * P.ny + iy) * P.wpr, lo, hi);
+    if (!row_span(G, ext, nx, ny, iy, iz, lo, hi, a)) return 0;
+    return popcount_range(bits + (size_t)(iz * ny + iy) * wpr, lo, hi);
 }
 
 /*
  * VOI members of every tile of beamlet j (64 grid rows each, lane = row) and
  * of its whole row of D; one wave, two tiles per step so that the loads of
- * both are in flight together.
+ * both are in flight together.  Everything the loop reads from the plan and
+ * the beamlet record is taken into registers first.
  */
 __device__ void count_beamlet(const PlanDev &P, int j)
 {
     const int lane = lane_id();
     const BeamletRec &R = P.rec[j];
-    const RowSolver q = row_solver(P, R);
-    const int n_rows = R.n_iy * R.n_iz, n_tiles = R.n_tiles;
+    const RowGeom G = row_geom(P, R);
+    const int n_iy = R.n_iy, iy0 = R.iy0, iz0 = R.iz0, tile0 = R.tile0, n_tiles = R.n_tiles;
+    const int n_rows = n_iy * R.n_iz;
+    const int nx = P.nx, ny = P.ny, wpr = P.wpr;
+    const uint32_t *__restrict__ bits = P.bits;
+    const int2 *__restrict__ ext = P.ext;
+    int32_t *__restrict__ tile_count = P.tile_count;
+    // rows r and r + 64 of this lane, stepped by 128 rows per iteration
+    RowCursor ca{lane % n_iy, lane / n_iy};
+    RowCursor cb{(lane + kRowsPerTile) % n_iy, (lane + kRowsPerTile) / n_iy};
+    const int dy = (2 * kRowsPerTile) % n_iy, dz = (2 * kRowsPerTile) / n_iy;
     int64_t total = 0;
     for (int t = 0; t < n_tiles; t += 2) {
         const int r = t * kRowsPerTile + lane;
-        const int c0 = wave_sum(count_row(P, R, q, r, n_rows));
-        const int c1 = wave_sum(count_row(P, R, q, r + kRowsPerTile, n_rows));
+        const int x0 = count_row(G, bits, ext, nx, ny, wpr, iy0, iz0, ca, r < n_rows);
+        const int x1 = count_row(G, bits, ext, nx, ny, wpr, iy0, iz0, cb, r + kRowsPerTile < n_rows);
+        const int c0 = wave_sum(x0), c1 = wave_sum(x1);
         if (lane == 0) {
-            P.tile_count[R.tile0 + t] = c0;
-            if (t + 1 < n_tiles) P.tile_count[R.tile0 + t + 1] = c1;
+            tile_count[tile0 + t] = c0;
+            if (t + 1 < n_tiles) tile_count[tile0 + t + 1] = c1;
         }
         total += c0 + c1;
+        ca.step(dy, dz, n_iy);
+        cb.step(dy, dz, n_iy);
     }
     if (lane == 0) P.row_nnz[j] = total;
 }
@@ -704,8 +753,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         if (r < n_rows) {
             const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
             RowAffine a;
-            const RowSolver q = row_solver(P, R);
-            if (row_span(P, R, q, iy, iz, lo, hi, a)) {
+            const RowGeom G = row_geom(P, R);
+            if (row_span(G, P.ext, P.nx, P.ny, iy, iz, lo, hi, a)) {
                 grow = iz * ny + iy;
                 const double x = (double)lo;
                 s_lo = (float)(a.t0 + x * t1 - tA);
