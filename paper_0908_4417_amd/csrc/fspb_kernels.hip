@@ -229,7 +229,8 @@ __device__ void raytrace_trilinear(const PlanDev &P, const BeamletRec &R, float 
     }
 }
 
-__device__ void raytrace_beamlet(const PlanDev &P, int j)
+// inlined: as a call it held k_raytrace at 196 VGPRs (two waves per SIMD), inlined it needs 90
+__device__ __attribute__((always_inline)) inline void raytrace_beamlet(const PlanDev &P, int j)
 {
     const int lane = lane_id();
     const BeamletRec &R = P.rec[j];
@@ -443,27 +444,42 @@ constexpr int kScanBlock = 1024;
 /* Exclusive scan of row_nnz into indptr[0..n]; indptr[n] = nnz.  One workgroup of kScanBlock. */
 __device__ void scan_plan(const PlanDev &P, int64_t *indptr)
 {
+    // each thread takes kScanPer consecutive rows per pass, so one pass covers 8192 rows and
+    // all of its loads are issued together
+    constexpr int kScanPer = 8;
     __shared__ int64_t wsum[kScanBlock / kWave];
     __shared__ int64_t carry_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+    const int n = P.n_beamlets;
+    const int64_t *__restrict__ row_nnz = P.row_nnz;
     if (tid == 0) carry_s = 0;
     __syncthreads();
-    for (int base = 0; base < P.n_beamlets; base += kScanBlock) {
-        const int i = base + tid;
-        const int64_t v = i < P.n_beamlets ? P.row_nnz[i] : 0;
-        const int64_t inc = wave_incl_scan(v);
+    for (int base = 0; base < n; base += kScanBlock * kScanPer) {
+        const int i0 = base + tid * kScanPer;
+        int64_t v[kScanPer], s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = i0 + k < n ? row_nnz[i0 + k] : 0;
+            s += v[k];
+        }
+        const int64_t inc = wave_incl_scan(s);
         if (lane == kWave - 1) wsum[wave] = inc;
         __syncthreads();
         int64_t woff = 0;
         for (int w = 0; w < wave; ++w) woff += wsum[w];
         const int64_t carry = carry_s;
-        if (i < P.n_beamlets) indptr[i] = carry + woff + inc - v;
+        int64_t e = carry + woff + inc - s;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < n) indptr[i0 + k] = e;
+            e += v[k];
+        }
         __syncthreads();
         if (tid == kScanBlock - 1) carry_s = carry + woff + inc;
         __syncthreads();
     }
     if (tid == 0) {
-        indptr[P.n_beamlets] = carry_s;
+        indptr[n] = carry_s;
         P.nnz[0] = carry_s;
     }
 }

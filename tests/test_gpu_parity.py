@@ -181,6 +181,21 @@ def test_edge_cases(torch_gpu, oracle_lib):
     _full_compare(oracle_lib, prob3)
 
 
+def test_more_than_8192_beamlets(torch_gpu, oracle_lib):
+    """10,000 beamlet rows: the row-pointer scan takes more than one pass."""
+    g = fi.water_phantom((24, 24, 24), (0.5, 0.5, 0.5))
+    k = fi.default_kernel(4)
+    k.cutoff_u = k.cutoff_v = 0.3
+    beams = [fi.Beam(0.0, (0.0, 0.0, 0.0), 100.0, 0.1, 0.1, 100, 100, -4.95, -4.95)]
+    prob = fi.Problem("many", g, beams, k)
+    _say("parity: 10,000 beamlets on a 24^3 grid")
+    plan, csr, ora, r = _full_compare(oracle_lib, prob)
+    assert plan.n_beamlets == 10000
+    counts = np.diff(csr.indptr.cpu().numpy())
+    assert (counts > 0).sum() > 8192
+    _say(f"  nnz={csr.nnz} max_rel={r['max_rel']:.2e} band={r['band_mismatches']}")
+
+
 def test_state_and_capacity_errors(torch_gpu):
     import ctypes as C
     import torch
