@@ -1050,12 +1050,8 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
     }
     if (!workspace && !workspace_needed) return fail(FSPB_ERR_INVALID, "workspace and workspace_needed are both NULL");
 
-    int64_t beamlets = 0, rows = 0, tiles = 0;
-    for (int i = 0; i < n_plans; ++i) {
-        beamlets += plans[i]->h.n_beamlets;
-        rows += (int64_t)plans[i]->h.ny * plans[i]->h.nz;
-        tiles += plans[i]->h.n_tiles;
-    }
+    int64_t beamlets = 0;
+    for (int i = 0; i < n_plans; ++i) beamlets += plans[i]->h.n_beamlets;
     if (beamlets >= (int64_t)1 << 31) return fail(FSPB_ERR_INVALID, "too many beamlets in the batch");
     size_t off = 0;
     auto take = [&](size_t bytes) {
