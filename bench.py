@@ -78,8 +78,9 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_calibration_bytes": n * 4, "dispatches": 3}), flush=True)
 
 
-def traffic_from_profile(kernel_name, workload):
-    """HBM bytes per fill launch from committed rocprofv3 counter summaries, if current."""
+def fill_profile(workload):
+    """Committed rocprofv3 counter figures of the fill (profiles/fill_traffic.json), if they
+    were taken on this workload with the current fill sources; else None."""
     path = os.path.join(ROOT, "profiles", "fill_traffic.json")
     if not os.path.exists(path):
         return None
@@ -91,7 +92,30 @@ def traffic_from_profile(kernel_name, workload):
     from paper_0908_4417_amd import build as b
     if d.get("kernel_source_sha") != b.kernel_source_sha() or d.get("workload") != workload:
         return None
-    return d.get("bytes_per_launch")
+    return d
+
+
+def traffic_from_profile(kernel_name, workload):
+    """HBM bytes per fill launch from committed rocprofv3 counter summaries, if current."""
+    d = fill_profile(workload)
+    return None if d is None else d.get("bytes_per_launch")
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x one wave64 instruction per 4 cycles x 2.4 GHz, in lane
+# instructions per second (packed FP32 is kept out of the code objects)
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+
+
+def valu_roofline(workload, fill_s):
+    """The fill against its real bound: VALU instructions per launch (SQ_INSTS_VALU from the
+    committed counter profile) over the fill time measured here."""
+    d = fill_profile(workload)
+    if d is None or not d.get("valu_insts_per_launch"):
+        return None
+    achieved = d["valu_insts_per_launch"] * 64 / fill_s
+    return {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(VALU_PEAK_LANE_INSTR / 1e12, 2),
+            "unit": "T VALU lane-instructions/s", "frac": round(achieved / VALU_PEAK_LANE_INSTR, 4),
+            "valu_insts_per_nonzero": round(d["valu_insts_per_launch"] * 64 / d["algorithmic_bytes_per_launch"] * 8, 1)}
 
 
 def cpu_baseline(prob, target_s, n_beamlets):
@@ -451,6 +475,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_from_profile("k_fill", workload),
                 "kernel": "k_fill", "bytes_per_launch": alg_bytes}
+    roofline_alu = valu_roofline(workload, fill_s)
 
     out = {
         "metric": METRIC,
@@ -469,6 +494,9 @@ def main():
                    "beamlets": desc.n_beamlets, "nnz": nnz, "plans_in_flight": P},
         "ms_per_step_one_stream": round(ms_step_serial, 4),
         "roofline": roofline,
+        # the fill is VALU-bound: the same launch against the VALU issue peak (null when the
+        # committed counter profile does not match these fill sources or this workload)
+        "roofline_alu": roofline_alu,
         "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
         # device time of fspb_raytrace + fspb_dose_coeffs (per-kernel medians), as the paper's T_GPU
         "device_ms_per_plan": round(sum(kt.values()), 4),
