@@ -20,6 +20,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fspb_device.h"
 #include "fspb_mlp_device.h"
 
@@ -590,7 +592,7 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
         const float isk = __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
         const float eu = edge_pair(etab, u, c.ha[i] * isk, isk);
         const float ev = edge_pair(etab, v, c.hb[i] * isk, isk);
-        L = fmaf(c.w4[i] * eu, ev, L);
+        L = i == 0 ? c.w4[0] * eu * ev : fmaf(c.w4[i] * eu, ev, L);   // no add of 0 for the first term
     }
     return A * L;
 }
@@ -625,7 +627,7 @@ __device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__re
         const float isk = kIsScale * __builtin_amdgcn_rcpf(c3);
         const float eu = edge_pair(etab, u, c2 * c.half_a * isk, isk);
         const float ev = edge_pair(etab, v, c2 * c.half_b * isk, isk);
-        L = fmaf(0.25f * c1 * eu, ev, L);
+        L = i == 0 ? 0.25f * c1 * eu * ev : fmaf(0.25f * c1 * eu, ev, L);
     }
     return A * L;
 }
@@ -790,17 +792,23 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         int rcur = 0;
         int64_t written = out0;
         // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
-        auto chunk = [&](const int p, const int rr) {
+        // a tile whose counted members equal its candidates (no masked voxel inside its rows)
+        // takes every candidate: no mask read, and member lanes are the low ones of the chunk
+        const bool dense = tile_count[tile0 + tl] == total;
+        auto chunk = [&](const int p, const int rr, auto dense_tag) {
+            constexpr bool DENSE = decltype(dense_tag)::value;
             const int k = p - __shfl(excl, rr, kWave);
             const int ix = __shfl(lo, rr, kWave) + k;
             const int gr = __shfl(grow, rr, kWave);
             bool member = false;
-            if (p < total) {
+            if (DENSE) {
+                member = p < total;
+            } else if (p < total) {
                 const uint32_t wo = ((uint32_t)(gr * wpr) + ((uint32_t)ix >> 5)) << 2;   // byte offset
                 member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
             }
             const uint64_t mask = __ballot(member);
-            const uint32_t slot = (uint32_t)mbcnt64(mask);
+            const uint32_t slot = DENSE ? (uint32_t)lane : (uint32_t)mbcnt64(mask);
             const float sl = __shfl(s_lo, rr, kWave);
             const float ul = __shfl(U_lo, rr, kWave);
             const float vl = __shfl(V_lo, rr, kWave);
@@ -845,7 +853,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             }
             written += __popcll(mask);
         };
-        if (!SURR) {
+        auto walk2 = [&](auto dense_tag) {
             // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane
             for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
                 while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
@@ -857,9 +865,13 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                     if (p1 >= eq) r1 = q;
                     if (p2 >= eq) r2 = q;
                 }
-                chunk(p1, r1);
-                chunk(p2, r2);
+                chunk(p1, r1, dense_tag);
+                chunk(p2, r2, dense_tag);
             }
+        };
+        if (!SURR) {
+            if (dense) walk2(std::true_type{});
+            else walk2(std::false_type{});
         } else {
             for (int c0 = 0; c0 < total; c0 += kWave) {
                 while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
@@ -870,7 +882,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                     if (eq > c0 + kWave - 1) break;
                     if (p >= eq) rr = q;
                 }
-                chunk(p, rr);
+                chunk(p, rr, std::false_type{});
             }
         }
     }
