@@ -121,8 +121,36 @@ __global__ __launch_bounds__(kBlock) void k_fluence_dose(const int64_t *__restri
     }
 }
 
-/* g_j = sum_i D_ij r_i; one wave per row, lane-strided partial sums then a
- * fixed butterfly.  Columns outside [0, n_voxels) are skipped. */
+/*
+ * Entries [e0, e1) of a CSR row split for 16-byte loads: [e0, a) head, [a, b) whole
+ * steps of `step` entries (4 consecutive per lane), [b, e1) tail; the head is
+ * shorter than 4 entries.  Only when indices and values have the same offset
+ * modulo 16 bytes; otherwise head and steps are empty and the whole row is tail.
+ */
+struct RowSplit { int64_t a, b; };
+
+__device__ inline RowSplit row_split(const int32_t *indices, const float *values, int64_t e0, int64_t e1,
+                                     int step)
+{
+    const uintptr_t oi = (uintptr_t)indices, ov = (uintptr_t)values;
+    if ((oi & 3) || (ov & 3) || ((oi ^ ov) & 15)) return {e0, e0};
+    const int64_t mis = (int64_t)((oi >> 2) & 3);          // element offset of the array modulo 4
+    const int64_t a = min(e1, ((e0 + mis + 3) & ~(int64_t)3) - mis);
+    return {a, a + (e1 - a) / step * step};
+}
+
+__device__ inline float dot4(int4 i, float4 v, const float *__restrict__ x, uint32_t n, float acc)
+{
+    if ((uint32_t)i.x < n) acc = fmaf(v.x, x[(uint32_t)i.x], acc);
+    if ((uint32_t)i.y < n) acc = fmaf(v.y, x[(uint32_t)i.y], acc);
+    if ((uint32_t)i.z < n) acc = fmaf(v.z, x[(uint32_t)i.z], acc);
+    if ((uint32_t)i.w < n) acc = fmaf(v.w, x[(uint32_t)i.w], acc);
+    return acc;
+}
+
+/* g_j = sum_i D_ij r_i; one wave per row: 16-byte loads of four consecutive
+ * entries per lane, two steps in flight, lane partial sums then a fixed
+ * butterfly.  Columns outside [0, n_voxels) are skipped. */
 __global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__restrict__ indptr,
                                                              const int32_t *__restrict__ indices,
                                                              const float *__restrict__ values, int n_rows,
@@ -131,25 +159,35 @@ __global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__re
 {
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
-    const int64_t e1 = indptr[j + 1];
-    int64_t e = indptr[j] + lane_id();
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    // four independent partial sums per lane (entries e + k * 64), then the tail into the first
-    for (; e + 3 * kWave < e1; e += 4 * kWave) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t i = (uint32_t)indices[e + k * kWave];
-            const float v = values[e + k * kWave];
-            if (i < (uint32_t)n_voxels) acc[k] = fmaf(v, r[i], acc[k]);
-        }
+    const int lane = lane_id();
+    const uint32_t n = (uint32_t)n_voxels;
+    const int64_t e0 = indptr[j], e1 = indptr[j + 1];
+    const RowSplit sp = row_split(indices, values, e0, e1, 4 * kWave);
+    float acc0 = 0.0f, acc1 = 0.0f;
+    if (e0 + lane < sp.a) {
+        const uint32_t i = (uint32_t)indices[e0 + lane];
+        if (i < n) acc0 = fmaf(values[e0 + lane], r[i], acc0);
     }
-    for (; e < e1; e += kWave) {
-        const uint32_t i = (uint32_t)indices[e];
-        if (i < (uint32_t)n_voxels) acc[0] = fmaf(values[e], r[i], acc[0]);
+    int64_t e = sp.a + 4 * lane;
+    for (; e + 4 * kWave < sp.b; e += 8 * kWave) {
+        const int4 i0 = *reinterpret_cast<const int4 *>(indices + e);
+        const float4 v0 = *reinterpret_cast<const float4 *>(values + e);
+        const int4 i1 = *reinterpret_cast<const int4 *>(indices + e + 4 * kWave);
+        const float4 v1 = *reinterpret_cast<const float4 *>(values + e + 4 * kWave);
+        acc0 = dot4(i0, v0, r, n, acc0);
+        acc1 = dot4(i1, v1, r, n, acc1);
     }
-    float s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    s = wave_sum(s);
-    if (lane_id() == 0) g[j] = s;
+    if (e < sp.b) {
+        const int4 i0 = *reinterpret_cast<const int4 *>(indices + e);
+        const float4 v0 = *reinterpret_cast<const float4 *>(values + e);
+        acc0 = dot4(i0, v0, r, n, acc0);
+    }
+    for (int64_t t = sp.b + lane; t < e1; t += kWave) {
+        const uint32_t i = (uint32_t)indices[t];
+        if (i < n) acc1 = fmaf(values[t], r[i], acc1);
+    }
+    float s = wave_sum(acc0 + acc1);
+    if (lane == 0) g[j] = s;
 }
 
 /* dose_i = sum_j D_ij w_j over voxel row i: 16 lanes per row, lane-strided
@@ -162,25 +200,27 @@ __global__ __launch_bounds__(kBlock) void k_voxel_dose(const int64_t *__restrict
 {
     const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 4;
     const int l = threadIdx.x & 15;
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const uint32_t n = (uint32_t)n_w;
+    float acc0 = 0.0f, acc1 = 0.0f;
     if (i < n_voxels) {
-        const int64_t e1 = t_indptr[i + 1];
-        int64_t e = t_indptr[i] + l;
-        // four independent partial sums per lane (entries e + 16 k), then the tail into the first
-        for (; e + 48 < e1; e += 64) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t j = (uint32_t)t_indices[e + 16 * k];
-                const float v = t_values[e + 16 * k];
-                if (j < (uint32_t)n_w) acc[k] = fmaf(v, w[j], acc[k]);
-            }
+        // 16-byte loads of four consecutive entries per lane (64 per step), head and tail lane-strided
+        const int64_t e0 = t_indptr[i], e1 = t_indptr[i + 1];
+        const RowSplit sp = row_split(t_indices, t_values, e0, e1, 64);
+        if (e0 + l < sp.a) {
+            const uint32_t j = (uint32_t)t_indices[e0 + l];
+            if (j < n) acc0 = fmaf(t_values[e0 + l], w[j], acc0);
         }
-        for (; e < e1; e += 16) {
+        for (int64_t e = sp.a + 4 * l; e < sp.b; e += 64) {
+            const int4 j4 = *reinterpret_cast<const int4 *>(t_indices + e);
+            const float4 v4 = *reinterpret_cast<const float4 *>(t_values + e);
+            acc1 = dot4(j4, v4, w, n, acc1);
+        }
+        for (int64_t e = sp.b + l; e < e1; e += 16) {
             const uint32_t j = (uint32_t)t_indices[e];
-            if (j < (uint32_t)n_w) acc[0] = fmaf(t_values[e], w[j], acc[0]);
+            if (j < n) acc0 = fmaf(t_values[e], w[j], acc0);
         }
     }
-    float s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    float s = acc0 + acc1;
 #pragma unroll
     for (int d = 8; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
     if (l == 0 && i < n_voxels) dose[i] = s;

@@ -31,3 +31,37 @@ def test_fluence_dose_and_gradient_match_oracle(oracle_lib):
     # the gradient is deterministic
     g2 = csr.gradient(torch.from_numpy(r.astype(np.float32)).cuda()).cpu().numpy()
     np.testing.assert_array_equal(g2, gr.astype(np.float32))
+
+
+@pytest.mark.parametrize("off_i,off_v", [(0, 0), (1, 1), (3, 3), (1, 2), (0, 3)])
+def test_products_on_offset_arrays(oracle_lib, off_i, off_v):
+    """D^T-style row products with the index and value arrays starting 0-3 elements past a
+    16-byte boundary: equal offsets take the 16-byte-load path after a short head, unequal
+    ones the lane-strided path; both must give the FP64 definitions' sums."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_4417_amd import CSR, VoxelCSR
+    n_rows, n_cols = 300, 4000
+    indptr, indices, values = fi.random_csr(17, n_rows, n_cols, 700.0, empty_frac=0.1)
+    nnz = len(indices)
+    print(f"\n  offsets indices {off_i} values {off_v}: rows={n_rows} nnz={nnz}", flush=True)
+    bi = torch.zeros(nnz + 4, dtype=torch.int32, device="cuda:0")
+    bv = torch.zeros(nnz + 4, dtype=torch.float32, device="cuda:0")
+    ii = bi[off_i:off_i + nnz]
+    vv = bv[off_v:off_v + nnz]
+    ii.copy_(torch.from_numpy(indices))
+    vv.copy_(torch.from_numpy(values))
+    ip = torch.from_numpy(indptr).to("cuda:0")
+    rng = np.random.default_rng(5)
+    r = rng.normal(size=n_cols).astype(np.float32)
+    g = CSR(ip, ii, vv, n_cols).gradient(torch.from_numpy(r).to("cuda:0")).cpu().numpy().astype(np.float64)
+    rows = np.repeat(np.arange(n_rows), np.diff(indptr))
+    gref = np.bincount(rows, weights=values.astype(np.float64) * r[indices].astype(np.float64), minlength=n_rows)
+    scale = np.bincount(rows, weights=np.abs(values.astype(np.float64) * r[indices]), minlength=n_rows).max()
+    assert np.max(np.abs(g - gref)) <= 1e-5 * scale
+    # the same arrays read as voxel rows (rows = 300 "voxels", columns = 4000 "beamlets")
+    w = rng.uniform(size=n_cols).astype(np.float32)
+    d = VoxelCSR(ip, ii, vv, n_cols).dose(torch.from_numpy(w).to("cuda:0")).cpu().numpy().astype(np.float64)
+    dref = np.bincount(rows, weights=values.astype(np.float64) * w[indices].astype(np.float64), minlength=n_rows)
+    assert np.max(np.abs(d - dref)) <= 1e-5 * max(dref.max(), 1e-30)
