@@ -71,7 +71,7 @@ typedef struct fspb_plan fspb_plan;
 
 /* CT-derived density grid (Sec. 2.2: the CT images and their bounding prism). */
 typedef struct {
-    int32_t nx, ny, nz;          /* voxels per axis, each >= 1, nx*ny*nz < 2^31 */
+    int32_t nx, ny, nz;          /* voxels per axis, each >= 1, nx < 2^30, nx*ny*nz < 2^31 */
     int32_t reserved;            /* must be 0 */
     double spacing[3];           /* voxel size (cm), each > 0 */
     double origin[3];            /* centre of voxel (0,0,0) (cm) */

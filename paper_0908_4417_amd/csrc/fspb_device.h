@@ -12,6 +12,8 @@ namespace fspb {
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kRowsPerTile = 64;     // grid rows (iy, iz) per count/fill tile: one per lane
 constexpr int kMaxTerms = 4;
+// flag in PlanDev::ext[].x: the grid row has non-member voxels between its first and last member
+constexpr int kExtHoles = 1 << 30;
 // erfc on [0, kErfcMax] by piecewise quadratics on kErfcIntervals equal intervals
 // (training targets of the kernel surrogate)
 constexpr int kErfcIntervals = 512;
@@ -57,7 +59,8 @@ struct alignas(16) PlanDev {
     double lo[3];                // lower corner of the bounding box
     const float *density;
     uint32_t *bits;              // [nz*ny][wpr] density > rho_min
-    int2 *ext;                   // [nz*ny] first / last member column of each grid row
+    int2 *ext;                   // [nz*ny] first / last member column of each grid row; bit 30
+                                 // of .x set: non-member voxels lie between them
     float rho_min;
     // kernel
     int32_t n_terms, n_pdd;

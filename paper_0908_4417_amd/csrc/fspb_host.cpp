@@ -207,6 +207,7 @@ fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams
         return fail(FSPB_ERR_INVALID, "grid dimensions must be >= 1 (got %d x %d x %d)", g->nx, g->ny, g->nz);
     if ((int64_t)g->nx * g->ny * g->nz >= (int64_t)1 << 31)
         return fail(FSPB_ERR_INVALID, "grid has 2^31 or more voxels");
+    if (g->nx >= 1 << 30) return fail(FSPB_ERR_INVALID, "grid.nx must be < 2^30 (got %d)", g->nx);
     if (g->reserved != 0) return fail(FSPB_ERR_INVALID, "grid.reserved must be 0");
     for (int k = 0; k < 3; ++k) {
         if (!(finite(g->spacing[k]) && g->spacing[k] > 0.0))

@@ -67,7 +67,7 @@ __device__ void prep_row(const PlanDev &P, int row)
     const int lane = lane_id();
     const float *d = P.density + (size_t)row * P.nx;
     uint32_t *bits = P.bits + (size_t)row * P.wpr;
-    int first = P.nx, last = -1;
+    int first = P.nx, last = -1, members = 0;
     for (int x0 = 0; x0 < P.nx; x0 += kWave) {
         const int x = x0 + lane;
         const bool m = x < P.nx && d[x] > P.rho_min;
@@ -77,9 +77,12 @@ __device__ void prep_row(const PlanDev &P, int row)
         if (b) {
             first = min(first, x0 + __ffsll((unsigned long long)b) - 1);
             last = x0 + 63 - __clzll((long long)b);
+            members += __popcll(b);
         }
     }
-    if (lane == 0) P.ext[row] = make_int2(first, last);   // first > last: no member voxel
+    // first > last: no member voxel; kExtHoles marks a row with non-members between them
+    const int holes = members != last - first + 1 && members > 0 ? kExtHoles : 0;
+    if (lane == 0) P.ext[row] = make_int2(first | holes, last);
 }
 
 __global__ __launch_bounds__(kBlock) void k_prep(const PlanDev *__restrict__ plans)
@@ -333,7 +336,7 @@ __device__ inline RowAffine row_affine(const RowGeom &G, int iy, int iz)
  * Solved in FP64 from the four linear inequalities.  Returns false if empty.
  */
 __device__ inline bool row_span(const RowGeom &G, const int2 *__restrict__ ext_rows, int nx, int ny, int iy,
-                                int iz, int &lo, int &hi, RowAffine &a)
+                                int iz, int &lo, int &hi, RowAffine &a, bool &holes)
 {
     a = row_affine(G, iy, iz);
     const double c0[4] = {a.U0 - G.cu * a.t0, -a.U0 - G.cu * a.t0,
@@ -349,8 +352,9 @@ __device__ inline bool row_span(const RowGeom &G, const int2 *__restrict__ ext_r
     const int2 ext = ext_rows[iz * ny + iy];
     xlo = fmin(xlo, (double)nx);                    // both bounds now in [-1, nx]
     xhi = fmax(xhi, -1.0);
-    lo = max((int)ceil(xlo), max(ext.x, 0));
+    lo = max((int)ceil(xlo), max(ext.x & ~kExtHoles, 0));
     hi = min((int)floor(xhi), min(ext.y, nx - 1));
+    holes = (ext.x & kExtHoles) != 0;
     return ok && lo <= hi;
 }
 
@@ -390,7 +394,10 @@ __device__ inline int count_row(const RowGeom &G, const uint32_t *__restrict__ b
     const int iy = iy0 + c.iy, iz = iz0 + c.iz;
     int lo, hi;
     RowAffine a;
-    if (!row_span(G, ext, nx, ny, iy, iz, lo, hi, a)) return 0;
+    bool holes;
+    if (!row_span(G, ext, nx, ny, iy, iz, lo, hi, a, holes)) return 0;
+    // every voxel between the row's first and last member is one: no mask words needed
+    if (!holes) return hi - lo + 1;
     return popcount_range(bits + (size_t)(iz * ny + iy) * wpr, lo, hi);
 }
 
@@ -772,7 +779,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
             RowAffine a;
             const RowGeom G = row_geom(P, R);
-            if (row_span(G, P.ext, P.nx, P.ny, iy, iz, lo, hi, a)) {
+            bool holes;
+            if (row_span(G, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
                 grow = iz * ny + iy;
                 const double x = (double)lo;
                 s_lo = (float)(a.t0 + x * t1 - tA);

@@ -69,6 +69,7 @@ def test_workspace_query(fspb):
 
 @pytest.mark.parametrize("mutate,msg", [
     (lambda g, b, k: setattr(g, "nx", 0), "dimensions"),
+    (lambda g, b, k: (setattr(g, "nx", 1 << 30), setattr(g, "ny", 1), setattr(g, "nz", 1)), "nx must be"),
     (lambda g, b, k: setattr(g, "reserved", 3), "reserved"),
     (lambda g, b, k: g.spacing.__setitem__(1, -0.5), "spacing"),
     (lambda g, b, k: g.origin.__setitem__(2, float("nan")), "origin"),
