@@ -185,9 +185,11 @@ fspb_status fspb_plan_create(const fspb_grid *grid, const fspb_beam *beams, int3
  * table points; with FSPB_DEPTH_TRILINEAR the density is instead sampled by
  * trilinear interpolation at the table points (FP64) and summed by
  * trapezoids.  Also derives the density mask (density > rho_min) used by the
- * VOI test.  Reads the borrowed density; enqueues work on `stream` (on the
- * plan's first call, after the copy of the plan's records into the workspace).
- * Invalidates the row counts of an earlier fspb_dose_coeffs.
+ * VOI test and counts every beamlet's VOI members (Sec. 2.1), which
+ * fspb_dose_coeffs turns into row pointers.  Reads the borrowed density;
+ * enqueues work on `stream` (on the plan's first call, after the copy of the
+ * plan's records into the workspace).  Invalidates the row pointers of an
+ * earlier fspb_dose_coeffs.
  */
 fspb_status fspb_raytrace(fspb_plan *plan, void *stream);
 

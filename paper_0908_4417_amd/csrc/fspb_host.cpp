@@ -749,9 +749,13 @@ fspb_status fspb_raytrace(fspb_plan *p, void *stream)
     hipStream_t s = static_cast<hipStream_t>(stream);
     fspb_status us = plan_upload(p, s);
     if (us != FSPB_OK) return us;
+    // the VOI counts need only the mask, so they run before the depth tables: queued behind
+    // another plan's fill, they then get the CUs that fill's last workgroups leave free
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[0], s), "record event");
     FSPB_HIP(fspb::launch_prep(p->d_plan, p->h, s), "launch prep");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[1], s), "record event");
+    FSPB_HIP(fspb::launch_count(p->d_plan, p->h, s), "launch count");
+    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[3], s), "record event");
     FSPB_HIP(fspb::launch_raytrace(p->d_plan, p->h, s), "launch raytrace");
     if (p->timing) {
         FSPB_HIP(hipEventRecord(p->ev[2], s), "record event");
@@ -782,8 +786,7 @@ fspb_status fspb_dose_coeffs(fspb_plan *p, int64_t *indptr, int32_t *indices, fl
     p->counted = false;
     FSPB_HIP(hipMemcpyAsync(p->d_out, &p->out, sizeof(OutDev), hipMemcpyHostToDevice, s), "upload output record");
     p->have_dose_ev = false;
-    if (p->timing) FSPB_HIP(hipEventRecord(p->ev[3], s), "record event");
-    FSPB_HIP(fspb::launch_count(p->d_plan, p->h, s), "launch count");
+    // tile and row counts were made by fspb_raytrace
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[4], s), "record event");
     FSPB_HIP(fspb::launch_scan(p->d_plan, p->d_out, p->h, s), "launch scan");
     if (p->timing) FSPB_HIP(hipEventRecord(p->ev[5], s), "record event");
@@ -859,8 +862,8 @@ fspb_status fspb_plan_get_timing(fspb_plan *p, fspb_timing *t)
     if (!p->have_trace_ev || !p->have_dose_ev) return FSPB_OK;
     FSPB_HIP(hipEventSynchronize(p->ev[7]), "wait for timing events");
     FSPB_HIP(hipEventElapsedTime(&t->prep_ms, p->ev[0], p->ev[1]), "elapsed");
-    FSPB_HIP(hipEventElapsedTime(&t->raytrace_ms, p->ev[1], p->ev[2]), "elapsed");
-    FSPB_HIP(hipEventElapsedTime(&t->count_ms, p->ev[3], p->ev[4]), "elapsed");
+    FSPB_HIP(hipEventElapsedTime(&t->count_ms, p->ev[1], p->ev[3]), "elapsed");
+    FSPB_HIP(hipEventElapsedTime(&t->raytrace_ms, p->ev[3], p->ev[2]), "elapsed");
     FSPB_HIP(hipEventElapsedTime(&t->scan_ms, p->ev[4], p->ev[5]), "elapsed");
     FSPB_HIP(hipEventElapsedTime(&t->fill_ms, p->ev[6], p->ev[7]), "elapsed");
     t->valid = 1;
