@@ -447,16 +447,19 @@ fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices,
 
 /*
  * Voxel-row form of D: the transpose of a beamlet-row CSR (n_rows beamlets,
- * nnz entries, columns in [0, n_voxels)) by a stable radix sort on the voxel
- * index.  Each voxel row lists its beamlets in ascending order, so the
- * result is canonical and bit-reproducible.
+ * nnz entries, columns in [0, n_voxels)): a stable sort of the entries by
+ * voxel index.  When a row's entries form long stretches within 32-column
+ * buckets (as in D), the stretches are sorted by bucket and each bucket's
+ * entries placed by a counting sort; otherwise a radix sort of the entries.
+ * Each voxel row lists its beamlets in ascending order, so the result is
+ * canonical and bit-reproducible.
  *   indptr (n_rows + 1, int64), indices (nnz), values (nnz): DEVICE, input;
  *   t_indptr (n_voxels + 1, int64), t_indices (nnz, beamlet ids),
  *   t_values (nnz): DEVICE, written.
  * workspace: DEVICE, 256-byte aligned, caller-owned, about 24 bytes per
  * entry; NULL = size query (returns FSPB_ERR_CAPACITY and sets
- * *workspace_needed).  nnz must be below 2^32.  Synchronises `stream` once
- * (after the voxel-row pointers are known); a column index outside
+ * *workspace_needed).  nnz must be below 2^32.  Synchronises `stream` twice
+ * (after the voxel-row pointers and after the stretch count); a column index outside
  * [0, n_voxels) returns FSPB_ERR_INVALID with only t_indptr written.
  */
 fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,

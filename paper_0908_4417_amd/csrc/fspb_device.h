@@ -123,7 +123,7 @@ hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices
                                    int n_voxels, const float *r, float *g, hipStream_t s);
 hipError_t launch_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values, int n_voxels,
                              int n_w, const float *w, float *dose, hipStream_t s);
-size_t transpose_workspace(int64_t nnz, int n_voxels);
+size_t transpose_workspace(int64_t nnz, int n_voxels, int n_rows);
 int transpose_passes(int n_voxels);
 /* Synchronises s; *bad_host = 1 when a column index lies outside [0, n_voxels)
  * (then only t_indptr is written). */

@@ -1602,7 +1602,7 @@ fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, co
     g_last_error.clear();
     if (n_rows < 0 || n_voxels < 1 || nnz < 0) return fail(FSPB_ERR_INVALID, "n_rows, n_voxels or nnz out of range");
     if (nnz >= ((int64_t)1 << 32) - 1) return fail(FSPB_ERR_INVALID, "nnz must be below 2^32");
-    const size_t need = fspb::transpose_workspace(nnz, n_voxels);
+    const size_t need = fspb::transpose_workspace(nnz, n_voxels, n_rows);
     if (workspace_needed) *workspace_needed = need;
     if (!workspace) return fail(FSPB_ERR_CAPACITY, "workspace query: %zu bytes needed", need);
     if (workspace_bytes < need)

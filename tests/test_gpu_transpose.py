@@ -55,6 +55,38 @@ def test_random_matrix_matches_oracle(torch_gpu, oracle_lib, seed, n_rows, n_col
     assert np.max(np.abs(d - ref)) <= 4e-6 * max(ref.max(), 1e-30)
 
 
+@pytest.mark.parametrize("seed,mode", [(6, "reversed runs"), (7, "repeated columns"), (8, "shuffled rows")])
+def test_unsorted_rows_match_oracle(torch_gpu, oracle_lib, seed, mode):
+    """Rows whose columns are not strictly ascending: the transpose is still the stable sort
+    of the row-major entries by column.  Reversing each stretch of a row within one 32-column
+    bucket keeps the stretches long (bucket placement for unsorted rows); shuffling whole rows
+    makes them short (radix sort)."""
+    torch = torch_gpu
+    indptr, indices, values = fi.random_csr(seed, 400, 6000, 120.0)
+    rng = np.random.default_rng(seed)
+    for j in range(len(indptr) - 1):
+        a, b = int(indptr[j]), int(indptr[j + 1])
+        if mode == "shuffled rows":
+            p = rng.permutation(b - a)
+            indices[a:b] = indices[a:b][p]
+            values[a:b] = values[a:b][p]
+            continue
+        cut = [a] + [e for e in range(a + 1, b) if indices[e] >> 5 != indices[e - 1] >> 5] + [b]
+        for s0, s1 in zip(cut[:-1], cut[1:]):
+            if mode == "reversed runs":
+                indices[s0:s1] = indices[s0:s1][::-1].copy()
+                values[s0:s1] = values[s0:s1][::-1].copy()
+            elif s1 - s0 >= 2:
+                indices[s0 + 1] = indices[s0]
+    print(f"\n  {mode}: seed={seed} nnz={len(indices)}", flush=True)
+    t = _csr(torch, indptr, indices, values, 6000).transpose()
+    torch.cuda.synchronize()
+    ep, ei, ev = oracle_lib.csr_transpose(indptr, indices, values, 6000)
+    np.testing.assert_array_equal(t.indptr.cpu().numpy(), ep)
+    np.testing.assert_array_equal(t.indices.cpu().numpy(), ei)
+    np.testing.assert_array_equal(t.values.cpu().numpy(), ev)
+
+
 def test_empty_and_invalid(torch_gpu):
     torch = torch_gpu
     import paper_0908_4417_amd as m
