@@ -493,7 +493,8 @@ namespace {
  * output is the stable sort of the row-major entries by column, as the radix
  * path gives, for about two reads and one write of the matrix.  Buckets of 32
  * columns: with 128 the slab's transpose took 29 ms, with 32 20 ms, with 16 19 ms
- * (the pelvis 22, 14 and 17 ms; the radix path 30 and 18 ms).
+ * (the pelvis 22, 14 and 17 ms; the radix path 30 and 18 ms); staging each batch
+ * of runs in LDS brought the 32-column case to 12.6 ms (pelvis 11.9 ms).
  */
 constexpr int kBucketShift = 5;
 constexpr int kBucketCols = 1 << kBucketShift;
@@ -563,51 +564,83 @@ __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__
 
 /*
  * The same placement for rows with strictly ascending columns, column by
- * column: each lane holds one of 64 runs of the bucket (rows ascending) and
- * its next entry (prefetched one ahead); at column c the lanes whose next
- * entry has column c write it, ranked by lane, so each column's entries from
- * the 64 runs go out as one contiguous stretch.
+ * column.  A batch of 64 runs of the bucket (rows ascending; each at most 32
+ * entries, one per column) is first copied into LDS, the runs' entries
+ * flattened over the lanes so that all loads are independent; then each lane
+ * holds one run and, at column c, the lanes whose next entry has column c write
+ * it, ranked by lane, so each column's entries from the batch go out as one
+ * contiguous stretch.
  */
-__global__ __launch_bounds__(kBlock) void k_bucket_columns(const int64_t *__restrict__ indptr,
-                                                           const int32_t *__restrict__ indices,
-                                                           const float *__restrict__ values, int n_voxels,
-                                                           int n_buckets, const int64_t *__restrict__ run_ptr,
-                                                           const uint32_t *__restrict__ run_src,
-                                                           const int64_t *__restrict__ b_ptr,
-                                                           const int32_t *__restrict__ b_rows,
-                                                           const float *__restrict__ b_ids,
-                                                           const int64_t *__restrict__ t_indptr, uint32_t nnz,
-                                                           int32_t *__restrict__ t_indices, float *__restrict__ t_values)
+constexpr int kColWaves = 2;                               // waves per workgroup of k_bucket_columns
+
+__global__ __launch_bounds__(kColWaves * kWave) void k_bucket_columns(
+    const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices, const float *__restrict__ values,
+    int n_voxels, int n_buckets, const int64_t *__restrict__ run_ptr, const uint32_t *__restrict__ run_src,
+    const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+    const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
+    float *__restrict__ t_values)
 {
-    __shared__ uint32_t s_pos[kWavesPerBlock][kBucketCols];
+    constexpr int kStage = kWave * kBucketCols;            // 64 runs of at most 32 entries
+    __shared__ uint32_t s_pos[kColWaves][kBucketCols];
+    __shared__ float s_val[kColWaves][kStage];
+    __shared__ uint8_t s_col[kColWaves][kStage];
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int b = blockIdx.x * kWavesPerBlock + wave;
+    const int b = blockIdx.x * kColWaves + wave;
     if (b >= n_buckets) return;
-    uint32_t *pos = s_pos[wave];                     // next free position of each column's list
+    uint32_t *pos = s_pos[wave];                           // next free position of each column's list
+    float *sv = s_val[wave];
+    uint8_t *sc = s_col[wave];
     for (int c = lane; c < kBucketCols; c += kWave) {
         const int col = (b << kBucketShift) + c;
         pos[c] = col < n_voxels ? (uint32_t)t_indptr[col] : 0u;
     }
-    __builtin_amdgcn_wave_barrier();
-    constexpr int kNone = 0x7fffffff;
     const int col0 = b << kBucketShift;
     const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1];
     for (int64_t qb = q0; qb < q1; qb += kWave) {
+        // lane i: run qb + i (row, first entry, length)
         const int64_t q = qb + lane;
         int row = 0;
-        uint32_t k = 0u, end = 0u;
+        uint32_t src = 0u, len = 0u;
         if (q < q1) {
             row = b_rows[q];
             const uint32_t id = __float_as_uint(b_ids[q]);
-            k = run_src[id];
-            end = (int64_t)id + 1 < run_ptr[row + 1] ? run_src[id + 1] : (uint32_t)indptr[row + 1];
+            src = run_src[id];
+            const uint32_t end = (int64_t)id + 1 < run_ptr[row + 1] ? run_src[id + 1] : (uint32_t)indptr[row + 1];
+            len = min(end - src, (uint32_t)kBucketCols);   // at most 32 for strictly ascending rows
         }
-        int ca = k < end ? indices[k] : kNone;        // this lane's next entry and the one after it
-        float va = k < end ? values[k] : 0.0f;
-        int cb = k + 1 < end ? indices[k + 1] : kNone;
-        float vb = k + 1 < end ? values[k + 1] : 0.0f;
+        uint32_t incl = len;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += y;
+        }
+        const uint32_t excl = incl - len;
+        const uint32_t total = __shfl(incl, kWave - 1, kWave);   // <= kStage
+        // stage: entry p of the batch (run walked wave-uniformly) -> LDS
+        int rcur = 0;
+        for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+            while (rcur + 1 < kWave && (uint32_t)__builtin_amdgcn_readlane((int)excl, rcur + 1) <= c0) ++rcur;
+            const uint32_t p = c0 + lane;
+            int rr = rcur;
+            for (int k = rcur + 1; k < kWave; ++k) {
+                const uint32_t ek = (uint32_t)__builtin_amdgcn_readlane((int)excl, k);
+                if (ek > c0 + kWave - 1) break;
+                if (p >= ek) rr = k;
+            }
+            // shuffles on every lane: the source lane rr may be past the end of the batch's entries
+            const uint32_t e = __shfl(src, rr, kWave) + (p - __shfl(excl, rr, kWave));
+            if (p < total) {
+                sc[p] = (uint8_t)(indices[e] - col0);
+                sv[p] = values[e];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // place: lane = run, its entries sc/sv[excl, excl + len)
+        uint32_t k = excl;
+        const uint32_t end = excl + len;
+        int ca = k < end ? (int)sc[k] : kBucketCols;
         for (int c = 0; c < kBucketCols; ++c) {
-            const bool has = ca == col0 + c;
+            const bool has = ca == c;
             const uint64_t m = __ballot(has);
             if (m == 0) continue;
             const uint32_t p0 = pos[c];
@@ -615,18 +648,16 @@ __global__ __launch_bounds__(kBlock) void k_bucket_columns(const int64_t *__rest
                 const uint32_t p = p0 + (uint32_t)mbcnt64(m);
                 if (p < nnz) {   // always true for consistent runs; keeps every store in bounds
                     t_indices[p] = row;
-                    t_values[p] = va;
+                    t_values[p] = sv[k];
                 }
                 ++k;
-                ca = cb;
-                va = vb;
-                cb = k + 1 < end ? indices[k + 1] : kNone;
-                vb = k + 1 < end ? values[k + 1] : 0.0f;
+                ca = k < end ? (int)sc[k] : kBucketCols;
             }
             __builtin_amdgcn_wave_barrier();
             if (lane == 0) pos[c] = p0 + (uint32_t)__popcll(m);
             __builtin_amdgcn_wave_barrier();
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -880,7 +911,7 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
                                indices, values, n_voxels, nb, run_ptr, rsrc, bptr, brow, bid, t_indptr, (uint32_t)nnz,
                                t_indices, t_values);
         else
-            hipLaunchKernelGGL(k_bucket_columns, dim3(blocks_of(nb, kWavesPerBlock)), dim3(kBlock), 0, s, indptr,
+            hipLaunchKernelGGL(k_bucket_columns, dim3(blocks_of(nb, kColWaves)), dim3(kColWaves * kWave), 0, s, indptr,
                                indices, values, n_voxels, nb, run_ptr, rsrc, bptr, brow, bid, t_indptr, (uint32_t)nnz,
                                t_indices, t_values);
         return hipGetLastError();
