@@ -153,7 +153,11 @@ typedef struct {
     int64_t table_entries;       /* sum of depth-table lengths */
     int64_t n_tiles;             /* units of work of the count and fill kernels */
     int32_t max_table;           /* longest depth table */
-    int32_t reserved;
+    int32_t fill_lds_bytes;      /* LDS of one fill workgroup: the erf table (8 KB on [0, 4], or
+                                    16 KB mirrored onto [-4, 4] where that does not lower the
+                                    fill's workgroups per CU on this device), the longest depth
+                                    table and the depth dose as (value, slope) pairs, and the
+                                    tile offsets of the beamlet with most tiles */
 } fspb_plan_desc;
 
 /*

@@ -91,7 +91,8 @@ struct alignas(16) PlanDev {
     // attached kernel surrogate (use_mlp = 0: analytic fill)
     const float *mlp_p;          // FP32 parameters
     const uint16_t *mlp_w2;      // BF16 W2 [out][in]
-    int32_t use_mlp, pad1;
+    int32_t use_mlp;
+    int32_t erf_mirrored;        // fill stages erf on [-kErfMax, kErfMax] (analytic and tabulated forms)
 };
 
 /* Caller-owned CSR output of one plan (device pointers). */
@@ -113,7 +114,13 @@ hipError_t launch_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &
 /* Fill rows row0 .. row0 + n_rows - 1 (dout->row0 must equal row0). */
 hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &h, int row0, int n_rows,
                        hipStream_t s);
+/* Dynamic LDS of one fill workgroup: in the form launch_fill uses, or in a given erf table form. */
 size_t fill_shared_bytes(const PlanDev &h);
+size_t fill_shared_bytes(const PlanDev &h, bool mirrored_erf);
+bool fill_mirrored_erf(const PlanDev &h);
+/* 1 when the mirrored erf table keeps the plan's fill at the same workgroups per CU as the
+ * 8 KB table (occupancy query for the current device); 0 otherwise. */
+int choose_erf_form(const PlanDev &h);
 
 /* Eq. 1 and its adjoint on a CSR. */
 /* Eq. 1 on a beamlet-row CSR and on its voxel-row transpose (fspb_sparse.hip). */

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -396,6 +397,24 @@ const std::vector<float2> &fill_erf_table()
     return t;
 }
 
+/*
+ * The fill's erf table form for a plan (fspb::choose_erf_form), remembered per
+ * device, kernel shape and LDS size: plans of one geometry share the answer.
+ */
+std::mutex g_form_mu;
+std::map<std::array<int64_t, 4>, int> g_form;
+
+int erf_form(const fspb::PlanDev &h, int device)
+{
+    const std::array<int64_t, 4> key{device, h.n_terms, h.gen, (int64_t)fspb::fill_shared_bytes(h, false)};
+    std::lock_guard<std::mutex> lk(g_form_mu);
+    auto it = g_form.find(key);
+    if (it != g_form.end()) return it->second;
+    const int f = fspb::choose_erf_form(h);
+    g_form.emplace(key, f);
+    return f;
+}
+
 /* A staging buffer of at least `bytes` on `device`, claimed for the caller. */
 fspb_status stage_acquire(size_t bytes, int device, Staging **out)
 {
@@ -714,6 +733,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     // fspb_raytrace or fspb_batch_create copies it on its stream
     int dev = 0;
     FSPB_HIP(hipGetDevice(&dev), "get device");
+    h.erf_mirrored = erf_form(h, dev);
     FSPB_HIP(hipEventCreateWithFlags(&p->nnz_ready, hipEventDisableTiming), "create count event");
     st = slot_acquire(&p->nnz_host);
     if (st != FSPB_OK) return st;
@@ -881,7 +901,7 @@ fspb_status fspb_plan_info(const fspb_plan *p, fspb_plan_desc *d)
     d->table_entries = p->table_entries;
     d->n_tiles = p->h.n_tiles;
     d->max_table = p->h.max_table;
-    d->reserved = 0;
+    d->fill_lds_bytes = (int32_t)fspb::fill_shared_bytes(p->h);
     return FSPB_OK;
 }
 
@@ -1104,7 +1124,7 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
         start[1][i + 1] = start[1][i] + h.n_beamlets;
         start[2][i + 1] = start[2][i] + h.n_beamlets;
         b->max_terms = std::max(b->max_terms, h.n_terms);
-        b->lds = std::max(b->lds, fspb::fill_shared_bytes(h));
+        b->lds = std::max(b->lds, fspb::fill_shared_bytes(h));   // each plan's erf table form
         b->outs[i].overflow = plans[i]->d_overflow;
     }
     for (int st = 0; st < kWaveStages; ++st) b->total[st] = start[st][n_plans];

@@ -523,11 +523,16 @@ __device__ inline gptr<T> as_global(T *p)
  * erf(z) at the table coordinate x = z kErfScale: linear interpolation in the
  * LDS copy of the table on [0, kErfMax] (one 8-byte (value, difference) read),
  * sign restored by odd symmetry, held at +-erf(kErfMax) beyond the table.
- * Halving the table this way (8 KB) keeps the fill's LDS per workgroup small
- * enough for six workgroups per CU on the largest plans.
+ *
+ * The fill stages the table in one of two forms: this one (8 KB), or mirrored
+ * onto [-kErfMax, kErfMax] (16 KB, arguments offset by kErfIntervals), where a
+ * signed argument needs no absolute value or sign restore.  The mirrored form
+ * saves four instructions per coefficient of a two-term kernel and is used
+ * wherever its larger LDS footprint does not cost the fill a workgroup per CU.
  */
 constexpr float kErfScale = (float)kErfIntervals / kErfMax;
 constexpr int kErfLdsFloats = 2 * kErfIntervals;
+constexpr float kErfTopSigned = 2.0f * kErfIntervals - 1.0f / 1024.0f;   // below 2 kErfIntervals, fract < 1
 
 __device__ inline float erf_lds(const float *__restrict__ tab, float x)
 {
@@ -538,10 +543,22 @@ __device__ inline float erf_lds(const float *__restrict__ tab, float x)
     return copysignf(fmaf(q.y, f, q.x), x);
 }
 
-/* erf_lds for an argument known to be >= 0 (no sign to restore). */
+/* erf_lds for an argument known to be >= 0 (no sign to restore); SE: in the
+ * mirrored table, offset included. */
+template <bool SE = false>
 __device__ inline float erf_lds_pos(const float *__restrict__ tab, float x)
 {
-    const float xc = fminf(x, (float)kErfIntervals - 1.0f / 1024.0f);
+    const float xc = fminf(x, SE ? kErfTopSigned : (float)kErfIntervals - 1.0f / 1024.0f);
+    const int k = (int)xc;
+    const float f = __builtin_amdgcn_fractf(xc);
+    const float2 q = reinterpret_cast<const float2 *>(tab)[k];
+    return fmaf(q.y, f, q.x);
+}
+
+/* erf in the mirrored table at x + kErfIntervals (the offset is part of the argument). */
+__device__ inline float erf_lds_signed(const float *__restrict__ tab, float xo)
+{
+    const float xc = __builtin_amdgcn_fmed3f(xo, 0.0f, kErfTopSigned);
     const int k = (int)xc;
     const float f = __builtin_amdgcn_fractf(xc);
     const float2 q = reinterpret_cast<const float2 *>(tab)[k];
@@ -552,12 +569,22 @@ __device__ inline float erf_lds_pos(const float *__restrict__ tab, float x)
  * One bracket of Eq. 3, erf((h - x) is) + erf((h + x) is), with
  * is = 1/(sqrt2 sigma): isk = is kErfScale and hk = h isk put both arguments
  * in table coordinates.  The bracket is even in x, so it is evaluated at |x|,
- * where the second argument is never negative (h > 0).
+ * where the second argument is never negative (h > 0).  SE: mirrored table,
+ * hk already offset by kErfIntervals.
  */
+template <bool SE>
 __device__ inline float edge_pair(const float *__restrict__ tab, float x, float hk, float isk)
 {
     const float ax = fabsf(x);
+    if (SE) return erf_lds_signed(tab, fmaf(-ax, isk, hk)) + erf_lds_pos<true>(tab, fmaf(ax, isk, hk));
     return erf_lds(tab, fmaf(-ax, isk, hk)) + erf_lds_pos(tab, fmaf(ax, isk, hk));
+}
+
+/* hk of the bracket: h isk, plus the mirrored table's offset */
+template <bool SE>
+__device__ inline float edge_offset(float h, float isk)
+{
+    return SE ? fmaf(h, isk, (float)kErfIntervals) : h * isk;
 }
 
 /* Per-beamlet constants of the fill, held in registers. */
@@ -575,7 +602,7 @@ struct FillConst {
 // is kErfScale = kIsScale / sigma
 constexpr float kIsScale = 0.70710678118654752f * kErfScale;
 
-template <int K, bool GUARD>
+template <int K, bool GUARD, bool SE>
 __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restrict__ tab,
                                    const float2 *__restrict__ pdd, const float *__restrict__ etab,
                                    float s, float U, float V)
@@ -597,8 +624,8 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
     for (int i = 0; i < K; ++i) {
         if (GUARD && i >= c.n_terms) break;
         const float isk = __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
-        const float eu = edge_pair(etab, u, c.ha[i] * isk, isk);
-        const float ev = edge_pair(etab, v, c.hb[i] * isk, isk);
+        const float eu = edge_pair<SE>(etab, u, edge_offset<SE>(c.ha[i], isk), isk);
+        const float ev = edge_pair<SE>(etab, v, edge_offset<SE>(c.hb[i], isk), isk);
         L = i == 0 ? c.w4[0] * eu * ev : fmaf(c.w4[i] * eu, ev, L);   // no add of 0 for the first term
     }
     return A * L;
@@ -609,7 +636,7 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
  * (already interpolated in theta), c1, c2, c3 of each term from LDS depth
  * tables (value, slope) laid out [c][term][node].
  */
-template <int K>
+template <int K, bool SE>
 __device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__restrict__ tab,
                                        const float2 *__restrict__ sA, const float2 *__restrict__ sc,
                                        const float *__restrict__ etab, float s, float U, float V)
@@ -632,8 +659,8 @@ __device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__re
         const float2 q1 = sc[i * c.nc + kc], q2 = sc[(K + i) * c.nc + kc], q3 = sc[(2 * K + i) * c.nc + kc];
         const float c1 = fmaf(fc, q1.y, q1.x), c2 = fmaf(fc, q2.y, q2.x), c3 = fmaf(fc, q3.y, q3.x);
         const float isk = kIsScale * __builtin_amdgcn_rcpf(c3);
-        const float eu = edge_pair(etab, u, c2 * c.half_a * isk, isk);
-        const float ev = edge_pair(etab, v, c2 * c.half_b * isk, isk);
+        const float eu = edge_pair<SE>(etab, u, edge_offset<SE>(c2 * c.half_a, isk), isk);
+        const float ev = edge_pair<SE>(etab, v, edge_offset<SE>(c2 * c.half_b, isk), isk);
         L = i == 0 ? 0.25f * c1 * eu * ev : fmaf(0.25f * c1 * eu, ev, L);
     }
     return A * L;
@@ -652,9 +679,10 @@ __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readla
  * D_ij of beamlet j (one CSR row) by a workgroup of W waves: LDS-staged
  * tables, then each wave takes tiles of 64 grid rows; a tile's VOI candidates
  * are flattened across its rows, 64 per chunk, members compacted by ballot.
- * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K).
+ * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K);
+ * SE: mirrored erf table.
  */
-template <int K, int W, bool GUARD, bool SURR, bool GEN = false>
+template <int K, int W, bool GUARD, bool SURR, bool GEN = false, bool SE = false>
 __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem)
 {
     const BeamletRec &R = P.rec[j];
@@ -704,13 +732,14 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
 
     // ---- LDS: erf table, depth table, depth dose, tile prefix
     float *s_erf = reinterpret_cast<float *>(smem);
-    float2 *s_tab = reinterpret_cast<float2 *>(s_erf + kErfLdsFloats);
+    constexpr int kErfFloats = SE ? 2 * kErfLdsFloats : kErfLdsFloats;
+    float2 *s_tab = reinterpret_cast<float2 *>(s_erf + kErfFloats);
     float2 *s_pdd = s_tab + P.max_table;
     int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
     __shared__ int wsum[W];
     // surrogate: per-wave h1 tile after the tile prefix, and W2 fragments in registers
     uint16_t *s_h1 = reinterpret_cast<uint16_t *>(
-        smem + ((sizeof(float) * kErfLdsFloats + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
+        smem + ((sizeof(float) * kErfFloats + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
                  sizeof(int) * ((size_t)P.max_tiles + 1) + 15) & ~(size_t)15)) + wave * (64 * mlp::kH1Stride);
     mlp::W2Frags wf;
     if (SURR) mlp::load_w2_frags(P.mlp_w2, wf);
@@ -719,7 +748,21 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
 
     {
         const float2 *et = P.erf_tab;
-        for (int i = tid; i < kErfIntervals; i += kB) reinterpret_cast<float2 *>(s_erf)[i] = et[i];
+        if (SE) {
+            // [0, n): erf on [-kErfMax, 0) from the odd symmetry; [n, 2n): the table
+            for (int i = tid; i < 2 * kErfIntervals; i += kB) {
+                float2 q;
+                if (i >= kErfIntervals) {
+                    q = et[i - kErfIntervals];
+                } else {
+                    const float2 m = et[kErfIntervals - 1 - i];
+                    q = make_float2(-(m.x + m.y), m.y);
+                }
+                reinterpret_cast<float2 *>(s_erf)[i] = q;
+            }
+        } else {
+            for (int i = tid; i < kErfIntervals; i += kB) reinterpret_cast<float2 *>(s_erf)[i] = et[i];
+        }
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
         for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
@@ -791,12 +834,27 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                 hi = -1;
             }
         }
-        const int cnt = hi - lo + 1;
+        int cnt = hi - lo + 1;
+        {
+            // rows with candidates move to the low lanes, in order, empty rows after them
+            // (a permutation of the wave), so that row starts are distinct candidates
+            const uint64_t ne = __ballot(cnt > 0);
+            const int dst = cnt > 0 ? mbcnt64(ne) : __popcll(ne) + mbcnt64(~ne);
+            const int a = dst << 2;
+            lo = __builtin_amdgcn_ds_permute(a, lo);
+            cnt = __builtin_amdgcn_ds_permute(a, cnt);
+            grow = __builtin_amdgcn_ds_permute(a, grow);
+            s_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(s_lo)));
+            U_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(U_lo)));
+            V_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(V_lo)));
+        }
+        const int n_ne = __popcll(__ballot(cnt > 0));
         const int incl = wave_incl_scan(cnt);
         const int excl = incl - cnt;
         const int total = readlane(incl, kWave - 1);   // wave-uniform: the chunk loop stays scalar
         // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
-        // rows are walked once, wave-uniformly, as the chunks advance
+        // rows are walked once, wave-uniformly, as the chunks advance (rcur: row of
+        // the first candidate of the next chunk)
         int rcur = 0;
         int64_t written = out0;
         // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
@@ -842,15 +900,15 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                 if (in_box) mlp::features(d, au, av, a_f, x);
                 const float y = mlp::forward_wave(P.mlp_p, wf, x, s_h1);
                 if (in_box) D = y * g * g;
-                else if (member) D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
+                else if (member) D = dose_value<K, GUARD, SE>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
             }
             if (member) {
                 const float kf = (float)k;
                 if (GEN)
-                    D = dose_value_gen<K>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                    D = dose_value_gen<K, SE>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
                                           fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
                 else if (!SURR)
-                    D = dose_value<K, GUARD>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                    D = dose_value<K, GUARD, SE>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
                                              fmaf(kf, V1f, vl));
                 if (slot < avail) {
                     *(gptr<int32_t>)(ip + (slot << 2)) = gr * nx + ix;
@@ -862,19 +920,29 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             written += __popcll(mask);
         };
         auto walk2 = [&](auto dense_tag) {
-            // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane
+            // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane.
+            // Bit b of (mhi:mlo) marks a row starting at candidate c0 + b (0 < b < 128);
+            // a lane's row is rcur plus the row starts at or below its candidate, a
+            // masked bit count of the mask shifted down by one
             for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
-                while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
-                const int p1 = c0 + lane, p2 = p1 + kWave;
-                int r1 = rcur, r2 = rcur;
-                for (int q = rcur + 1; q < kWave; ++q) {
-                    const int eq = readlane(excl, q);
-                    if (eq > c0 + 2 * kWave - 1) break;
-                    if (p1 >= eq) r1 = q;
-                    if (p2 >= eq) r2 = q;
+                uint64_t mlo = 0, mhi = 0;
+                int rnext = rcur;
+                for (int q = rcur + 1; q < n_ne; ++q) {
+                    const int b = readlane(excl, q) - c0;
+                    if (b > 2 * kWave) break;
+                    rnext = q;
+                    if (b == 2 * kWave) break;
+                    if (b < kWave) mlo |= 1ull << b;
+                    else mhi |= 1ull << (b - kWave);
                 }
-                chunk(p1, r1, dense_tag);
-                chunk(p2, r2, dense_tag);
+                const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
+                const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rcur));
+                const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rcur + __popcll(nlo))));
+                chunk(c0 + lane, r1, dense_tag);
+                chunk(c0 + kWave + lane, r2, dense_tag);
+                rcur = rnext;
             }
         };
         if (!SURR) {
@@ -896,14 +964,14 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     }
 }
 
-template <int K, bool SURR, bool GEN>
+template <int K, bool SURR, bool GEN, bool SE>
 __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     // launched before the host has read the plan's total: write nothing if it does not fit
     if (outs[0].check_nnz && *plans[0].nnz > outs[0].capacity) return;
-    fill_beamlet<K, kWavesPerBlock, false, SURR, GEN>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
+    fill_beamlet<K, kWavesPerBlock, false, SURR, GEN, SE>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
 }
 
 /* ------------------------------------------------------------ batches */
@@ -948,7 +1016,7 @@ __global__ __launch_bounds__(kScanBlock) void kp_scan(const PlanDev *const *__re
 }
 
 template <int K, int W>
-__global__ __launch_bounds__(W * kWave) void kp_fill(const PlanDev *const *__restrict__ plans,
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(4))) void kp_fill(const PlanDev *const *__restrict__ plans,
                                                      const OutDev *__restrict__ outs,
                                                      const int2 *__restrict__ items, int n_items,
                                                      int *__restrict__ counter)
@@ -962,7 +1030,10 @@ __global__ __launch_bounds__(W * kWave) void kp_fill(const PlanDev *const *__res
         __syncthreads();
         if (w >= n_items) break;
         const int2 it = items[w];
-        fill_beamlet<K, W, true, false>(*plans[it.x], outs[it.x], it.y, smem);
+        const PlanDev &P = *plans[it.x];
+        // each plan in the erf table form of its own fill (identical results to it)
+        if (P.erf_mirrored && !P.use_mlp) fill_beamlet<K, W, true, false, false, true>(P, outs[it.x], it.y, smem);
+        else fill_beamlet<K, W, true, false>(P, outs[it.x], it.y, smem);
         __syncthreads();
     }
 }
@@ -1008,12 +1079,69 @@ hipError_t launch_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &
     return hipGetLastError();
 }
 
-size_t fill_shared_bytes(const PlanDev &h)
+size_t fill_shared_bytes(const PlanDev &h, bool mirrored_erf)
 {
-    size_t b = sizeof(float) * kErfLdsFloats + sizeof(float2) * ((size_t)h.max_table + (size_t)lds_pdd_pairs(h)) +
+    size_t b = sizeof(float) * (mirrored_erf ? 2 * kErfLdsFloats : kErfLdsFloats) + sizeof(float2) * ((size_t)h.max_table + (size_t)lds_pdd_pairs(h)) +
                sizeof(int) * ((size_t)h.max_tiles + 1);
     if (h.use_mlp) b = ((b + 15) & ~(size_t)15) + sizeof(uint16_t) * 64 * mlp::kH1Stride * kWavesPerBlock;
     return b;
+}
+
+size_t fill_shared_bytes(const PlanDev &h)
+{
+    return fill_shared_bytes(h, fill_mirrored_erf(h));
+}
+
+bool fill_mirrored_erf(const PlanDev &h) { return h.erf_mirrored && !h.use_mlp; }
+
+template <bool GEN>
+static const void *fill_kernel_ptr(int K, bool se)
+{
+    switch (K) {
+    case 1: return se ? (const void *)k_fill<1, false, GEN, true> : (const void *)k_fill<1, false, GEN, false>;
+    case 2: return se ? (const void *)k_fill<2, false, GEN, true> : (const void *)k_fill<2, false, GEN, false>;
+    case 3: return se ? (const void *)k_fill<3, false, GEN, true> : (const void *)k_fill<3, false, GEN, false>;
+    default: return se ? (const void *)k_fill<4, false, GEN, true> : (const void *)k_fill<4, false, GEN, false>;
+    }
+}
+
+/*
+ * Workgroups of a fill kernel per CU: the runtime's limit from registers and
+ * waves, and an LDS limit computed here with the allocation (static + dynamic)
+ * rounded up to 512 bytes and counted in two halves of the CU's LDS.  The
+ * halves are what the measured fill times follow: the mirrored table takes
+ * the slab (24 KB per workgroup) 2 % faster at five workgroups per CU, and the
+ * pelvis (27 KB, three per half would need 83 KB) 7 % slower, though the
+ * runtime's query (160 KB, whole) gives five for both.
+ */
+static int fill_groups_per_cu(const void *f, size_t lds, int lds_per_cu)
+{
+    int n = 0;
+    hipFuncAttributes attr{};
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, 0) != hipSuccess ||
+        hipFuncGetAttributes(&attr, f) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    const size_t need = (lds + attr.sharedSizeBytes + 511) & ~(size_t)511;
+    return std::min(n, 2 * (int)((size_t)(lds_per_cu / 2) / need));
+}
+
+int choose_erf_form(const PlanDev &h)
+{
+    const size_t lds_m = fill_shared_bytes(h, true), lds_s = fill_shared_bytes(h, false);
+    if (lds_m > 64 * 1024) return 0;
+    int dev = 0, lds_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds_cu <= 0) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const void *fm = h.gen ? fill_kernel_ptr<true>(h.n_terms, true) : fill_kernel_ptr<false>(h.n_terms, true);
+    const void *fs = h.gen ? fill_kernel_ptr<true>(h.n_terms, false) : fill_kernel_ptr<false>(h.n_terms, false);
+    const int nm = fill_groups_per_cu(fm, lds_m, lds_cu), ns = fill_groups_per_cu(fs, lds_s, lds_cu);
+    return nm > 0 && nm >= ns ? 1 : 0;
 }
 
 hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,
@@ -1071,29 +1199,19 @@ hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &
     if (n_rows <= 0) return hipSuccess;
     const dim3 grid(n_rows), block(kBlock);
     const size_t lds = fill_shared_bytes(h);
-    if (h.gen) {
+    if (h.use_mlp) {
         switch (h.n_terms) {
-        case 1: hipLaunchKernelGGL((k_fill<1, false, true>), grid, block, lds, s, dplan, dout); break;
-        case 2: hipLaunchKernelGGL((k_fill<2, false, true>), grid, block, lds, s, dplan, dout); break;
-        case 3: hipLaunchKernelGGL((k_fill<3, false, true>), grid, block, lds, s, dplan, dout); break;
-        default: hipLaunchKernelGGL((k_fill<4, false, true>), grid, block, lds, s, dplan, dout); break;
+        case 1: hipLaunchKernelGGL((k_fill<1, true, false, false>), grid, block, lds, s, dplan, dout); break;
+        case 2: hipLaunchKernelGGL((k_fill<2, true, false, false>), grid, block, lds, s, dplan, dout); break;
+        case 3: hipLaunchKernelGGL((k_fill<3, true, false, false>), grid, block, lds, s, dplan, dout); break;
+        default: hipLaunchKernelGGL((k_fill<4, true, false, false>), grid, block, lds, s, dplan, dout); break;
         }
-    } else if (h.use_mlp) {
-        switch (h.n_terms) {
-        case 1: hipLaunchKernelGGL((k_fill<1, true, false>), grid, block, lds, s, dplan, dout); break;
-        case 2: hipLaunchKernelGGL((k_fill<2, true, false>), grid, block, lds, s, dplan, dout); break;
-        case 3: hipLaunchKernelGGL((k_fill<3, true, false>), grid, block, lds, s, dplan, dout); break;
-        default: hipLaunchKernelGGL((k_fill<4, true, false>), grid, block, lds, s, dplan, dout); break;
-        }
-    } else {
-        switch (h.n_terms) {
-        case 1: hipLaunchKernelGGL((k_fill<1, false, false>), grid, block, lds, s, dplan, dout); break;
-        case 2: hipLaunchKernelGGL((k_fill<2, false, false>), grid, block, lds, s, dplan, dout); break;
-        case 3: hipLaunchKernelGGL((k_fill<3, false, false>), grid, block, lds, s, dplan, dout); break;
-        default: hipLaunchKernelGGL((k_fill<4, false, false>), grid, block, lds, s, dplan, dout); break;
-        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    const void *f = h.gen ? fill_kernel_ptr<true>(h.n_terms, fill_mirrored_erf(h))
+                          : fill_kernel_ptr<false>(h.n_terms, fill_mirrored_erf(h));
+    void *args[] = {const_cast<PlanDev **>(&dplan), const_cast<OutDev **>(&dout)};
+    return hipLaunchKernel(f, grid, block, args, lds, s);
 }
 
 }  // namespace fspb

@@ -95,6 +95,32 @@ def test_heterogeneous_full_parity(torch_gpu, oracle_lib, seed, n, gantries, sad
     _say(f"  nnz={csr.nnz} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e} band={r['band_mismatches']}")
 
 
+@pytest.mark.parametrize("pdd_step", [0.1, 0.02])
+def test_erf_table_forms(torch_gpu, oracle_lib, pdd_step):
+    """The fill stages erf mirrored onto [-4, 4] (16 KB) unless that costs it a
+    workgroup per CU; a depth dose of 3001 nodes (24 KB of LDS) makes the
+    mirrored form too large, so the 8 KB symmetric table is taken.  Both forms
+    must match the oracle."""
+    g = fi.slab_phantom(44, n=(37, 29, 23), spacing=(0.45, 0.5, 0.55), lung_side=(2, 8), bone_side=(1, 3))
+    beams = []
+    for gd in (17.0, 95.0, 181.0):
+        beams += fi.coplanar_beams(1, (0.3, 0.2, -0.1), 80.0, 0.7, 0.9, 5, 3, start_deg=gd)
+    k = fi.default_kernel(44)
+    k.cutoff_u, k.cutoff_v = 2.1, 2.7
+    if pdd_step != k.pdd_step:
+        x = np.arange(int(round((len(k.pdd) - 1) * k.pdd_step / pdd_step)) + 1) * pdd_step
+        k.pdd = np.interp(x, np.arange(len(k.pdd)) * k.pdd_step, k.pdd).astype(np.float32)
+        k.pdd_step = pdd_step
+    _say(f"parity: erf table form, {len(k.pdd)} depth-dose nodes")
+    plan, csr, ora, r = _full_compare(oracle_lib, fi.Problem("erf_form", g, beams, k))
+    # LDS of the symmetric form is 8 KB of erf + 8 B per depth / dose node + the tile offsets
+    pairs = 8 * (plan.desc.max_table + len(k.pdd))
+    mirrored = plan.desc.fill_lds_bytes >= 16384 + pairs
+    assert mirrored == (len(k.pdd) < 1000), f"fill LDS {plan.desc.fill_lds_bytes} B for {pairs} B of tables"
+    _say(f"  mirrored={mirrored} lds={plan.desc.fill_lds_bytes} nnz={csr.nnz} max_rel={r['max_rel']:.2e} "
+         f"band={r['band_mismatches']}")
+
+
 def test_water_axes_on_voxel_faces(torch_gpu, oracle_lib):
     """Axes along voxel faces and through voxel edges (gantry 0/90/180/270, v = 0 row)."""
     g = fi.water_phantom((40, 40, 12), (0.5, 0.5, 0.5))

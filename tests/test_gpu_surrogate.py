@@ -107,7 +107,10 @@ def test_training_is_deterministic(torch_gpu):
 
 
 def test_fallback_outside_the_training_box(torch_gpu):
-    """Beamlets narrower than the box (a = 0.2) never use the network: bit-identical to analytic."""
+    """Beamlets narrower than the box (a = 0.2) never use the network: the analytic
+    kernel's pattern and values.  The surrogate fill keeps the 8 KB erf table while the
+    plain fill of a plan this small stages the mirrored one, so values agree to the
+    rounding of the two table forms (the network's own error is 1e-3 of the maximum)."""
     torch = torch_gpu
     from paper_0908_4417_amd import Plan
     g = fi.slab_phantom(3, n=(40, 40, 30), spacing=(0.5, 0.5, 0.5), lung_side=(3, 6), bone_side=(1, 2))
@@ -119,7 +122,9 @@ def test_fallback_outside_the_training_box(torch_gpu):
     sur = _sur(fi.surrogate_init(3))
     plan.set_surrogate(sur)
     b = plan.compute()
-    assert torch.equal(ai, b.indices) and torch.equal(av, b.values)
+    assert torch.equal(ai, b.indices)
+    av, bv = av.double().cpu().numpy(), b.values.double().cpu().numpy()
+    np.testing.assert_allclose(bv, av, rtol=1e-5, atol=1e-7 * av.max())
     # a plan with other kernel parameters is refused
     import paper_0908_4417_amd as m
     other = Plan(fi.Problem("o", g, prob.beams, fi.default_kernel(4)), "cuda:0")
