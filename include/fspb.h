@@ -131,7 +131,8 @@ typedef struct {
     double table_step;           /* nominal depth-table element; <= 0 selects half the
                                     smallest voxel spacing (Sec. 3.2) */
     float rho_min;               /* voxels with density <= rho_min are in no VOI */
-    uint32_t flags;              /* 0 or FSPB_DEPTH_TRILINEAR */
+    uint32_t flags;              /* 0, or FSPB_DEPTH_TRILINEAR and at most one of
+                                    FSPB_ERF_COMPACT, FSPB_ERF_MIRRORED */
     const fspb_kernel_tables *tables;   /* NULL: the analytic form above (weight, sigma0,
                                            sigma_slope, width_scale, pdd); else these tables
                                            replace them (pdd is still validated, unused) */
@@ -145,6 +146,20 @@ typedef struct {
  * through the voxels (the default).
  */
 #define FSPB_DEPTH_TRILINEAR 1u
+
+/*
+ * kernel.flags: the form in which the fill stages its erf table (linear
+ * interpolation between 1025 nodes on [0, 4], the same interpolant in both
+ * forms, so the coefficients agree to rounding).  By default plan creation
+ * takes the mirrored form (16 KB, the table extended onto [-4, 4] so that a
+ * signed argument is read directly) unless its larger LDS footprint would
+ * cost the fill workgroups per CU on the current device, and the compact form
+ * (8 KB on [0, 4], the sign restored by odd symmetry) otherwise.  These flags
+ * force one form; FSPB_ERF_MIRRORED fails with FSPB_ERR_INVALID when the
+ * fill's LDS would then exceed 64 KB.
+ */
+#define FSPB_ERF_COMPACT  2u
+#define FSPB_ERF_MIRRORED 4u
 
 /* Static description of a created plan. */
 typedef struct {
@@ -231,6 +246,30 @@ fspb_status fspb_dose_coeffs_rows(fspb_plan *plan, int32_t j0, int32_t j1, const
                                   int32_t *indices, float *values, int64_t capacity, int64_t *nnz_out,
                                   void *stream);
 
+/*
+ * The partition of a plan's rows for the small-memory mode (Sec. 4: a plan
+ * computed a few beams at a time, each part copied out before the next):
+ * consecutive beamlet ranges [bounds[k], bounds[k + 1]), k < *n_ranges, each
+ * of whose entries take at most max_bytes (8 bytes per entry: FP32 value and
+ * int32 column), to be filled one after another with fspb_dose_coeffs_rows.
+ * Each range is as long as the budget allows (greedy from row 0).  With
+ * beam_rows (n_beams > 0; beam_rows[b] = nu * nv of beam b, summing to
+ * n_rows) a range ends at the furthest beam boundary that fits, and only a
+ * range that cannot hold the rest of its beam ends inside it; with n_beams =
+ * 0 every row boundary is a candidate.  Host-only: no device work.
+ *
+ * indptr     HOST, n_rows + 1 non-decreasing int64 row pointers (the counts of
+ *            fspb_dose_coeffs with NULL indices, copied to the host).
+ * bounds     HOST out, max_ranges + 1 int32 (bounds[0] = 0, bounds[*n_ranges] = n_rows);
+ *            NULL = size query.
+ * n_ranges   HOST out: number of ranges.
+ * Errors: INVALID (bad arguments, or a single row larger than the budget:
+ * nothing written), CAPACITY (bounds NULL or more than max_ranges ranges;
+ * *n_ranges reports the count, bounds is not written).
+ */
+fspb_status fspb_row_ranges(const int64_t *indptr, int32_t n_rows, const int32_t *beam_rows, int32_t n_beams,
+                            int64_t max_bytes, int32_t *bounds, int32_t max_ranges, int32_t *n_ranges);
+
 /* Release the plan's host metadata (the workspace stays the caller's). NULL is a no-op. */
 void fspb_plan_destroy(fspb_plan *plan);
 
@@ -273,7 +312,9 @@ fspb_status fspb_plan_get_timing(fspb_plan *plan, fspb_timing *out);
  * needs no host synchronisation and can be replayed.  Plans stay owned by
  * the caller and must outlive the batch; while a plan belongs to a batch it
  * must not be run on its own concurrently with the batch (they share its
- * workspace).
+ * workspace).  A batch computes Eq. 2-3 analytically: plans with kernel
+ * tables or with a surrogate attached are rejected at creation, and a
+ * surrogate cannot be attached to a plan while a batch holds it.
  * ------------------------------------------------------------------------ */
 typedef struct fspb_batch fspb_batch;
 
@@ -412,6 +453,7 @@ fspb_status fspb_surrogate_set_params(fspb_surrogate *sur, const float *params);
  * Attach a surrogate to a plan (NULL detaches it: analytic fill).  The plan's
  * kernel parameters must equal the surrogate's (same terms, widths, sigma
  * law and depth-dose table); the surrogate must outlive the attachment.
+ * INVALID when the plan uses kernel tables or belongs to a live batch.
  * After the plan's first fspb_raytrace this waits for all device work, then
  * replaces the device copy of the plan record.
  */

@@ -19,6 +19,8 @@ FSPB_ERR_HIP = -4
 FSPB_ERR_NOMEM = -5
 FSPB_ERR_OVERFLOW = -6
 FSPB_DEPTH_TRILINEAR = 1       # fspb_kernel.flags: trilinear-sampled depth table
+FSPB_ERF_COMPACT = 2           # fspb_kernel.flags: force the 8 KB erf table on [0, 4]
+FSPB_ERF_MIRRORED = 4          # fspb_kernel.flags: force the 16 KB erf table mirrored onto [-4, 4]
 
 
 class FspbError(RuntimeError):
@@ -124,6 +126,8 @@ _SIGS = {
     "fspb_surrogate_destroy": (None, [C.c_void_p]),
     "fspb_dose_coeffs_rows": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_int64, C.POINTER(C.c_int64), C.c_void_p]),
+    "fspb_row_ranges": (C.c_int32, [C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int64,
+                                    C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
     "fspb_fluence_dose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_fluence_gradient": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
@@ -341,6 +345,28 @@ def fspb_dose_coeffs_rows(h, j0, j1, indptr, indices, values, capacity, stream):
     if st == FSPB_ERR_CAPACITY:
         return st, n.value
     return _check(st), n.value
+
+
+def fspb_row_ranges(indptr, beam_rows, max_bytes):
+    """Host row partition of a byte budget: list of (j0, j1); beam_rows None = by beamlet.
+    Raises ValueError when a single row exceeds the budget."""
+    import numpy as np
+    ip = np.ascontiguousarray(indptr, dtype=np.int64)
+    n_rows = len(ip) - 1
+    br = None if beam_rows is None else np.ascontiguousarray(beam_rows, dtype=np.int32)
+    brp = None if br is None else br.ctypes.data_as(C.POINTER(C.c_int32))
+    nb = 0 if br is None else len(br)
+    ipp = ip.ctypes.data_as(C.POINTER(C.c_int64))
+    n = C.c_int32(0)
+    st = lib().fspb_row_ranges(ipp, n_rows, brp, nb, int(max_bytes), None, 0, C.byref(n))
+    if st == FSPB_ERR_INVALID:
+        raise ValueError(lib().fspb_last_error().decode())
+    if st != FSPB_ERR_CAPACITY:
+        _check(st)
+    bounds = np.zeros(n.value + 1, dtype=np.int32)
+    _check(lib().fspb_row_ranges(ipp, n_rows, brp, nb, int(max_bytes), bounds.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 n.value, C.byref(n)))
+    return [(int(bounds[k]), int(bounds[k + 1])) for k in range(n.value)]
 
 
 def fspb_fluence_dose(indptr, indices, values, n_rows, n_voxels, w, dose, stream):

@@ -174,6 +174,7 @@ struct fspb_plan {
     bool have_trace_ev = false, have_dose_ev = false;
     Staging *upload = nullptr;          // claimed staging buffer of a pending upload
     size_t upload_bytes = 0;            // its length: workspace bytes [0, upload_bytes)
+    int32_t batches = 0;                // live batches holding this plan
     int64_t *nnz_host = nullptr;        // pinned slot the nonzero count is read into
     hipEvent_t nnz_ready = nullptr;     // recorded after that read
     ~fspb_plan()
@@ -260,7 +261,10 @@ fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams
     if (!finite(K->cutoff_u) || !finite(K->cutoff_v) || !finite(K->table_step))
         return fail(FSPB_ERR_INVALID, "kernel cutoffs and table_step must be finite");
     if (!std::isfinite(K->rho_min)) return fail(FSPB_ERR_INVALID, "kernel.rho_min must be finite");
-    if (K->flags & ~FSPB_DEPTH_TRILINEAR) return fail(FSPB_ERR_INVALID, "kernel.flags has unknown bits");
+    if (K->flags & ~(FSPB_DEPTH_TRILINEAR | FSPB_ERF_COMPACT | FSPB_ERF_MIRRORED))
+        return fail(FSPB_ERR_INVALID, "kernel.flags has unknown bits");
+    if ((K->flags & FSPB_ERF_COMPACT) && (K->flags & FSPB_ERF_MIRRORED))
+        return fail(FSPB_ERR_INVALID, "kernel.flags: FSPB_ERF_COMPACT and FSPB_ERF_MIRRORED exclude each other");
     if (const fspb_kernel_tables *T = K->tables) {
         if (T->n_depth < 2 || T->n_adepth < 2 || T->n_theta < 1 || T->reserved != 0)
             return fail(FSPB_ERR_INVALID, "kernel.tables: n_depth, n_adepth must be >= 2, n_theta >= 1, reserved 0");
@@ -733,7 +737,16 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     // fspb_raytrace or fspb_batch_create copies it on its stream
     int dev = 0;
     FSPB_HIP(hipGetDevice(&dev), "get device");
-    h.erf_mirrored = erf_form(h, dev);
+    if (K->flags & FSPB_ERF_MIRRORED) {
+        if (fspb::fill_shared_bytes(h, true) > 64 * 1024)
+            return fail(FSPB_ERR_INVALID, "FSPB_ERF_MIRRORED: the fill would need %zu bytes of LDS (64 KB at most)",
+                        fspb::fill_shared_bytes(h, true));
+        h.erf_mirrored = 1;
+    } else if (K->flags & FSPB_ERF_COMPACT) {
+        h.erf_mirrored = 0;
+    } else {
+        h.erf_mirrored = erf_form(h, dev);
+    }
     FSPB_HIP(hipEventCreateWithFlags(&p->nnz_ready, hipEventDisableTiming), "create count event");
     st = slot_acquire(&p->nnz_host);
     if (st != FSPB_OK) return st;
@@ -860,6 +873,58 @@ fspb_status fspb_dose_coeffs_rows(fspb_plan *p, int32_t j0, int32_t j1, const in
     p->out.check_nnz = 0;   // the range's size was checked above
     FSPB_HIP(hipMemcpyAsync(p->d_out, &p->out, sizeof(OutDev), hipMemcpyHostToDevice, s), "upload output record");
     FSPB_HIP(fspb::launch_fill(p->d_plan, p->d_out, p->h, j0, j1 - j0, s), "launch fill");
+    return FSPB_OK;
+}
+
+fspb_status fspb_row_ranges(const int64_t *indptr, int32_t n_rows, const int32_t *beam_rows, int32_t n_beams,
+                            int64_t max_bytes, int32_t *bounds, int32_t max_ranges, int32_t *n_ranges)
+{
+    g_last_error.clear();
+    if (!indptr || !n_ranges) return fail(FSPB_ERR_INVALID, "indptr or n_ranges is NULL");
+    if (n_rows < 0 || n_beams < 0 || max_bytes < 0 || max_ranges < 0)
+        return fail(FSPB_ERR_INVALID, "n_rows, n_beams, max_bytes and max_ranges must be >= 0");
+    if (n_beams > 0 && !beam_rows) return fail(FSPB_ERR_INVALID, "beam_rows is NULL");
+    for (int32_t j = 0; j < n_rows; ++j)
+        if (indptr[j + 1] < indptr[j]) return fail(FSPB_ERR_INVALID, "indptr decreases at row %d", j);
+    // candidate ends: the beam boundaries (by beam), or every row boundary
+    std::vector<int32_t> units;
+    if (n_beams > 0) {
+        int64_t acc = 0;
+        units.push_back(0);
+        for (int32_t b = 0; b < n_beams; ++b) {
+            if (beam_rows[b] < 0) return fail(FSPB_ERR_INVALID, "beam_rows[%d] < 0", b);
+            acc += beam_rows[b];
+            units.push_back((int32_t)std::min<int64_t>(acc, INT32_MAX));
+        }
+        if (acc != n_rows) return fail(FSPB_ERR_INVALID, "beam_rows sum to %lld, not %d rows", (long long)acc, n_rows);
+    }
+    const int64_t cap = max_bytes / 8;   // FP32 value + int32 column per entry
+    int32_t count = 0, j0 = 0;
+    size_t u = 0;                        // first beam boundary > j0
+    std::vector<int32_t> ends;
+    while (j0 < n_rows) {
+        const int64_t limit = indptr[j0] + cap;
+        while (u < units.size() && units[u] <= j0) ++u;
+        int32_t j1 = j0;
+        // furthest beam boundary that fits, else furthest row boundary
+        for (size_t k = u; k < units.size() && indptr[units[k]] <= limit; ++k) j1 = units[k];
+        if (j1 == j0) {
+            int32_t r = j0 + 1;
+            if (indptr[r] > limit)
+                return fail(FSPB_ERR_INVALID, "row %d alone needs %lld bytes, more than the budget of %lld", j0,
+                            (long long)(8 * (indptr[r] - indptr[j0])), (long long)max_bytes);
+            while (r + 1 <= n_rows && indptr[r + 1] <= limit) ++r;
+            j1 = r;
+        }
+        ends.push_back(j1);
+        ++count;
+        j0 = j1;
+    }
+    *n_ranges = count;
+    if (!bounds || count > max_ranges)
+        return fail(FSPB_ERR_CAPACITY, "%d ranges do not fit max_ranges = %d", count, bounds ? max_ranges : 0);
+    bounds[0] = 0;
+    for (int32_t k = 0; k < count; ++k) bounds[k + 1] = ends[(size_t)k];
     return FSPB_OK;
 }
 
@@ -1069,6 +1134,8 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
     for (int i = 0; i < n_plans; ++i) {
         if (!plans[i]) return fail(FSPB_ERR_INVALID, "plans[%d] is NULL", i);
         if (plans[i]->h.gen) return fail(FSPB_ERR_INVALID, "plans[%d] uses kernel tables (not batched)", i);
+        if (plans[i]->h.use_mlp)
+            return fail(FSPB_ERR_INVALID, "plans[%d] has a surrogate attached (a batch computes Eq. 2-3 analytically)", i);
         for (int k = 0; k < i; ++k)
             if (plans[k] == plans[i]) return fail(FSPB_ERR_INVALID, "plan %d appears twice", i);
     }
@@ -1178,6 +1245,7 @@ fspb_status fspb_batch_create(fspb_plan *const *plans, int32_t n_plans, void *wo
         if (it != g_tune_cache.end()) b->cfg = it->second;
     }
     FSPB_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "create capture stream");
+    for (fspb_plan *q : b->plans) ++q->batches;
     *out = guard.release();
     return FSPB_OK;
 }
@@ -1322,7 +1390,12 @@ fspb_status fspb_batch_check(fspb_batch *b, void *stream)
     return FSPB_OK;
 }
 
-void fspb_batch_destroy(fspb_batch *b) { delete b; }
+void fspb_batch_destroy(fspb_batch *b)
+{
+    if (!b) return;
+    for (fspb_plan *q : b->plans) --q->batches;
+    delete b;
+}
 
 }  // extern "C"
 
@@ -1562,6 +1635,8 @@ fspb_status fspb_plan_set_surrogate(fspb_plan *p, const fspb_surrogate *s)
     if (!p) return fail(FSPB_ERR_INVALID, "plan is NULL");
     if (s && p->h.gen)
         return fail(FSPB_ERR_INVALID, "the surrogate models the analytic kernel; this plan uses kernel tables");
+    if (s && p->batches > 0)
+        return fail(FSPB_ERR_INVALID, "the plan belongs to %d batch(es), which compute Eq. 2-3 analytically", p->batches);
     if (s) {
         bool same = s->n_terms == p->n_terms && s->pdd_step == p->pdd_step && s->pdd == p->pdd;
         for (int i = 0; same && i < p->n_terms; ++i)

@@ -83,7 +83,10 @@ class VoxelCSR:
         return d
 
 
-def _structs(problem, density_ptr):
+_ERF_FORMS = {None: 0, "compact": L.FSPB_ERF_COMPACT, "mirrored": L.FSPB_ERF_MIRRORED}
+
+
+def _structs(problem, density_ptr, erf_form=None):
     g = problem.grid
     nz, ny, nx = g.density.shape
     grid = L.FspbGrid(nx, ny, nz, 0, (C.c_double * 3)(*g.spacing), (C.c_double * 3)(*g.origin),
@@ -98,7 +101,7 @@ def _structs(problem, density_ptr):
     kern = L.FspbKernel(kp.n_terms, len(pdd), pad(kp.weight), pad(kp.sigma0), pad(kp.sigma_slope),
                         pad(kp.width_scale), pdd.ctypes.data_as(C.POINTER(C.c_float)), kp.pdd_step,
                         kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min,
-                        L.FSPB_DEPTH_TRILINEAR if kp.depth == "trilinear" else 0)
+                        (L.FSPB_DEPTH_TRILINEAR if kp.depth == "trilinear" else 0) | _ERF_FORMS[erf_form])
     kt = getattr(kp, "tables", None)
     if kt is not None:
         arrs = [np.ascontiguousarray(x, dtype=np.float32) for x in (kt.c1, kt.c2, kt.c3, kt.A)]
@@ -113,29 +116,12 @@ def _structs(problem, density_ptr):
 
 def chunk_ranges(indptr, beam_rows, max_bytes, by_beam=True):
     """Beamlet ranges [j0, j1) covering all rows whose entries take at most
-    ``max_bytes`` each (8 bytes per entry), given the row pointers.  With
-    ``by_beam`` a range ends at a beam boundary where one fits (the paper
-    computes a plan beam by beam on a small card); otherwise, or inside a beam
-    too large for the budget, at a beamlet.  A single row larger than the
-    budget raises ValueError."""
-    per = np.asarray(indptr, dtype=np.int64)
-    n = len(per) - 1
-    cap = int(max_bytes) // 8
-    rows = np.arange(n + 1)
-    units = np.concatenate([[0], np.cumsum(beam_rows)]).astype(np.int64) if by_beam else rows
-    out = []
-    j0 = 0
-    while j0 < n:
-        limit = per[j0] + cap
-        cand = units[(units > j0) & (per[units] <= limit)]
-        if len(cand) == 0:
-            cand = rows[(rows > j0) & (per[rows] <= limit)]
-            if len(cand) == 0:
-                raise ValueError(f"row {j0} alone needs {8 * int(per[j0 + 1] - per[j0])} bytes")
-        j1 = int(cand.max())
-        out.append((j0, j1))
-        j0 = j1
-    return out
+    ``max_bytes`` each (8 bytes per entry), given the host row pointers: the
+    library's fspb_row_ranges.  With ``by_beam`` a range ends at a beam
+    boundary where one fits (the paper computes a plan beam by beam on a small
+    card); otherwise, or inside a beam too large for the budget, at a beamlet.
+    A single row larger than the budget raises ValueError."""
+    return L.fspb_row_ranges(indptr, beam_rows if by_beam else None, max_bytes)
 
 
 class Plan:
@@ -144,17 +130,18 @@ class Plan:
     ``problem`` is a ``fspb_inputs.Problem`` (or anything with the same
     fields).  The density is copied to the device once; the plan borrows that
     tensor, and ``set_density`` may overwrite it in place (same shape) before
-    the next ``raytrace``.
+    the next ``raytrace``.  ``erf_form`` ("compact", "mirrored") forces the
+    fill's erf table form; None lets plan creation choose it.
     """
 
-    def __init__(self, problem, device="cuda:0", density=None):
+    def __init__(self, problem, device="cuda:0", density=None, erf_form=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         if density is None:
             density = torch.from_numpy(np.ascontiguousarray(problem.grid.density, dtype=np.float32))
         self.density = density.to(self.device, dtype=torch.float32).contiguous()
-        grid, beams, kern, self._pdd = _structs(problem, self.density.data_ptr())
+        grid, beams, kern, self._pdd = _structs(problem, self.density.data_ptr(), erf_form)
         st, _, need = L.fspb_plan_create(grid, beams, len(problem.beams), kern, None, 0)
         assert st == L.FSPB_ERR_CAPACITY
         self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
