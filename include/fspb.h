@@ -504,9 +504,11 @@ fspb_status fspb_fluence_gradient(const int64_t *indptr, const int32_t *indices,
  *   t_values (nnz): DEVICE, written.
  * workspace: DEVICE, 256-byte aligned, caller-owned, about 24 bytes per
  * entry; NULL = size query (returns FSPB_ERR_CAPACITY and sets
- * *workspace_needed).  nnz must be below 2^32.  Synchronises `stream` twice
- * (after the voxel-row pointers and after the stretch count); a column index outside
- * [0, n_voxels) returns FSPB_ERR_INVALID with only t_indptr written.
+ * *workspace_needed).  nnz must be below 2^32.  Stream-ordered: no host
+ * synchronisation, so the call can be captured in a HIP graph.  An entry
+ * whose column lies outside [0, n_voxels) is left out: t_indptr counts the
+ * valid entries only (t_indptr[n_voxels] < nnz tells the caller), and
+ * t_indices / t_values past t_indptr[n_voxels] are unspecified.
  */
 fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int32_t n_rows,
                                int32_t n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices,

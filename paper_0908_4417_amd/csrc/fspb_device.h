@@ -131,12 +131,12 @@ hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices
 hipError_t launch_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values, int n_voxels,
                              int n_w, const float *w, float *dose, hipStream_t s);
 size_t transpose_workspace(int64_t nnz, int n_voxels, int n_rows);
-int transpose_passes(int n_voxels);
-/* Synchronises s; *bad_host = 1 when a column index lies outside [0, n_voxels)
- * (then only t_indptr is written). */
+int transpose_passes(int n_keys);
+/* Stream-ordered (no host synchronisation); entries whose column lies outside
+ * [0, n_voxels) are left out of the voxel rows. */
 hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
                             int n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices, float *t_values,
-                            void *workspace, int32_t *bad_host, hipStream_t s);
+                            void *workspace, hipStream_t s);
 
 /* Batched launches over n_plans plans (persistent grids). */
 hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,

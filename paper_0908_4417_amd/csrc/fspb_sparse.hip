@@ -4,18 +4,28 @@
  *   beamlet-row CSR (what the fill writes: row j = beamlet, columns = voxels)
  *     k_fluence_dose      dose_i += w_j D_ij with FP32 atomics   -- one wave per row
  *     k_fluence_gradient  g_j = sum_i D_ij r_i, fixed order      -- one wave per row
- *   voxel-row CSR (row i = voxel, columns = beamlets), built by
- *     k_expand_rows, k_col_count + scan         row ids of the entries, voxel-row pointers
- *     k_rs_hist, scan, k_rs_scatter             one pass of a stable LSD radix sort on the
- *                                               voxel index, 8 bits per pass
+ *   voxel-row CSR (row i = voxel, columns = beamlets): the transpose, a stable
+ *   sort of the row-major entries by column
+ *     k_key_count + scan                        voxel-row pointers
+ *     run path (the default for D, whose rows are long stretches of columns):
+ *       k_run_count + scan, k_run_sizes        stretches of each row within one
+ *                                              32-column bucket; the path flag
+ *       k_run_emit, k_key_count + scan         run records, bucket pointers
+ *       k_rs_hist, scan, k_rs_scatter          stable LSD radix sort of the runs by bucket
+ *       k_bucket_place                         one wave per bucket places its runs'
+ *                                              entries by a counting sort on the column
+ *     entry path (short stretches):
+ *       k_expand_rows, then k_rs_hist, scan, k_rs_scatter per 8 bits of the column
  *     k_voxel_dose        dose_i = sum_j D_ij w_j, fixed order  -- 16 lanes per voxel row
  *
- * The radix sort is stable and the input rows are in ascending beamlet order,
- * so every voxel row lists its beamlets in ascending order: the transpose is
- * canonical and bit-reproducible.
+ * Both sorts are stable and the input rows are in ascending beamlet order, so
+ * every voxel row lists its beamlets in ascending order: the transpose is
+ * canonical and bit-reproducible.  It runs without host synchronisation.
  */
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "fspb_device.h"
 
@@ -228,58 +238,87 @@ __global__ __launch_bounds__(kBlock) void k_voxel_dose(const int64_t *__restrict
 
 /* ------------------------------------------------------------ transpose */
 
+/*
+ * The transpose never synchronises the host: both of its sort paths are
+ * enqueued, and a flag the device computes from the data (how long the
+ * stretches of each row within a bucket of columns are) lets one of them run;
+ * the other's kernels return at once.  Sizes only the device knows (the number
+ * of stretches) are read by the kernels themselves, which walk their work
+ * grid-stride from a grid sized by a host bound.
+ */
+struct Gate {
+    const int32_t *flag;   // nullptr: always run
+    int32_t want;
+};
+__device__ inline bool gate_closed(Gate g) { return g.flag && *g.flag != g.want; }
+
+/* An element count known on the host (dev == nullptr) or read from device memory. */
+struct Count {
+    int64_t n;
+    const int64_t *dev;
+};
+__device__ inline int64_t count_of(Count c) { return c.dev ? *c.dev : c.n; }
+
 /* rows[e] = j for every entry e of row j (clamped to [0, nnz)); one wave per row. */
 __global__ __launch_bounds__(kBlock) void k_expand_rows(const int64_t *__restrict__ indptr, int n_rows, int64_t nnz,
-                                                        int32_t *__restrict__ rows)
+                                                        int32_t *__restrict__ rows, Gate g)
 {
+    if (gate_closed(g)) return;
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
     const int64_t e0 = indptr[j] > 0 ? indptr[j] : 0, e1 = indptr[j + 1] < nnz ? indptr[j + 1] : nnz;
     for (int64_t e = e0 + lane_id(); e < e1; e += kWave) rows[e] = j;
 }
 
-/* Entries per voxel; an index outside [0, n_voxels) raises *bad. */
-__global__ __launch_bounds__(kBlock) void k_col_count(const int32_t *__restrict__ indices, int64_t nnz,
-                                                      int n_voxels, uint32_t *__restrict__ counts,
-                                                      int32_t *__restrict__ bad)
+/* counts[k] += 1 for every key k in [0, n_valid) among the first n keys; other keys are skipped. */
+__global__ __launch_bounds__(kBlock) void k_key_count(const int32_t *__restrict__ keys, Count n_keys, int n_valid,
+                                                      uint32_t *__restrict__ counts, Gate g)
 {
+    if (gate_closed(g)) return;
+    const int64_t n = count_of(n_keys);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += stride) {
-        const uint32_t i = (uint32_t)indices[e];
-        if (i < (uint32_t)n_voxels) atomicAdd(counts + i, 1u);
-        else *bad = 1;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
+        const uint32_t i = (uint32_t)keys[e];
+        if (i < (uint32_t)n_valid) atomicAdd(counts + i, 1u);
     }
 }
 
-/* Scan, phase 1: sum of each kScanChunk-value chunk. */
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
-                                                        uint32_t *__restrict__ partial)
+/* Scan, phase 1: sum of each kScanChunk-value chunk (grid-stride over chunks). */
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ in, Count n_in,
+                                                        uint32_t *__restrict__ partial, Gate g)
 {
+    if (gate_closed(g)) return;
     __shared__ uint32_t s_w[kWavesPerBlock];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v = 0;
+    const int64_t n = count_of(n_in), nch = (n + kScanChunk - 1) / kScanChunk;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int64_t base = c * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+        uint32_t v = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) v += base + k < n ? in[base + k] : 0u;
-    v = wave_sum(v);
-    if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int k = 0; k < kWavesPerBlock; ++k) t += s_w[k];
-        partial[blockIdx.x] = t;
+        for (int k = 0; k < kScanItems; ++k) v += base + k < n ? in[base + k] : 0u;
+        v = wave_sum(v);
+        if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int k = 0; k < kWavesPerBlock; ++k) t += s_w[k];
+            partial[c] = t;
+        }
+        __syncthreads();
     }
 }
 
 /* Scan, phase 2: exclusive scan of the chunk sums in place (one workgroup);
  * partial[nb] = total, also stored to *total64 when given. */
-__global__ __launch_bounds__(kScanTop) void k_scan_top(uint32_t *__restrict__ partial, int nb,
-                                                       int64_t *__restrict__ total64)
+__global__ __launch_bounds__(kScanTop) void k_scan_top(uint32_t *__restrict__ partial, Count n_in,
+                                                       int64_t *__restrict__ total64, Gate g)
 {
+    if (gate_closed(g)) return;
     __shared__ uint32_t s_w[kScanTop / kWave];
+    const int64_t nb = (count_of(n_in) + kScanChunk - 1) / kScanChunk;
     const int l = lane_id(), w = threadIdx.x >> 6;
     uint32_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += kScanTop) {
-        const int i = b0 + threadIdx.x;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanTop) {
+        const int64_t i = b0 + threadIdx.x;
         const uint32_t v = i < nb ? partial[i] : 0u;
         uint32_t x = v;
 #pragma unroll
@@ -304,46 +343,57 @@ __global__ __launch_bounds__(kScanTop) void k_scan_top(uint32_t *__restrict__ pa
     }
 }
 
-/* Scan, phase 3: exclusive scan within each chunk plus its chunk offset. */
+/* Scan, phase 3: exclusive scan within each chunk plus its chunk offset (grid-stride). */
 template <typename OUT>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *__restrict__ in, int64_t n,
-                                                      const uint32_t *__restrict__ partial, OUT *__restrict__ out)
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *__restrict__ in, Count n_in,
+                                                      const uint32_t *__restrict__ partial, OUT *__restrict__ out,
+                                                      Gate g)
 {
+    if (gate_closed(g)) return;
     __shared__ uint32_t s_w[kWavesPerBlock];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t sum = 0;
+    const int64_t n = count_of(n_in), nch = (n + kScanChunk - 1) / kScanChunk;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int64_t base = c * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? in[base + k] : 0u;
-        sum += v[k];
-    }
-    uint32_t total;
-    uint32_t run = partial[blockIdx.x] + block_excl_scan(sum, s_w, &total);
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < n ? in[base + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        uint32_t run = partial[c] + block_excl_scan(sum, s_w, &total);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) out[base + k] = (OUT)run;
-        run += v[k];
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < n) out[base + k] = (OUT)run;
+            run += v[k];
+        }
     }
 }
 
 /* Radix pass, phase 1: digit histogram of each kSortTile-entry tile, stored
  * digit-major (hist[d * n_tiles + tile]) so that one exclusive scan gives every
- * (digit, tile) its first output slot. */
-__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
-                                                    uint32_t *__restrict__ hist, int n_tiles)
+ * (digit, tile) its first output slot.  Keys above `clamp` count as `clamp`
+ * (the sentinel that sorts entries with an invalid column last). */
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *__restrict__ keys, Count n_in, uint32_t clamp,
+                                                    int shift, uint32_t *__restrict__ hist, Gate g)
 {
+    if (gate_closed(g)) return;
     __shared__ uint32_t h[kRadix];
-    h[threadIdx.x] = 0u;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile + threadIdx.x;
+    const int64_t n = count_of(n_in), n_tiles = (n + kSortTile - 1) / kSortTile;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        h[threadIdx.x] = 0u;
+        __syncthreads();
+        const int64_t base = tile * kSortTile + threadIdx.x;
 #pragma unroll 4
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t i = base + (int64_t)r * kBlock;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+        for (int r = 0; r < kSortItems; ++r) {
+            const int64_t i = base + (int64_t)r * kBlock;
+            if (i < n) atomicAdd(&h[(min(keys[i], clamp) >> shift) & (kRadix - 1)], 1u);
+        }
+        __syncthreads();
+        hist[(int64_t)threadIdx.x * n_tiles + tile] = h[threadIdx.x];
+        __syncthreads();
     }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
 /*
@@ -356,16 +406,17 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *__restrict__
  * scan turns the waves' counts into tile-local slots (digit-major, lower
  * waves first), the tile is sorted by digit in LDS and written out in that
  * order, so each digit's run goes to consecutive addresses.  keys_out may be
- * NULL (last pass).
+ * NULL (last pass).  Grid-stride over the tiles.
  */
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
                                                        const int32_t *__restrict__ rows_in,
-                                                       const float *__restrict__ vals_in, int64_t n, int shift,
-                                                       const uint32_t *__restrict__ offs, int n_tiles,
+                                                       const float *__restrict__ vals_in, Count n_in, uint32_t clamp,
+                                                       int shift, const uint32_t *__restrict__ offs,
                                                        uint32_t *__restrict__ keys_out,
                                                        int32_t *__restrict__ rows_out,
-                                                       float *__restrict__ vals_out)
+                                                       float *__restrict__ vals_out, Gate g)
 {
+    if (gate_closed(g)) return;
     __shared__ uint32_t s_key[kSortTile];
     __shared__ int32_t s_row[kSortTile];
     __shared__ float s_val[kSortTile];
@@ -374,75 +425,79 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
     __shared__ uint32_t s_w[kWavesPerBlock];
     constexpr int kSub = kSortTile / kWavesPerBlock;    // entries per wave
     const int t = threadIdx.x, wave = t >> 6, lane = t & (kWave - 1);
-    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
-    const int64_t sub0 = tile0 + (int64_t)wave * kSub;
+    const int64_t n = count_of(n_in), n_tiles = (n + kSortTile - 1) / kSortTile;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t tile0 = tile * kSortTile;
+        const int64_t sub0 = tile0 + (int64_t)wave * kSub;
 #pragma unroll
-    for (int w = 0; w < kWavesPerBlock; ++w) cnt[w][t] = 0u;
-    __syncthreads();
+        for (int w = 0; w < kWavesPerBlock; ++w) cnt[w][t] = 0u;
+        __syncthreads();
 
-    uint32_t key[kSortItems], pos[kSortItems];
-    int32_t row[kSortItems];
-    float val[kSortItems];
+        uint32_t key[kSortItems], pos[kSortItems];
+        int32_t row[kSortItems];
+        float val[kSortItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t i = sub0 + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        key[r] = valid ? keys_in[i] : 0u;
-        row[r] = valid ? rows_in[i] : 0;
-        val[r] = valid ? vals_in[i] : 0.0f;
-        const uint32_t d = (key[r] >> shift) & (kRadix - 1);
-        uint64_t peers = __ballot(valid);
+        for (int r = 0; r < kSortItems; ++r) {
+            const int64_t i = sub0 + (int64_t)r * kWave + lane;
+            const bool valid = i < n;
+            key[r] = valid ? min(keys_in[i], clamp) : 0u;
+            row[r] = valid ? rows_in[i] : 0;
+            val[r] = valid ? vals_in[i] : 0.0f;
+            const uint32_t d = (key[r] >> shift) & (kRadix - 1);
+            uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            for (int b = 0; b < kRadixBits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint32_t rank = (uint32_t)mbcnt64(peers);
+            uint32_t before = 0u;
+            if (valid) before = cnt[wave][d];                 // every lane of the group reads the old count
+            if (valid && rank == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
+            pos[r] = before + rank;
         }
-        const uint32_t rank = (uint32_t)mbcnt64(peers);
-        uint32_t before = 0u;
-        if (valid) before = cnt[wave][d];                 // every lane of the group reads the old count
-        if (valid && rank == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
-        pos[r] = before + rank;
-    }
-    __syncthreads();
-    {
-        // thread t = digit t: tile-local start of the digit, then of each wave's part of it
-        uint32_t c[kWavesPerBlock], tot = 0;
+        __syncthreads();
+        {
+            // thread t = digit t: tile-local start of the digit, then of each wave's part of it
+            uint32_t c[kWavesPerBlock], tot = 0;
 #pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-            c[w] = cnt[w][t];
-            tot += c[w];
-        }
-        uint32_t total;
-        const uint32_t start = block_excl_scan(tot, s_w, &total);
-        uint32_t b = start;
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                c[w] = cnt[w][t];
+                tot += c[w];
+            }
+            uint32_t total;
+            const uint32_t start = block_excl_scan(tot, s_w, &total);
+            uint32_t b = start;
 #pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-            cnt[w][t] = b;
-            b += c[w];
+            for (int w = 0; w < kWavesPerBlock; ++w) {
+                cnt[w][t] = b;
+                b += c[w];
+            }
+            goff[t] = offs[(int64_t)t * n_tiles + tile] - start;
         }
-        goff[t] = offs[(int64_t)t * n_tiles + blockIdx.x] - start;
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t i = sub0 + (int64_t)r * kWave + lane;
-        if (i < n) {
-            const uint32_t lp = cnt[wave][(key[r] >> shift) & (kRadix - 1)] + pos[r];
-            s_key[lp] = key[r];
-            s_row[lp] = row[r];
-            s_val[lp] = val[r];
+        for (int r = 0; r < kSortItems; ++r) {
+            const int64_t i = sub0 + (int64_t)r * kWave + lane;
+            if (i < n) {
+                const uint32_t lp = cnt[wave][(key[r] >> shift) & (kRadix - 1)] + pos[r];
+                s_key[lp] = key[r];
+                s_row[lp] = row[r];
+                s_val[lp] = val[r];
+            }
         }
-    }
-    __syncthreads();
-    const int64_t rem = n - tile0;
-    const int m = rem < kSortTile ? (int)rem : kSortTile;
-    for (int lp = t; lp < m; lp += kBlock) {
-        const uint32_t key_ = s_key[lp];
-        const uint32_t p = goff[(key_ >> shift) & (kRadix - 1)] + (uint32_t)lp;
-        if (keys_out) keys_out[p] = key_;
-        rows_out[p] = s_row[lp];
-        vals_out[p] = s_val[lp];
+        __syncthreads();
+        const int64_t rem = n - tile0;
+        const int m = rem < kSortTile ? (int)rem : kSortTile;
+        for (int lp = t; lp < m; lp += kBlock) {
+            const uint32_t key_ = s_key[lp];
+            const uint32_t p = goff[(key_ >> shift) & (kRadix - 1)] + (uint32_t)lp;
+            if (keys_out) keys_out[p] = key_;
+            rows_out[p] = s_row[lp];
+            vals_out[p] = s_val[lp];
+        }
+        __syncthreads();
     }
 }
 
@@ -486,8 +541,9 @@ namespace {
 
 /*
  * Run transpose.  A run is a maximal stretch of consecutive entries of one row
- * whose columns share a bucket of kBucketCols columns (col >> kBucketShift).
- * The transpose sorts the runs by bucket (stably, so a bucket's runs keep row
+ * whose columns share a bucket of kBucketCols columns (col >> kBucketShift;
+ * a column outside [0, n_voxels) takes the sentinel bucket n_buckets).  The
+ * transpose sorts the runs by bucket (stably, so a bucket's runs keep row
  * order), then one wave per bucket walks its runs' entries in that order and
  * places each with a stable counting sort on the column's low bits: the
  * output is the stable sort of the row-major entries by column, as the radix
@@ -499,56 +555,81 @@ namespace {
 constexpr int kBucketShift = 5;
 constexpr int kBucketCols = 1 << kBucketShift;
 
+__device__ inline int bucket_key(int col, int n_voxels, int n_buckets)
+{
+    return (uint32_t)col < (uint32_t)n_voxels ? (col >> kBucketShift) : n_buckets;
+}
+
 /* run_cnt[j] = runs of row j; one wave per row.  *unsorted is set when a row's
  * columns are not strictly ascending. */
 __global__ __launch_bounds__(kBlock) void k_run_count(const int64_t *__restrict__ indptr,
-                                                      const int32_t *__restrict__ indices, int n_rows,
-                                                      uint32_t *__restrict__ run_cnt, int32_t *__restrict__ unsorted)
+                                                      const int32_t *__restrict__ indices, int n_rows, int n_voxels,
+                                                      int n_buckets, uint32_t *__restrict__ run_cnt,
+                                                      int32_t *__restrict__ unsorted)
 {
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
     const int lane = lane_id();
     const int64_t e0 = indptr[j], e1 = indptr[j + 1];
     uint32_t runs = 0;
-    int prev = -1;                                     // column of the entry before the chunk
+    int prev_col = 0, prev_b = -1;                     // entry before the chunk (bucket -1: none)
     bool down = false;
     for (int64_t c = e0; c < e1; c += kWave) {
         const int64_t e = c + lane;
         const bool in = e < e1;
         const int col = in ? indices[e] : 0;
-        int cp = __shfl_up(col, 1, kWave);
-        if (lane == 0) cp = prev;
-        const int b = col >> kBucketShift;
-        runs += (uint32_t)__popcll(__ballot(in && (cp < 0 || b != (cp >> kBucketShift))));
-        down = down || (in && cp >= 0 && col <= cp);
-        prev = __shfl(col, kWave - 1, kWave);
+        const int b = bucket_key(col, n_voxels, n_buckets);
+        int cp = __shfl_up(col, 1, kWave), bp = __shfl_up(b, 1, kWave);
+        if (lane == 0) {
+            cp = prev_col;
+            bp = prev_b;
+        }
+        runs += (uint32_t)__popcll(__ballot(in && b != bp));
+        down = down || (in && bp >= 0 && col <= cp);
+        prev_col = __shfl(col, kWave - 1, kWave);
+        prev_b = __shfl(b, kWave - 1, kWave);
     }
     if (lane == 0) run_cnt[j] = runs;
     if (__ballot(down) && lane == 0) *unsorted = 1;
 }
 
+/*
+ * The path flag: the run transpose when the runs are at most half the entries
+ * (a plan's D has tens of entries per run), else the radix sort of the
+ * entries; and the length of the run sort's digit histograms.  One thread.
+ */
+__global__ void k_run_sizes(const int64_t *__restrict__ n_runs, int64_t nnz, int32_t *__restrict__ use_runs,
+                            int64_t *__restrict__ hist_len)
+{
+    const int64_t R = *n_runs;
+    *use_runs = 2 * R <= nnz ? 1 : 0;
+    *hist_len = (int64_t)kRadix * ((R + kSortTile - 1) / kSortTile);
+}
+
 /* Records of every run (row-major run ids from run_ptr): its bucket, row, id
  * (as the value payload of the run sort) and first entry. */
 __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__ indptr,
-                                                     const int32_t *__restrict__ indices, int n_rows,
-                                                     const int64_t *__restrict__ run_ptr,
+                                                     const int32_t *__restrict__ indices, int n_rows, int n_voxels,
+                                                     int n_buckets, const int64_t *__restrict__ run_ptr,
                                                      uint32_t *__restrict__ run_key, int32_t *__restrict__ run_row,
-                                                     float *__restrict__ run_id, uint32_t *__restrict__ run_src)
+                                                     float *__restrict__ run_id, uint32_t *__restrict__ run_src,
+                                                     Gate g)
 {
+    if (gate_closed(g)) return;
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
     const int lane = lane_id();
     const int64_t e0 = indptr[j], e1 = indptr[j + 1];
     uint32_t r = (uint32_t)run_ptr[j];
-    int prev = -1;                                     // column of the entry before the chunk
+    int prev_b = -1;                                   // bucket of the entry before the chunk
     for (int64_t c = e0; c < e1; c += kWave) {
         const int64_t e = c + lane;
         const bool in = e < e1;
         const int col = in ? indices[e] : 0;
-        int cp = __shfl_up(col, 1, kWave);
-        if (lane == 0) cp = prev;
-        const int b = col >> kBucketShift;
-        const bool start = in && (cp < 0 || b != (cp >> kBucketShift));
+        const int b = bucket_key(col, n_voxels, n_buckets);
+        int bp = __shfl_up(b, 1, kWave);
+        if (lane == 0) bp = prev_b;
+        const bool start = in && b != bp;
         const uint64_t m = __ballot(start);
         if (start) {
             const uint32_t id = r + (uint32_t)mbcnt64(m);
@@ -558,35 +639,81 @@ __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__
             run_src[id] = (uint32_t)e;
         }
         r += (uint32_t)__popcll(m);
-        prev = __shfl(col, kWave - 1, kWave);
+        prev_b = __shfl(b, kWave - 1, kWave);
     }
 }
 
-/*
- * The same placement for rows with strictly ascending columns, column by
- * column.  A batch of 64 runs of the bucket (rows ascending; each at most 32
- * entries, one per column) is first copied into LDS, the runs' entries
- * flattened over the lanes so that all loads are independent; then each lane
- * holds one run and, at column c, the lanes whose next entry has column c write
- * it, ranked by lane, so each column's entries from the batch go out as one
- * contiguous stretch.
- */
-constexpr int kColWaves = 2;                               // waves per workgroup of k_bucket_columns
+constexpr int kColWaves = 2;                               // waves per workgroup of k_bucket_place
 
-__global__ __launch_bounds__(kColWaves * kWave) void k_bucket_columns(
-    const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices, const float *__restrict__ values,
-    int n_voxels, int n_buckets, const int64_t *__restrict__ run_ptr, const uint32_t *__restrict__ run_src,
-    const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
-    const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
-    float *__restrict__ t_values)
+/* The runs of bucket b, taken 64 at a time: lane i holds run q0 + i (its row,
+ * first entry and length), with the batch's exclusive prefix of lengths. */
+struct RunBatch {
+    int row;
+    uint32_t src, len, excl, total;
+};
+
+__device__ inline RunBatch load_runs(int64_t qb, int64_t q1, const int64_t *__restrict__ indptr,
+                                     const int64_t *__restrict__ run_ptr, const uint32_t *__restrict__ run_src,
+                                     const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+                                     uint32_t max_len)
+{
+    const int lane = lane_id();
+    const int64_t q = qb + lane;
+    RunBatch B{0, 0u, 0u, 0u, 0u};
+    if (q < q1) {
+        B.row = b_rows[q];
+        const uint32_t id = __float_as_uint(b_ids[q]);
+        B.src = run_src[id];
+        const uint32_t end = (int64_t)id + 1 < run_ptr[B.row + 1] ? run_src[id + 1] : (uint32_t)indptr[B.row + 1];
+        B.len = min(end - B.src, max_len);
+    }
+    uint32_t incl = B.len;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
+    B.excl = incl - B.len;
+    B.total = __shfl(incl, kWave - 1, kWave);
+    return B;
+}
+
+/* Lane of the run holding batch entry p = c0 + lane: the last lane whose
+ * exclusive prefix is <= p, walked wave-uniformly from *rcur. */
+__device__ inline int run_of(const RunBatch &B, uint32_t c0, int &rcur)
+{
+    while (rcur + 1 < kWave && (uint32_t)__builtin_amdgcn_readlane((int)B.excl, rcur + 1) <= c0) ++rcur;
+    const uint32_t p = c0 + lane_id();
+    int rr = rcur;
+    for (int k = rcur + 1; k < kWave; ++k) {
+        const uint32_t ek = (uint32_t)__builtin_amdgcn_readlane((int)B.excl, k);
+        if (ek > c0 + kWave - 1) break;
+        if (p >= ek) rr = k;
+    }
+    return rr;
+}
+
+/*
+ * Placement for rows with strictly ascending columns, column by column.  A
+ * batch of 64 runs of the bucket (rows ascending; each at most 32 entries,
+ * one per column) is first copied into LDS, the runs' entries flattened over
+ * the lanes so that all loads are independent; then each lane holds one run
+ * and, at column c, the lanes whose next entry has column c write it, ranked
+ * by lane, so each column's entries from the batch go out as one contiguous
+ * stretch.
+ */
+__device__ void place_columns(int b, int wave, const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices,
+                              const float *__restrict__ values, int n_voxels, const int64_t *__restrict__ run_ptr,
+                              const uint32_t *__restrict__ run_src, const int64_t *__restrict__ b_ptr,
+                              const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+                              const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
+                              float *__restrict__ t_values)
 {
     constexpr int kStage = kWave * kBucketCols;            // 64 runs of at most 32 entries
     __shared__ uint32_t s_pos[kColWaves][kBucketCols];
     __shared__ float s_val[kColWaves][kStage];
     __shared__ uint8_t s_col[kColWaves][kStage];
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int b = blockIdx.x * kColWaves + wave;
-    if (b >= n_buckets) return;
+    const int lane = lane_id();
     uint32_t *pos = s_pos[wave];                           // next free position of each column's list
     float *sv = s_val[wave];
     uint8_t *sc = s_col[wave];
@@ -597,47 +724,23 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_bucket_columns(
     const int col0 = b << kBucketShift;
     const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1];
     for (int64_t qb = q0; qb < q1; qb += kWave) {
-        // lane i: run qb + i (row, first entry, length)
-        const int64_t q = qb + lane;
-        int row = 0;
-        uint32_t src = 0u, len = 0u;
-        if (q < q1) {
-            row = b_rows[q];
-            const uint32_t id = __float_as_uint(b_ids[q]);
-            src = run_src[id];
-            const uint32_t end = (int64_t)id + 1 < run_ptr[row + 1] ? run_src[id + 1] : (uint32_t)indptr[row + 1];
-            len = min(end - src, (uint32_t)kBucketCols);   // at most 32 for strictly ascending rows
-        }
-        uint32_t incl = len;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += y;
-        }
-        const uint32_t excl = incl - len;
-        const uint32_t total = __shfl(incl, kWave - 1, kWave);   // <= kStage
-        // stage: entry p of the batch (run walked wave-uniformly) -> LDS
+        const RunBatch B = load_runs(qb, q1, indptr, run_ptr, run_src, b_rows, b_ids, kBucketCols);
+        // stage: entry p of the batch -> LDS
         int rcur = 0;
-        for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
-            while (rcur + 1 < kWave && (uint32_t)__builtin_amdgcn_readlane((int)excl, rcur + 1) <= c0) ++rcur;
+        for (uint32_t c0 = 0; c0 < B.total; c0 += kWave) {
             const uint32_t p = c0 + lane;
-            int rr = rcur;
-            for (int k = rcur + 1; k < kWave; ++k) {
-                const uint32_t ek = (uint32_t)__builtin_amdgcn_readlane((int)excl, k);
-                if (ek > c0 + kWave - 1) break;
-                if (p >= ek) rr = k;
-            }
+            const int rr = run_of(B, c0, rcur);
             // shuffles on every lane: the source lane rr may be past the end of the batch's entries
-            const uint32_t e = __shfl(src, rr, kWave) + (p - __shfl(excl, rr, kWave));
-            if (p < total) {
+            const uint32_t e = __shfl(B.src, rr, kWave) + (p - __shfl(B.excl, rr, kWave));
+            if (p < B.total) {
                 sc[p] = (uint8_t)(indices[e] - col0);
                 sv[p] = values[e];
             }
         }
         __builtin_amdgcn_wave_barrier();
         // place: lane = run, its entries sc/sv[excl, excl + len)
-        uint32_t k = excl;
-        const uint32_t end = excl + len;
+        uint32_t k = B.excl;
+        const uint32_t end = B.excl + B.len;
         int ca = k < end ? (int)sc[k] : kBucketCols;
         for (int c = 0; c < kBucketCols; ++c) {
             const bool has = ca == c;
@@ -647,7 +750,7 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_bucket_columns(
             if (has) {
                 const uint32_t p = p0 + (uint32_t)mbcnt64(m);
                 if (p < nnz) {   // always true for consistent runs; keeps every store in bounds
-                    t_indices[p] = row;
+                    t_indices[p] = B.row;
                     t_values[p] = sv[k];
                 }
                 ++k;
@@ -662,29 +765,22 @@ __global__ __launch_bounds__(kColWaves * kWave) void k_bucket_columns(
 }
 
 /*
- * Bucket b's entries into the voxel-row arrays; one wave per bucket.  Its runs
- * (positions b_ptr[b] .. b_ptr[b + 1] of the run sort's output, rows ascending)
- * are taken 64 at a time, their entries flattened over the lanes in run
- * order; an entry of column col goes to t_indptr[col] + (entries of col placed
- * before it), counted per column in LDS.  Equal columns within a 64-entry
- * chunk are ranked by lane with seven ballots over the column's low bits.
+ * Placement for rows in any column order: the bucket's runs are taken 64 at a
+ * time, their entries flattened over the lanes in run order; an entry of
+ * column col goes to t_indptr[col] + (entries of col placed before it),
+ * counted per column in LDS.  Equal columns within a 64-entry chunk are
+ * ranked by lane with five ballots over the column's low bits.
  */
-__global__ __launch_bounds__(kBlock) void k_bucket_scatter(const int64_t *__restrict__ indptr,
-                                                           const int32_t *__restrict__ indices,
-                                                           const float *__restrict__ values, int n_voxels,
-                                                           int n_buckets, const int64_t *__restrict__ run_ptr,
-                                                           const uint32_t *__restrict__ run_src,
-                                                           const int64_t *__restrict__ b_ptr,
-                                                           const int32_t *__restrict__ b_rows,
-                                                           const float *__restrict__ b_ids,
-                                                           const int64_t *__restrict__ t_indptr, uint32_t nnz,
-                                                           int32_t *__restrict__ t_indices, float *__restrict__ t_values)
+__device__ void place_any(int b, int wave, const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices,
+                          const float *__restrict__ values, int n_voxels, const int64_t *__restrict__ run_ptr,
+                          const uint32_t *__restrict__ run_src, const int64_t *__restrict__ b_ptr,
+                          const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+                          const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
+                          float *__restrict__ t_values)
 {
-    __shared__ uint32_t s_base[kWavesPerBlock][kBucketCols];
-    __shared__ uint32_t s_cnt[kWavesPerBlock][kBucketCols];
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int b = blockIdx.x * kWavesPerBlock + wave;
-    if (b >= n_buckets) return;
+    __shared__ uint32_t s_base[kColWaves][kBucketCols];
+    __shared__ uint32_t s_cnt[kColWaves][kBucketCols];
+    const int lane = lane_id();
     uint32_t *base = s_base[wave];
     uint32_t *cnt = s_cnt[wave];
     for (int c = lane; c < kBucketCols; c += kWave) {
@@ -695,39 +791,14 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(const int64_t *__rest
     const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes under this one
     for (int64_t qb = q0; qb < q1; qb += kWave) {
-        // lane i: run qb + i (row, first entry, length)
-        const int64_t q = qb + lane;
-        int row = 0;
-        uint32_t src = 0u, len = 0u;
-        if (q < q1) {
-            row = b_rows[q];
-            const uint32_t id = __float_as_uint(b_ids[q]);
-            src = run_src[id];
-            const uint32_t end = (int64_t)id + 1 < run_ptr[row + 1] ? run_src[id + 1] : (uint32_t)indptr[row + 1];
-            len = end - src;
-        }
-        uint32_t incl = len;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += y;
-        }
-        const uint32_t excl = incl - len;
-        const uint32_t total = __shfl(incl, kWave - 1, kWave);
+        const RunBatch B = load_runs(qb, q1, indptr, run_ptr, run_src, b_rows, b_ids, 0xffffffffu);
         int rcur = 0;
-        for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
-            // run of entry p: the last lane whose exclusive prefix is <= p (walked wave-uniformly)
-            while (rcur + 1 < kWave && (uint32_t)__builtin_amdgcn_readlane((int)excl, rcur + 1) <= c0) ++rcur;
+        for (uint32_t c0 = 0; c0 < B.total; c0 += kWave) {
             const uint32_t p = c0 + lane;
-            int rr = rcur;
-            for (int k = rcur + 1; k < kWave; ++k) {
-                const uint32_t ek = (uint32_t)__builtin_amdgcn_readlane((int)excl, k);
-                if (ek > c0 + kWave - 1) break;
-                if (p >= ek) rr = k;
-            }
-            const bool in = p < total;
-            const uint32_t e = __shfl(src, rr, kWave) + (p - __shfl(excl, rr, kWave));
-            const int rowj = __shfl(row, rr, kWave);
+            const int rr = run_of(B, c0, rcur);
+            const bool in = p < B.total;
+            const uint32_t e = __shfl(B.src, rr, kWave) + (p - __shfl(B.excl, rr, kWave));
+            const int rowj = __shfl(B.row, rr, kWave);
             const int col = in ? indices[e] : 0;
             const float v = in ? values[e] : 0.0f;
             const int bin = col & (kBucketCols - 1);
@@ -752,10 +823,31 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(const int64_t *__rest
     }
 }
 
+/* One wave per bucket of columns (buckets below n_buckets; the sentinel
+ * bucket of invalid columns is not placed). */
+__global__ __launch_bounds__(kColWaves * kWave) void k_bucket_place(
+    const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices, const float *__restrict__ values,
+    int n_voxels, int n_buckets, const int64_t *__restrict__ run_ptr, const uint32_t *__restrict__ run_src,
+    const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+    const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
+    float *__restrict__ t_values, const int32_t *__restrict__ unsorted, Gate g)
+{
+    if (gate_closed(g)) return;
+    const int wave = threadIdx.x >> 6;
+    const int b = blockIdx.x * kColWaves + wave;
+    if (b >= n_buckets) return;
+    if (*unsorted)
+        place_any(b, wave, indptr, indices, values, n_voxels, run_ptr, run_src, b_ptr, b_rows, b_ids, t_indptr, nnz,
+                  t_indices, t_values);
+    else
+        place_columns(b, wave, indptr, indices, values, n_voxels, run_ptr, run_src, b_ptr, b_rows, b_ids, t_indptr,
+                      nnz, t_indices, t_values);
+}
+
 }  // namespace
 
 struct TransposeLayout {
-    size_t key[2], row[2], val[2], hist, offs, partial, counts, bad, run_cnt, run_ptr, total;
+    size_t key[2], row[2], val[2], hist, offs, partial, counts, bcnt, bptr, scal, run_cnt, run_ptr, total;
 };
 
 static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
@@ -769,6 +861,7 @@ static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
     };
     const int64_t n_tiles = (nnz + kSortTile - 1) / kSortTile;
     const int64_t n_hist = (int64_t)kRadix * (n_tiles > 0 ? n_tiles : 1);
+    const int64_t nb = (n_voxels + kBucketCols - 1) >> kBucketShift;
     int64_t n_scan = n_hist > n_voxels ? n_hist : n_voxels;
     if (n_rows > n_scan) n_scan = n_rows;
     const size_t e = (size_t)(nnz > 0 ? nnz : 1);
@@ -781,7 +874,9 @@ static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
     L.offs = take(sizeof(uint32_t) * (size_t)n_hist);
     L.partial = take(sizeof(uint32_t) * (size_t)((n_scan + kScanChunk - 1) / kScanChunk + 1));
     L.counts = take(sizeof(uint32_t) * (size_t)n_voxels);
-    L.bad = take(2 * sizeof(int32_t));   // bad column flag, unsorted-rows flag
+    L.bcnt = take(sizeof(uint32_t) * (size_t)(nb + 1));     // buckets and the sentinel
+    L.bptr = take(sizeof(int64_t) * (size_t)(nb + 2));
+    L.scal = take(64);   // unsorted-rows flag, path flag, run histogram length
     L.run_cnt = take(sizeof(uint32_t) * (size_t)(n_rows > 0 ? n_rows : 1));
     L.run_ptr = take(sizeof(int64_t) * ((size_t)n_rows + 1));
     L.total = off;
@@ -793,30 +888,76 @@ size_t transpose_workspace(int64_t nnz, int n_voxels, int n_rows)
     return transpose_layout(nnz, n_voxels, n_rows).total;
 }
 
-int transpose_passes(int n_voxels)
+int transpose_passes(int n_keys)
 {
     int bits = 0;
-    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n_voxels) ++bits;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n_keys) ++bits;
     const int p = (bits + kRadixBits - 1) / kRadixBits;
     return p > 0 ? p : 1;
 }
 
-/* Exclusive scan of n uint32 values in -> out (OUT = uint32_t or int64_t);
- * partial[nblocks] receives the total, and *total64 too when given. */
-template <typename OUT>
-static hipError_t scan_excl(const uint32_t *in, int64_t n, uint32_t *partial, OUT *out, int64_t *total64,
-                            hipStream_t s)
+/* Persistent grid of a grid-stride launch over `items` units of work. */
+static unsigned stride_grid(int64_t items)
 {
-    const unsigned nb = blocks_of(n, kScanChunk);
-    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, partial);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, partial, (int)nb, total64);
-    if (nb > 0) hipLaunchKernelGGL((k_scan_down<OUT>), dim3(nb), dim3(kBlock), 0, s, in, n, partial, out);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, 4096));
+}
+
+/* Exclusive scan of n uint32 values in -> out (OUT = uint32_t or int64_t); n is a
+ * host count or, with n.dev, a device count at most n_max.  partial[nblocks]
+ * receives the total, and *total64 too when given. */
+template <typename OUT>
+static hipError_t scan_excl(const uint32_t *in, Count n, int64_t n_max, uint32_t *partial, OUT *out,
+                            int64_t *total64, Gate g, hipStream_t s)
+{
+    const unsigned nb = stride_grid((n_max + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, partial, g);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, partial, n, total64, g);
+    hipLaunchKernelGGL((k_scan_down<OUT>), dim3(nb), dim3(kBlock), 0, s, in, n, partial, out, g);
     return hipGetLastError();
+}
+
+/*
+ * One stable LSD radix sort of (key, row, value) triples by key: `passes`
+ * passes of 8 bits, keys above clamp sorted as clamp, ping-pong through
+ * (k1, r1, v1) and (k0, r0, v0) (the input may be separate), the last pass
+ * writing rows and values to (rows_out, vals_out).  n is a host or device
+ * count, at most n_max.
+ */
+static hipError_t radix_sort(const uint32_t *keys, const int32_t *rows, const float *vals, Count n, int64_t n_max,
+                             uint32_t clamp, int passes, uint32_t *k0, int32_t *r0, float *v0, uint32_t *k1,
+                             int32_t *r1, float *v1, int32_t *rows_out, float *vals_out, uint32_t *hist,
+                             uint32_t *offs, uint32_t *partial, int64_t *hist_len_dev, Gate g, hipStream_t s)
+{
+    const int64_t tiles_max = (n_max + kSortTile - 1) / kSortTile;
+    const unsigned grid = stride_grid(tiles_max);
+    const Count hn = hist_len_dev ? Count{0, hist_len_dev} : Count{(int64_t)kRadix * tiles_max, nullptr};
+    const uint32_t *kin = keys;
+    const int32_t *rin = rows;
+    const float *vin = vals;
+    hipError_t e;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * kRadixBits;
+        const bool last = p == passes - 1;
+        uint32_t *kout = last ? nullptr : ((p & 1) ? k0 : k1);
+        int32_t *rout = last ? rows_out : ((p & 1) ? r0 : r1);
+        float *vout = last ? vals_out : ((p & 1) ? v0 : v1);
+        hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(kBlock), 0, s, kin, n, clamp, shift, hist, g);
+        if ((e = scan_excl<uint32_t>(hist, hn, (int64_t)kRadix * tiles_max, partial, offs, nullptr, g, s)) !=
+            hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(kBlock), 0, s, kin, rin, vin, n, clamp, shift, offs, kout,
+                           rout, vout, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        kin = kout;
+        rin = rout;
+        vin = vout;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
                             int n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices, float *t_values,
-                            void *workspace, int32_t *bad_host, hipStream_t s)
+                            void *workspace, hipStream_t s)
 {
     const TransposeLayout L = transpose_layout(nnz, n_voxels, n_rows);
     char *ws = static_cast<char *>(workspace);
@@ -827,121 +968,75 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
     uint32_t *offs = reinterpret_cast<uint32_t *>(ws + L.offs);
     uint32_t *partial = reinterpret_cast<uint32_t *>(ws + L.partial);
     uint32_t *counts = reinterpret_cast<uint32_t *>(ws + L.counts);
-    int32_t *bad = reinterpret_cast<int32_t *>(ws + L.bad);
+    int32_t *unsorted = reinterpret_cast<int32_t *>(ws + L.scal);
+    int32_t *use_runs = unsorted + 1;
+    int64_t *hist_len = reinterpret_cast<int64_t *>(ws + L.scal + 8);
+    const Gate always{nullptr, 0};
     hipError_t e;
 
-    // voxel-row pointers: entries per voxel, exclusive scan, total at t_indptr[n_voxels]
+    // voxel-row pointers: valid entries per voxel, exclusive scan, total at t_indptr[n_voxels]
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of(n_voxels, kBlock)), dim3(kBlock), 0, s, counts, (int64_t)n_voxels);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(bad), (int64_t)1);
-    if (nnz > 0) {
-        const int64_t want = (nnz + kBlock - 1) / kBlock;
-        const unsigned g = (unsigned)(want < 65536 ? want : 65536);
-        hipLaunchKernelGGL(k_col_count, dim3(g), dim3(kBlock), 0, s, indices, nnz, n_voxels, counts, bad);
-    }
-    if ((e = scan_excl<int64_t>(counts, n_voxels, partial, t_indptr, t_indptr + n_voxels, s)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(bad_host, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    if (*bad || nnz == 0) return hipSuccess;
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_key_count, dim3(stride_grid(blocks_of(nnz, kBlock))), dim3(kBlock), 0, s, indices,
+                           Count{nnz, nullptr}, n_voxels, counts, always);
+    if ((e = scan_excl<int64_t>(counts, Count{n_voxels, nullptr}, n_voxels, partial, t_indptr, t_indptr + n_voxels,
+                                always, s)) != hipSuccess)
+        return e;
+    if (nnz == 0 || n_rows == 0) return hipSuccess;
 
-    // runs (stretches of a row within one bucket of columns): the run transpose when they are
-    // at most half the entries (a plan's D has tens of entries per run), else the radix sort
+    // runs (stretches of a row within one bucket of columns) and the path flag
+    const int nb = (n_voxels + kBucketCols - 1) >> kBucketShift;
     uint32_t *run_cnt = reinterpret_cast<uint32_t *>(ws + L.run_cnt);
     int64_t *run_ptr = reinterpret_cast<int64_t *>(ws + L.run_ptr);
-    int32_t *unsorted = bad + 1;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(unsorted), (int64_t)1);
     hipLaunchKernelGGL(k_run_count, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
-                       n_rows, run_cnt, unsorted);
-    if ((e = scan_excl<int64_t>(run_cnt, n_rows, partial, run_ptr, run_ptr + n_rows, s)) != hipSuccess) return e;
-    int64_t n_runs = 0;
-    int32_t rows_unsorted = 0;
-    if ((e = hipMemcpyAsync(&n_runs, run_ptr + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+                       n_rows, n_voxels, nb, run_cnt, unsorted);
+    if ((e = scan_excl<int64_t>(run_cnt, Count{n_rows, nullptr}, n_rows, partial, run_ptr, run_ptr + n_rows, always,
+                                s)) != hipSuccess)
         return e;
-    if ((e = hipMemcpyAsync(&rows_unsorted, unsorted, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    if (2 * n_runs <= nnz) {
-        const int64_t R = n_runs;
-        const int nb = (n_voxels + kBucketCols - 1) >> kBucketShift;
-        // run records in the first half of key[0], row[0], val[0]; first entries and the
-        // sorted runs in their second half; bucket counts and pointers in `counts`
+    hipLaunchKernelGGL(k_run_sizes, dim3(1), dim3(1), 0, s, run_ptr + n_rows, nnz, use_runs, hist_len);
+    const Gate runs{use_runs, 1}, entries{use_runs, 0};
+
+    // run path: at most nnz / 2 runs.  Run records in the first half of key[0], row[0],
+    // val[0]; first entries and the sorted runs from `half` on; the sort's other buffers
+    // are key/row/val[1]
+    {
+        const int64_t half = (nnz + 1) / 2;
         uint32_t *rkey = key[0];
         int32_t *rrow = row[0];
         float *rid = val[0];
-        uint32_t *rsrc = key[0] + R;
-        int32_t *brow = row[0] + R;
-        float *bid = val[0] + R;
-        uint32_t *bcnt = counts;
-        int64_t *bptr = reinterpret_cast<int64_t *>(ws + L.counts + ((sizeof(uint32_t) * (size_t)nb + 7) & ~(size_t)7));
+        uint32_t *rsrc = key[0] + half;
+        int32_t *brow = row[0] + half;
+        float *bid = val[0] + half;
+        uint32_t *bcnt = reinterpret_cast<uint32_t *>(ws + L.bcnt);
+        int64_t *bptr = reinterpret_cast<int64_t *>(ws + L.bptr);
+        const Count n_runs{0, run_ptr + n_rows};
         hipLaunchKernelGGL(k_run_emit, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
-                           n_rows, run_ptr, rkey, rrow, rid, rsrc);
-        hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of(nb, kBlock)), dim3(kBlock), 0, s, bcnt, (int64_t)nb);
-        {
-            const int64_t want = (R + kBlock - 1) / kBlock;
-            const unsigned g = (unsigned)(want < 65536 ? want : 65536);
-            hipLaunchKernelGGL(k_col_count, dim3(g), dim3(kBlock), 0, s, reinterpret_cast<const int32_t *>(rkey), R,
-                               nb, bcnt, bad);
-        }
-        if ((e = scan_excl<int64_t>(bcnt, nb, partial, bptr, bptr + nb, s)) != hipSuccess) return e;
-        // stable sort of the runs by bucket: passes alternate between key/row/val[1] and the
-        // first half of key/row/val[0]; the last one writes rows and ids to brow, bid
-        const int rt = (int)blocks_of(R, kSortTile);
-        const int rpasses = transpose_passes(nb);
-        const uint32_t *kin = rkey;
-        const int32_t *rin = rrow;
-        const float *vin = rid;
-        for (int p = 0; p < rpasses; ++p) {
-            const int shift = p * kRadixBits;
-            const bool last = p == rpasses - 1;
-            const int o = (p & 1) ? 0 : 1;
-            uint32_t *kout = last ? nullptr : key[o];
-            int32_t *rout = last ? brow : row[o];
-            float *vout = last ? bid : val[o];
-            hipLaunchKernelGGL(k_rs_hist, dim3(rt), dim3(kBlock), 0, s, kin, R, shift, hist, rt);
-            if ((e = scan_excl<uint32_t>(hist, (int64_t)kRadix * rt, partial, offs, nullptr, s)) != hipSuccess)
-                return e;
-            hipLaunchKernelGGL(k_rs_scatter, dim3(rt), dim3(kBlock), 0, s, kin, rin, vin, R, shift, offs, rt, kout,
-                               rout, vout);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            kin = kout;
-            rin = rout;
-            vin = vout;
-        }
-        if (rows_unsorted)
-            hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks_of(nb, kWavesPerBlock)), dim3(kBlock), 0, s, indptr,
-                               indices, values, n_voxels, nb, run_ptr, rsrc, bptr, brow, bid, t_indptr, (uint32_t)nnz,
-                               t_indices, t_values);
-        else
-            hipLaunchKernelGGL(k_bucket_columns, dim3(blocks_of(nb, kColWaves)), dim3(kColWaves * kWave), 0, s, indptr,
-                               indices, values, n_voxels, nb, run_ptr, rsrc, bptr, brow, bid, t_indptr, (uint32_t)nnz,
-                               t_indices, t_values);
-        return hipGetLastError();
+                           n_rows, n_voxels, nb, run_ptr, rkey, rrow, rid, rsrc, runs);
+        hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of(nb + 1, kBlock)), dim3(kBlock), 0, s, bcnt, (int64_t)(nb + 1));
+        hipLaunchKernelGGL(k_key_count, dim3(stride_grid(blocks_of(half, kBlock))), dim3(kBlock), 0, s,
+                           reinterpret_cast<const int32_t *>(rkey), n_runs, nb + 1, bcnt, runs);
+        if ((e = scan_excl<int64_t>(bcnt, Count{nb + 1, nullptr}, nb + 1, partial, bptr, bptr + nb + 1, runs, s)) !=
+            hipSuccess)
+            return e;
+        // stable sort of the runs by bucket (the sentinel bucket last)
+        if ((e = radix_sort(rkey, rrow, rid, n_runs, half, (uint32_t)nb, transpose_passes(nb + 1), key[0], row[0],
+                            val[0], key[1], row[1], val[1], brow, bid, hist, offs, partial, hist_len, runs, s)) !=
+            hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_bucket_place, dim3(blocks_of(nb, kColWaves)), dim3(kColWaves * kWave), 0, s, indptr,
+                           indices, values, n_voxels, nb, run_ptr, rsrc, bptr, brow, bid, t_indptr, (uint32_t)nnz,
+                           t_indices, t_values, unsorted, runs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
 
-    // row id of every entry (into row[1], free until the second pass writes it)
+    // entry path: row id of every entry (into row[0]), then a radix sort of the entries by
+    // column (invalid columns as n_voxels, sorted last)
     hipLaunchKernelGGL(k_expand_rows, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, n_rows, nnz,
-                       row[1]);
-    const int n_tiles = (int)blocks_of(nnz, kSortTile);
-    const int passes = transpose_passes(n_voxels);
-    const uint32_t *kin = reinterpret_cast<const uint32_t *>(indices);
-    const int32_t *rin = row[1];
-    const float *vin = values;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = p * kRadixBits;
-        const bool last = p == passes - 1;
-        uint32_t *kout = last ? nullptr : key[p & 1];
-        int32_t *rout = last ? t_indices : row[p & 1];
-        float *vout = last ? t_values : val[p & 1];
-        hipLaunchKernelGGL(k_rs_hist, dim3(n_tiles), dim3(kBlock), 0, s, kin, nnz, shift, hist, n_tiles);
-        if ((e = scan_excl<uint32_t>(hist, (int64_t)kRadix * n_tiles, partial, offs, nullptr, s)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_rs_scatter, dim3(n_tiles), dim3(kBlock), 0, s, kin, rin, vin, nnz, shift, offs, n_tiles,
-                           kout, rout, vout);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        kin = kout;
-        rin = rout;
-        vin = vout;
-    }
-    return hipSuccess;
+                       row[0], entries);
+    return radix_sort(reinterpret_cast<const uint32_t *>(indices), row[0], values, Count{nnz, nullptr}, nnz,
+                      (uint32_t)n_voxels, transpose_passes(n_voxels + 1), key[0], row[0], val[0], key[1], row[1],
+                      val[1], t_indices, t_values, hist, offs, partial, nullptr, entries, s);
 }
 
 }  // namespace fspb

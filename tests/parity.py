@@ -69,3 +69,107 @@ def gpu_rows_from_csr(csr, rows):
         a, b = int(indptr[j]), int(indptr[j + 1])
         out.append((csr.indices[a:b].cpu().numpy(), csr.values[a:b].cpu().numpy()))
     return out
+
+
+def _gpu_entries(csr, ind, sel):
+    """Column and value arrays of the CSR rows `sel` (ascending), copied in one gather."""
+    import torch
+    a, b = ind[sel], ind[sel + 1]
+    if len(sel) and np.all(a[1:] == b[:-1]):                  # consecutive rows: one slice
+        lo, hi = int(a[0]), int(b[-1])
+        return csr.indices[lo:hi].cpu().numpy(), csr.values[lo:hi].cpu().numpy()
+    pos = np.concatenate([np.arange(x, y, dtype=np.int64) for x, y in zip(a, b)] + [np.zeros(0, np.int64)])
+    p = torch.from_numpy(pos).to(csr.values.device)
+    return csr.indices[p].cpu().numpy(), csr.values[p].cpu().numpy()
+
+
+def compare_plan(ora, csr, rows=None, chunk=64, values=None):
+    """Every row in ``rows`` (default: all rows of the plan) against the oracle,
+    ``chunk`` rows at a time, with the acceptance of ``compare_rows``.
+
+    The 1 % floor is taken as 0.99 % of the GPU's largest entry, which is at
+    most 1 % of the oracle's largest entry once the two maxima agree to 1e-4
+    (asserted at the end): the gated set includes every entry the bar names.
+    Rows whose columns match the oracle's exactly are compared vectorised;
+    the others go through ``compare_rows`` (cutoff-band check per voxel).
+    ``values`` (optional) replaces the CSR's values, e.g. a surrogate fill's.
+    """
+    import torch
+    ind = csr.indptr.cpu().numpy()
+    vals = csr.values if values is None else values
+    gmax = float(vals.max().item()) if vals.numel() else 0.0
+    thr = 0.99 * FLOOR * gmax
+    rows = np.arange(ora.n_beamlets) if rows is None else np.sort(np.asarray(rows))
+    worst, abs_sum, n_common, band, omax = 0.0, 0.0, 0, 0, 0.0
+    sq_sum = 0.0
+    for k in range(0, len(rows), chunk):
+        sel = rows[k:k + chunk].astype(np.int64)
+        off, oidx, oval = ora.rows(sel)
+        if len(oval):
+            omax = max(omax, float(oval.max()))
+        gi, gv = _gpu_entries(csr if values is None else type(csr)(csr.indptr, csr.indices, vals, csr.n_voxels),
+                              ind, sel)
+        gcnt = ind[sel + 1] - ind[sel]
+        gstart = np.concatenate([[0], np.cumsum(gcnt)])
+        # columns strictly ascending inside every GPU row
+        d = np.diff(gi.astype(np.int64))
+        inner = np.ones(len(d), dtype=bool)
+        inner[gstart[1:-1][gstart[1:-1] > 0] - 1] = False
+        assert np.all(d[inner] > 0), f"rows {sel[0]}..{sel[-1]}: GPU columns not strictly ascending"
+        same_cnt = gcnt == np.diff(off)
+        if np.all(same_cnt) and np.array_equal(gi, oidx):
+            o, g = oval, gv.astype(np.float64)
+            diff = np.abs(g - o)
+            abs_sum += float(diff.sum())
+            sq_sum += float((diff ** 2).sum())
+            n_common += len(o)
+            big = o > thr
+            if big.any():
+                rel = diff[big] / o[big]
+                q = int(np.argmax(rel))
+                worst = max(worst, float(rel[q]))
+                assert rel[q] <= REL_TOL, (f"rows {sel[0]}..{sel[-1]}: voxel {oidx[big][q]} relative error "
+                                           f"{rel[q]:.3e} (gpu {g[big][q]:.9g}, oracle {o[big][q]:.9g})")
+            continue
+        # pattern differs somewhere in the chunk: row by row with the band check
+        grows = [(gi[gstart[r]:gstart[r + 1]], gv[gstart[r]:gstart[r + 1]]) for r in range(len(sel))]
+        orows = [(oidx[off[r]:off[r + 1]], oval[off[r]:off[r + 1]]) for r in range(len(sel))]
+        res = compare_rows(ora, sel.tolist(), grows, orows, vmax=thr / FLOOR)
+        worst = max(worst, res["max_rel"])
+        abs_sum += res["eps"] * res["n"]
+        n_common += res["n"]
+        band += res["band_mismatches"]
+        for (a, av), (b, bv) in zip(grows, orows):
+            _, ia, ib = np.intersect1d(a, b, assume_unique=True, return_indices=True)
+            sq_sum += float(((av[ia].astype(np.float64) - bv[ib]) ** 2).sum())
+    if rows is None or len(rows) == ora.n_beamlets:
+        assert abs(gmax - omax) <= REL_TOL * omax, f"largest entry: gpu {gmax:.9g}, oracle {omax:.9g}"
+    return {"max_rel": worst, "eps": abs_sum / max(n_common, 1), "n": n_common, "rows": len(rows),
+            "band_mismatches": band, "vmax": omax, "rms": (sq_sum / max(n_common, 1)) ** 0.5}
+
+
+def coefficient_errors(ora, csr, chunk=64):
+    """Absolute coefficient errors against the oracle over every row, for an
+    approximate fill (the surrogate): max |dD| and the RMS of dD over entries
+    above 1 % of the maximum, both relative to the oracle's largest entry.
+    Columns must match the oracle's except in the cutoff band."""
+    ind = csr.indptr.cpu().numpy()
+    rows = np.arange(ora.n_beamlets)
+    worst, omax, parts = 0.0, 0.0, []
+    for k in range(0, len(rows), chunk):
+        sel = rows[k:k + chunk]
+        off, oidx, oval = ora.rows(sel)
+        gi, gv = _gpu_entries(csr, ind, sel)
+        if len(oval):
+            omax = max(omax, float(oval.max()))
+        if np.array_equal(ind[sel + 1] - ind[sel], np.diff(off)) and np.array_equal(gi, oidx):
+            o, d = oval, np.abs(gv.astype(np.float64) - oval)
+        else:
+            common, ga, oa = np.intersect1d(gi, oidx, return_indices=True)
+            assert len(common) >= len(oidx) - 64 * len(sel), "surrogate fill changed the VOI pattern"
+            o, d = oval[oa], np.abs(gv[ga].astype(np.float64) - oval[oa])
+        if len(d):
+            worst = max(worst, float(d.max()))
+            parts.append((o, d))
+    big = np.concatenate([d[o > FLOOR * omax] for o, d in parts]) if parts else np.zeros(1)
+    return {"max": worst / omax, "rms": float(np.sqrt(np.mean(big ** 2))) / omax, "vmax": omax}

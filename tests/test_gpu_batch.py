@@ -7,7 +7,9 @@
   results each time;
 * every launch shape (waves per group, groups per CU, queue order) and the
   tuner's choice give identical results;
-* sampled rows agree with the FP64 oracle;
+* rows agree with the FP64 oracle (all rows of the small batch, at least 10 %
+  of every plan's rows at full size);
+* plans with a surrogate attached are refused, and a batched plan refuses one;
 * a density change that adds nonzeros after sizing is reported as OVERFLOW.
 """
 import os
@@ -19,7 +21,7 @@ import pytest
 import fspb_inputs as fi
 
 sys.path.insert(0, os.path.dirname(__file__))
-from parity import compare_rows, gpu_rows_from_csr  # noqa: E402
+from parity import compare_plan  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -88,17 +90,17 @@ def test_small_batch_equals_single_plans(torch_gpu, oracle_lib):
     torch.cuda.synchronize()
     for k, o in enumerate(batch.outputs()):
         assert torch.equal(o.values, outs[k][2])
-    # oracle on sampled rows of every plan
+    # every row of every plan against the oracle
     for k, prob in enumerate(probs):
         ora = oracle_lib.OraclePlan(prob)
-        rng = np.random.default_rng(k)
-        rows = sorted(rng.choice(ora.n_beamlets, min(6, ora.n_beamlets), replace=False).tolist())
-        r = compare_rows(ora, rows, gpu_rows_from_csr(batch.outputs()[k], rows))
-        _say(f"  plan {k}: nnz={batch.nnz[k]} sampled max_rel={r['max_rel']:.2e} band={r['band_mismatches']}")
+        r = compare_plan(ora, batch.outputs()[k])
+        _say(f"  plan {k}: nnz={batch.nnz[k]} rows={r['rows']} max_rel={r['max_rel']:.2e} "
+             f"band={r['band_mismatches']}")
 
 
 def test_full_size_batch_sampled(torch_gpu, oracle_lib):
-    """32 plans of uneven size at full size, one graph launch; 3 sampled rows per plan."""
+    """32 plans of uneven size at full size, one graph launch; a seeded 10 % of
+    every plan's rows (at least 8) against the oracle."""
     import torch
     from paper_0908_4417_amd import Plan, Batch
     probs = fi.batched_configs(n_plans=32)
@@ -110,14 +112,19 @@ def test_full_size_batch_sampled(torch_gpu, oracle_lib):
     batch.run()
     torch.cuda.synchronize()
     assert batch.check() == 0
-    worst = 0.0
+    worst, rows_done, n_done, band = 0.0, 0, 0, 0
     for k, prob in enumerate(probs):
         ora = oracle_lib.OraclePlan(prob)
         rng = np.random.default_rng(1000 + k)
-        rows = sorted(rng.choice(ora.n_beamlets, 3, replace=False).tolist())
-        r = compare_rows(ora, rows, gpu_rows_from_csr(batch.outputs()[k], rows))
+        n_pick = min(ora.n_beamlets, max(8, -(-ora.n_beamlets // 10)))
+        rows = np.sort(rng.choice(ora.n_beamlets, n_pick, replace=False))
+        r = compare_plan(ora, batch.outputs()[k], rows=rows)
+        assert r["rows"] * 10 >= ora.n_beamlets
         worst = max(worst, r["max_rel"])
-    _say(f"  worst sampled max_rel over 32 plans: {worst:.2e}")
+        rows_done += r["rows"]
+        n_done += r["n"]
+        band += r["band_mismatches"]
+    _say(f"  {rows_done} rows, {n_done} entries compared: worst max_rel {worst:.2e}, band {band}")
     # two plans checked bit for bit against their single-plan runs
     for k in (0, 31):
         _, c = _single(probs[k])
@@ -146,3 +153,26 @@ def test_batch_overflow_is_reported(torch_gpu):
     # entries up to the capacity are intact, the indptr reports the new count
     assert int(batch.indptr[1][-1]) > n0
     assert batch.check() == 0                          # flags were cleared
+
+
+def test_batch_and_surrogate_exclude_each_other(torch_gpu):
+    """A batch computes Eq. 2-3 analytically: a plan with a surrogate attached is
+    refused at creation, and a plan held by a live batch refuses a surrogate."""
+    import paper_0908_4417_amd as m
+    from paper_0908_4417_amd import Plan, Batch, Surrogate
+    prob = fi.Problem("bs", fi.water_phantom((20, 20, 16), (0.5, 0.5, 0.5)),
+                      fi.coplanar_beams(1, (0.1, 0.0, 0.05), 100.0, 0.5, 0.5, 2, 2), fi.default_kernel(3))
+    sur = Surrogate(prob.kernel, fi.surrogate_init(3), max_batch=1024)
+    a, b = Plan(prob, "cuda:0"), Plan(prob, "cuda:0")
+    a.set_surrogate(sur)
+    with pytest.raises(m.FspbError, match="surrogate attached"):
+        Batch([b, a])
+    batch = Batch([b])
+    with pytest.raises(m.FspbError, match="batch"):
+        b.set_surrogate(sur)
+    del batch                                         # the plan leaves its only batch
+    import gc
+    gc.collect()
+    b.set_surrogate(sur)
+    a.set_surrogate(None)
+    Batch([a])

@@ -1,13 +1,20 @@
 """D computed in row ranges (the paper's beam-at-a-time mode for small cards).
 
 * the pieces of ``Plan.chunks`` put together equal the one-shot CSR bit for bit,
-  for whole-beam and beamlet-level budgets;
+  for whole-beam and beamlet-level budgets, and every piece's rows match the
+  FP64 oracle (also on the full-size 128^3 slab under a one-beam budget);
 * state and argument errors of fspb_dose_coeffs_rows.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import fspb_inputs as fi
+
+sys.path.insert(0, os.path.dirname(__file__))
+from parity import compare_plan  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -26,18 +33,30 @@ def _problem():
                       fi.default_kernel(61))
 
 
+def _piece_against_oracle(ora, plan, j0, j1, c):
+    """Rows j0..j1-1 of a piece (row pointers from 0) against the oracle's rows."""
+    from paper_0908_4417_amd import CSR
+    ip = plan.torch.zeros(plan.n_beamlets + 1, dtype=plan.torch.int64, device=plan.device)
+    ip[j0:j1 + 1] = c.indptr
+    ip[j1 + 1:] = c.indptr[-1]
+    return compare_plan(ora, CSR(ip, c.indices, c.values, plan.n_voxels), rows=np.arange(j0, j1))
+
+
 @pytest.mark.parametrize("frac,by_beam", [(0.45, True), (0.1, True), (0.07, False)])
-def test_chunks_equal_one_shot(torch_gpu, frac, by_beam):
+def test_chunks_equal_one_shot(torch_gpu, oracle_lib, frac, by_beam):
     torch = torch_gpu
     from paper_0908_4417_amd import Plan
     plan = Plan(_problem(), "cuda:0")
     full = plan.compute()
     ip, ix, vv = full.indptr.clone(), full.indices.clone(), full.values.clone()
     budget = int(8 * full.nnz * frac)
+    ora = oracle_lib.OraclePlan(_problem())
     got_i, got_v, ranges = [], [], []
     for j0, j1, c in plan.chunks(budget, by_beam=by_beam):
         assert 8 * c.nnz <= budget
         torch.testing.assert_close(c.indptr, ip[j0:j1 + 1] - ip[j0], rtol=0, atol=0)
+        r = _piece_against_oracle(ora, plan, j0, j1, c)
+        assert r["rows"] == j1 - j0
         got_i.append(c.indices.clone())
         got_v.append(c.values.clone())
         ranges.append((j0, j1))
@@ -68,3 +87,22 @@ def test_rows_errors(torch_gpu):
     plan.raytrace()                                          # a new trace invalidates the counts
     with pytest.raises(m.FspbError, match="count"):
         plan.compute_rows(0, 1)
+
+
+def test_full_size_slab_by_beam_against_oracle(torch_gpu, oracle_lib):
+    """The 128^3 slab (9 beams) under a one-beam budget: ten pieces, every row of
+    every piece against the oracle."""
+    from paper_0908_4417_amd import Plan
+    prob = fi.make_config(1)
+    plan = Plan(prob, "cuda:0")
+    nnz = plan.count()
+    budget = int(8 * nnz / len(prob.beams) * 1.05)
+    ora = oracle_lib.OraclePlan(prob)
+    worst, rows, pieces = 0.0, 0, 0
+    for j0, j1, c in plan.chunks(budget):
+        r = _piece_against_oracle(ora, plan, j0, j1, c)
+        worst = max(worst, r["max_rel"])
+        rows += r["rows"]
+        pieces += 1
+    assert rows == plan.n_beamlets and pieces >= len(prob.beams)
+    print(f"\n  {pieces} pieces of at most {budget} B, {rows} rows: max_rel {worst:.2e}", flush=True)

@@ -1,8 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Small problems are compared in full; the full-size workloads (128^3 slab,
-256 x 256 x 100 pelvis) are run at their real size and compared on a seeded
-sample of beamlet rows, each of which the oracle computes on its own.
+Small problems are compared in full.  The full-size workloads (128^3 slab,
+256 x 256 x 100 pelvis) are run at their real size and compared on every
+beamlet row (the oracle computes them 64 at a time on the host cores), with
+a quick 24-row sample beside it.
 """
 import os
 import sys
@@ -13,7 +14,7 @@ import pytest
 import fspb_inputs as fi
 
 sys.path.insert(0, os.path.dirname(__file__))
-from parity import compare_rows, gpu_rows_from_csr  # noqa: E402
+from parity import compare_plan, compare_rows, gpu_rows_from_csr  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -97,10 +98,14 @@ def test_heterogeneous_full_parity(torch_gpu, oracle_lib, seed, n, gantries, sad
 
 @pytest.mark.parametrize("pdd_step", [0.1, 0.02])
 def test_erf_table_forms(torch_gpu, oracle_lib, pdd_step):
-    """The fill stages erf mirrored onto [-4, 4] (16 KB) unless that costs it a
-    workgroup per CU; a depth dose of 3001 nodes (24 KB of LDS) makes the
-    mirrored form too large, so the 8 KB symmetric table is taken.  Both forms
-    must match the oracle."""
+    """The fill's two erf table forms, forced on the same plan (FSPB_ERF_COMPACT,
+    FSPB_ERF_MIRRORED), each against the oracle, and the two fills equal to
+    the rounding of the table forms.  Plan creation's own choice (the mirrored
+    form unless its LDS costs the fill workgroups per CU on this device) is
+    reported, not asserted: it depends on the compiler's register count.  A
+    depth dose of 3001 nodes (24 KB of LDS) is the case where the heuristic
+    usually keeps the 8 KB table."""
+    from paper_0908_4417_amd import Plan
     g = fi.slab_phantom(44, n=(37, 29, 23), spacing=(0.45, 0.5, 0.55), lung_side=(2, 8), bone_side=(1, 3))
     beams = []
     for gd in (17.0, 95.0, 181.0):
@@ -111,14 +116,25 @@ def test_erf_table_forms(torch_gpu, oracle_lib, pdd_step):
         x = np.arange(int(round((len(k.pdd) - 1) * k.pdd_step / pdd_step)) + 1) * pdd_step
         k.pdd = np.interp(x, np.arange(len(k.pdd)) * k.pdd_step, k.pdd).astype(np.float32)
         k.pdd_step = pdd_step
-    _say(f"parity: erf table form, {len(k.pdd)} depth-dose nodes")
-    plan, csr, ora, r = _full_compare(oracle_lib, fi.Problem("erf_form", g, beams, k))
-    # LDS of the symmetric form is 8 KB of erf + 8 B per depth / dose node + the tile offsets
-    pairs = 8 * (plan.desc.max_table + len(k.pdd))
-    mirrored = plan.desc.fill_lds_bytes >= 16384 + pairs
-    assert mirrored == (len(k.pdd) < 1000), f"fill LDS {plan.desc.fill_lds_bytes} B for {pairs} B of tables"
-    _say(f"  mirrored={mirrored} lds={plan.desc.fill_lds_bytes} nnz={csr.nnz} max_rel={r['max_rel']:.2e} "
-         f"band={r['band_mismatches']}")
+    prob = fi.Problem("erf_form", g, beams, k)
+    ora = oracle_lib.OraclePlan(prob)
+    vals = {}
+    for form in ("compact", "mirrored"):
+        plan = Plan(prob, "cuda:0", erf_form=form)
+        pairs = 8 * (plan.desc.max_table + len(k.pdd))     # depth table and depth dose in LDS
+        csr = plan.compute()
+        r = compare_plan(ora, csr)
+        lds = plan.desc.fill_lds_bytes
+        assert (lds >= 16384 + pairs) == (form == "mirrored"), (form, lds, pairs)
+        vals[form] = (csr.indices.clone(), csr.values.double().clone())
+        _say(f"  {form}: lds={lds} nnz={csr.nnz} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e} "
+             f"band={r['band_mismatches']}")
+    (ia, va), (ib, vb) = vals["compact"], vals["mirrored"]
+    assert bool((ia == ib).all())
+    assert float(((va - vb).abs() / va.abs().max()).max()) <= 1e-6
+    auto = Plan(prob, "cuda:0")
+    _say(f"  {len(k.pdd)} depth-dose nodes: plan creation chose the "
+         f"{'mirrored' if auto.desc.fill_lds_bytes >= 16384 + pairs else 'compact'} form")
 
 
 def test_water_axes_on_voxel_faces(torch_gpu, oracle_lib):
@@ -156,6 +172,23 @@ def test_full_size_workloads_sampled(torch_gpu, oracle_lib, k):
     _say(f"  nnz={csr.nnz} sampled={r['n']} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e} "
          f"band={r['band_mismatches']}")
     assert csr.nnz > 1e8
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_full_size_workloads_all_rows(torch_gpu, oracle_lib, k):
+    """Every row of the 128^3 slab (8100 rows) and of the 256 x 256 x 100 pelvis
+    (5184 rows) against the oracle: the 1e-4 bar on entries above 1 % of the
+    maximum, the pattern outside the cutoff band, and the paper's eps (Sec. 3.1)."""
+    import time
+    prob = fi.make_config(k)
+    _say(f"parity: {prob.name} full size, all rows")
+    plan, csr = _run(prob)
+    ora = oracle_lib.OraclePlan(prob)
+    t0 = time.time()
+    r = compare_plan(ora, csr)
+    assert r["rows"] == plan.n_beamlets and r["n"] >= csr.nnz - r["band_mismatches"]
+    _say(f"  rows={r['rows']} nnz={csr.nnz} compared={r['n']} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e} "
+         f"rms={r['rms']:.2e} band={r['band_mismatches']} vmax={r['vmax']:.6g} ({time.time() - t0:.1f} s)")
 
 
 def test_more_than_2_31_nonzeros(torch_gpu, oracle_lib):

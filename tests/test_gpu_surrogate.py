@@ -6,10 +6,16 @@
 * gradient of the mean squared error: GPU backward vs the oracle's backprop with the
   same BF16 rounding (relative L2 error <= 1e-3), on a batch that is not a multiple of 64.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import fspb_inputs as fi
+
+sys.path.insert(0, os.path.dirname(__file__))
+from parity import coefficient_errors, compare_plan  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -106,10 +112,11 @@ def test_training_is_deterministic(torch_gpu):
     assert outs[0][3] < 0.5 * outs[0][2], (outs[0][2], outs[0][3])
 
 
-def test_fallback_outside_the_training_box(torch_gpu):
+def test_fallback_outside_the_training_box(torch_gpu, oracle_lib):
     """Beamlets narrower than the box (a = 0.2) never use the network: the analytic
-    kernel's pattern and values.  The surrogate fill keeps the 8 KB erf table while the
-    plain fill of a plan this small stages the mirrored one, so values agree to the
+    kernel's pattern and values, judged against the FP64 oracle at the 1e-4 bar on
+    every row.  The surrogate fill keeps the 8 KB erf table while the plain fill of
+    a plan this small stages the mirrored one, so the two fills agree to the
     rounding of the two table forms (the network's own error is 1e-3 of the maximum)."""
     torch = torch_gpu
     from paper_0908_4417_amd import Plan
@@ -123,6 +130,8 @@ def test_fallback_outside_the_training_box(torch_gpu):
     plan.set_surrogate(sur)
     b = plan.compute()
     assert torch.equal(ai, b.indices)
+    r = compare_plan(oracle_lib.OraclePlan(prob), b)
+    print(f"\n  fallback fill vs oracle: rows={r['rows']} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e}", flush=True)
     av, bv = av.double().cpu().numpy(), b.values.double().cpu().numpy()
     np.testing.assert_allclose(bv, av, rtol=1e-5, atol=1e-7 * av.max())
     # a plan with other kernel parameters is refused
@@ -170,6 +179,9 @@ def test_trained_surrogate_dose_on_pelvis(torch_gpu, oracle_lib):
     t_surrogate = m.fspb_plan_get_timing(plan.handle).fill_ms
     dose = csr.dose(torch.ones(plan.n_beamlets, dtype=torch.float32, device="cuda:0"))
     dose = dose.cpu().numpy().astype(np.float64)
+    ce = coefficient_errors(ora, csr)
+    print(f"  coefficients vs oracle: max error {ce['max'] * 100:.3f} %, RMS {ce['rms'] * 100:.4f} % of max D "
+          f"(entries above 1 % of it)", flush=True)
     del csr
     dref = ora.fluence_dose(np.ones(ora.n_beamlets))
     dmax = dref.max()
@@ -185,3 +197,6 @@ def test_trained_surrogate_dose_on_pelvis(torch_gpu, oracle_lib):
     assert k_err <= 5e-3
     assert max_err <= 5e-3
     assert rms <= 1e-3
+    # the target is on the dose (Eq. 1); single coefficients carry the network's error
+    # near the beamlet edges unaveraged: a regression bound, not the target
+    assert ce["max"] <= 2e-2 and ce["rms"] <= 2e-3
