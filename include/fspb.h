@@ -516,6 +516,25 @@ fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, co
                                void *stream);
 
 /*
+ * fspb_csr_transpose for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument, and no allocation of any kind.  Its
+ * scratch is a static device array of FSPB_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * in the library, one per GPU, kept until the process ends.  Same arguments
+ * (minus the workspace), kernels and results as fspb_csr_transpose.
+ * Returns FSPB_ERR_CAPACITY (before any device work) when the transpose of
+ * these sizes needs more scratch than that: about 24 bytes per entry plus 4
+ * per voxel and 12 per row, i.e. up to roughly 2.5 million entries.  Every
+ * call on a GPU shares that GPU's array and leaves its contents behind: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.
+ */
+#define FSPB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fspb_status fspb_csr_transpose_noalloc(const int64_t *indptr, const int32_t *indices, const float *values,
+                                       int32_t n_rows, int32_t n_voxels, int64_t nnz, int64_t *t_indptr,
+                                       int32_t *t_indices, float *t_values, void *stream);
+
+/*
  * dose[i] = sum_j D_ij w[j] over the voxel-row CSR of fspb_csr_transpose:
  * each voxel row is summed by 16 lanes in a fixed order (bit-reproducible, no
  * atomics).  DEVICE pointers; w has n_beamlets entries, dose n_voxels and is

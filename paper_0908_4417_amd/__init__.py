@@ -32,7 +32,7 @@ from ._lib import (FspbBatchConfig, fspb_batch_create, fspb_batch_nnz, fspb_batc
                    fspb_surrogate_train, fspb_surrogate_get_params, fspb_surrogate_set_params,
                    fspb_plan_set_surrogate, fspb_surrogate_destroy, fspb_fluence_dose,
                    fspb_fluence_gradient, fspb_csr_transpose, fspb_voxel_dose, fspb_dose_coeffs_rows,
-                   fspb_row_ranges)
+                   fspb_row_ranges, fspb_csr_transpose_noalloc, NOALLOC_SCRATCH_BYTES)
 
 __all__ = [
     "Plan", "CSR", "VoxelCSR", "Batch", "Surrogate", "FspbError", "FspbBatchConfig", "FspbTrainConfig",
@@ -40,7 +40,7 @@ __all__ = [
     "fspb_surrogate_gradient", "fspb_surrogate_train", "fspb_surrogate_get_params",
     "fspb_surrogate_set_params", "fspb_plan_set_surrogate", "fspb_surrogate_destroy",
     "fspb_fluence_dose", "fspb_fluence_gradient", "fspb_csr_transpose", "fspb_voxel_dose",
-    "fspb_dose_coeffs_rows", "fspb_row_ranges",
+    "fspb_dose_coeffs_rows", "fspb_row_ranges", "fspb_csr_transpose_noalloc", "NOALLOC_SCRATCH_BYTES",
     "fspb_batch_create", "fspb_batch_nnz", "fspb_batch_bind", "fspb_batch_tune", "fspb_batch_get_config",
     "fspb_batch_set_config", "fspb_batch_run", "fspb_batch_check", "fspb_batch_destroy", "lib", "library_path", "EXPORTED",
     "fspb_plan_create", "fspb_raytrace", "fspb_dose_coeffs", "fspb_plan_destroy",

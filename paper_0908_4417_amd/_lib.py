@@ -135,6 +135,8 @@ _SIGS = {
     "fspb_csr_transpose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int64,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                        C.POINTER(C.c_size_t), C.c_void_p]),
+    "fspb_csr_transpose_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                               C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fspb_voxel_dose": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
     "fspb_status_string": (C.c_char_p, [C.c_int32]),
@@ -386,6 +388,19 @@ def fspb_csr_transpose(indptr, indices, values, n_rows, n_voxels, nnz, t_indptr,
     if st == FSPB_ERR_CAPACITY and not workspace:
         return st, need.value
     return _check(st), need.value
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def fspb_csr_transpose_noalloc(indptr, indices, values, n_rows, n_voxels, nnz, t_indptr, t_indices, t_values, stream):
+    """The transpose into the library's static device scratch (no allocation).  Returns the
+    status: CAPACITY (the sizes need more scratch) is returned, not raised."""
+    st = lib().fspb_csr_transpose_noalloc(indptr, indices, values, n_rows, n_voxels, nnz, t_indptr, t_indices,
+                                          t_values, stream)
+    if st == FSPB_ERR_CAPACITY:
+        return st
+    return _check(st)
 
 
 def fspb_voxel_dose(t_indptr, t_indices, t_values, n_voxels, n_beamlets, w, dose, stream):

@@ -137,6 +137,10 @@ int transpose_passes(int n_keys);
 hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const float *values, int n_rows,
                             int n_voxels, int64_t nnz, int64_t *t_indptr, int32_t *t_indices, float *t_values,
                             void *workspace, hipStream_t s);
+/* Size of the static device scratch of the allocation-free transpose, and its
+ * device address on the current device (looked up once per device). */
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+hipError_t noalloc_scratch_ptr(void **out);
 
 /* Batched launches over n_plans plans (persistent grids). */
 hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64_t *start, int n_plans,

@@ -1712,6 +1712,28 @@ fspb_status fspb_csr_transpose(const int64_t *indptr, const int32_t *indices, co
     return FSPB_OK;
 }
 
+fspb_status fspb_csr_transpose_noalloc(const int64_t *indptr, const int32_t *indices, const float *values,
+                                       int32_t n_rows, int32_t n_voxels, int64_t nnz, int64_t *t_indptr,
+                                       int32_t *t_indices, float *t_values, void *stream)
+{
+    g_last_error.clear();
+    if (n_rows < 0 || n_voxels < 1 || nnz < 0) return fail(FSPB_ERR_INVALID, "n_rows, n_voxels or nnz out of range");
+    if (nnz >= ((int64_t)1 << 32) - 1) return fail(FSPB_ERR_INVALID, "nnz must be below 2^32");
+    const size_t need = fspb::transpose_workspace(nnz, n_voxels, n_rows);
+    if (need > fspb::kNoAllocScratchBytes)
+        return fail(FSPB_ERR_CAPACITY, "transpose needs %zu bytes of scratch; the static scratch holds %zu", need,
+                    fspb::kNoAllocScratchBytes);
+    if (!indptr || !t_indptr) return fail(FSPB_ERR_INVALID, "indptr or t_indptr is NULL");
+    if (nnz > 0 && (!indices || !values || !t_indices || !t_values))
+        return fail(FSPB_ERR_INVALID, "entry arrays are NULL");
+    void *ws = nullptr;
+    FSPB_HIP(fspb::noalloc_scratch_ptr(&ws), "address of the static scratch");
+    FSPB_HIP(fspb::launch_transpose(indptr, indices, values, n_rows, n_voxels, nnz, t_indptr, t_indices, t_values, ws,
+                                    static_cast<hipStream_t>(stream)),
+             "launch transpose");
+    return FSPB_OK;
+}
+
 fspb_status fspb_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, const float *t_values,
                             int32_t n_voxels, int32_t n_beamlets, const float *w, float *dose, void *stream)
 {

@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "fspb_device.h"
 
@@ -1037,6 +1038,38 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
     return radix_sort(reinterpret_cast<const uint32_t *>(indices), row[0], values, Count{nnz, nullptr}, nnz,
                       (uint32_t)n_voxels, transpose_passes(n_voxels + 1), key[0], row[0], val[0], key[1], row[1],
                       val[1], t_indices, t_values, hist, offs, partial, nullptr, entries, s);
+}
+
+/*
+ * Scratch of the allocation-free transpose: a file-scope device array, one
+ * copy per GPU, held until the process ends.  Host code never passes the
+ * array's name to a kernel (on the host it is only a stand-in for the
+ * symbol): its device address is taken once per device with
+ * hipGetSymbolAddress and kept in noalloc_scratch_ptr.
+ */
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_ptr(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace fspb

@@ -210,3 +210,12 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "4"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_noalloc_transpose_size_limit(fspb):
+    """The allocation-free transpose refuses sizes beyond its static scratch on the host,
+    before any device work (so this runs without a GPU)."""
+    st = fspb.fspb_csr_transpose_noalloc(1, 1, 1, 100, 1000, 3_000_000, 1, 1, 1, None)
+    assert st == fspb.FSPB_ERR_CAPACITY and "scratch" in fspb.fspb_last_error()
+    with pytest.raises(fspb.FspbError, match="nnz"):
+        fspb.fspb_csr_transpose_noalloc(1, 1, 1, 100, 1000, -1, 1, 1, 1, None)
