@@ -19,8 +19,11 @@ constexpr int kExtHoles = 1 << 30;
 constexpr int kErfcIntervals = 512;
 constexpr float kErfcMax = 4.0f;
 // erf on [0, kErfMax] by linear interpolation between kErfIntervals + 1 equally
-// spaced nodes, 256 per unit of argument (the fill; negative arguments by odd
-// symmetry, held at +-erf(kErfMax) beyond the last node)
+// spaced nodes, 256 per unit of argument (the fill; held at +-erf(kErfMax)
+// beyond the last node).  The table holds each interval as (intercept, slope) in
+// the table coordinate: kErfIntervals entries on [0, kErfMax] (compact form, odd
+// symmetry for negative arguments), then 2 kErfIntervals on [-kErfMax, kErfMax]
+// (mirrored form, coordinate offset by kErfIntervals, first entry constant)
 constexpr int kErfIntervals = 1024;
 constexpr float kErfMax = 4.0f;
 
@@ -69,7 +72,7 @@ struct alignas(16) PlanDev {
     float c2[kMaxTerms];
     float pdd_inv_step, pdd_max;   // 1/step; n_pdd - 1
     const float *pdd;
-    const float2 *erf_tab;       // [kErfIntervals] (erf at node k, erf at node k+1 minus it)
+    const float2 *erf_tab;       // [3 kErfIntervals]: compact form, then mirrored form
     // general kernel form (0: the analytic form above): c tables [3][n_terms][n_cdepth]
     // (c1, c2, c3), A [n_theta][n_adepth]
     int32_t gen, n_cdepth, n_theta, n_adepth;
@@ -93,6 +96,12 @@ struct alignas(16) PlanDev {
     const uint16_t *mlp_w2;      // BF16 W2 [out][in]
     int32_t use_mlp;
     int32_t erf_mirrored;        // fill stages erf on [-kErfMax, kErfMax] (analytic and tabulated forms)
+    int32_t erf_nc;              // every term's c2 a/2 over sigma stays below kErfMax: the first
+                                 // argument of a bracket never passes the mirrored table's top
+    float d_floor;               // lower bound applied to D: 0 when every weight (c1) and every
+                                 // depth-dose (A) entry is >= 0, so that D >= 0 exactly; else -inf
+    int32_t erf_square;          // every beam's beamlets are square (a = b)
+    int32_t erf_mode;            // how the fill reads erf (0..3, see erf_mirrored_mode in the kernels)
 };
 
 /* Caller-owned CSR output of one plan (device pointers). */
@@ -118,6 +127,8 @@ hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &
 size_t fill_shared_bytes(const PlanDev &h);
 size_t fill_shared_bytes(const PlanDev &h, bool mirrored_erf);
 bool fill_mirrored_erf(const PlanDev &h);
+/* The erf mode of the plan's fill when it stages the mirrored table (1, 2 or 3). */
+int mirrored_erf_mode(const PlanDev &h);
 /* 1 when the mirrored erf table keeps the plan's fill at the same workgroups per CU as the
  * 8 KB table (occupancy query for the current device); 0 otherwise. */
 int choose_erf_form(const PlanDev &h);

@@ -375,19 +375,28 @@ void erfc_table(std::vector<float4> &t)
 }
 
 /*
- * Piecewise-linear erf used by the fill kernel on [0, kErfMax] (kErfIntervals
- * intervals of width w = 1/256): node k holds erf(k w) rounded to FP32 and the
- * difference to erf((k + 1) w) taken from that rounded value, so that the
- * interpolant is continuous to FP32 rounding at every node.
+ * Piecewise-linear erf used by the fill kernel, nodes w = 1/256 apart, each
+ * interval stored as the line through its end nodes in the table coordinate
+ * x = z / w: (intercept, slope) = (erf(z_k) - k s_k, s_k) with s_k =
+ * erf(z_{k+1}) - erf(z_k), so the kernel evaluates x s_k + intercept with one
+ * FMA (computed in FP64, rounded once).  First the compact form (intervals of
+ * [0, kErfMax], k = 0 .. n-1), then the mirrored form (intervals of [-kErfMax,
+ * kErfMax] in the coordinate x = z / w + n, k = 0 .. 2n-1), whose first
+ * interval is replaced by the constant erf(-kErfMax) (it differs from the line
+ * there by 6e-10) so that arguments below the table can read it unclamped.
  */
 void erf_table(std::vector<float2> &t)
 {
     const int n = fspb::kErfIntervals;
     const double w = (double)fspb::kErfMax / n;
-    t.resize(n);
+    t.resize((size_t)3 * n);
     for (int k = 0; k < n; ++k) {
-        const float y0 = (float)std::erf(k * w);
-        t[k] = make_float2(y0, (float)(std::erf((k + 1) * w) - (double)y0));
+        const double e0 = std::erf(k * w), e1 = std::erf((k + 1) * w), sl = e1 - e0;
+        t[k] = make_float2((float)(e0 - k * sl), (float)sl);
+    }
+    for (int k = 0; k < 2 * n; ++k) {
+        const double e0 = std::erf((k - n) * w), e1 = std::erf((k + 1 - n) * w), sl = e1 - e0;
+        t[(size_t)n + k] = k == 0 ? make_float2((float)e0, 0.0f) : make_float2((float)(e0 - k * sl), (float)sl);
     }
 }
 
@@ -402,15 +411,62 @@ const std::vector<float2> &fill_erf_table()
 }
 
 /*
+ * True when the first argument of every bracket of Eq. 3, (c2 a/2 - |x|) /
+ * (sqrt2 c3), stays below the mirrored erf table's top (kErfMax) with a margin
+ * of 24 table intervals for FP32 rounding: the fill then reads it without a
+ * clamp.  c3 (sigma) is smallest at its first node (analytic form: sigma0,
+ * the slope being >= 0); for tables, c2 / c3 is a ratio of two linear
+ * functions on each depth interval, so its largest value sits on a node.
+ */
+/* True when every weight (c1) and every depth-dose (A) value of the kernel is
+ * >= 0: then each coefficient of Eq. 2-3 is >= 0 (each bracket of Eq. 3 is). */
+bool nonnegative_kernel(const fspb_kernel *K)
+{
+    if (const fspb_kernel_tables *T = K->tables) {
+        for (int64_t i = 0; i < (int64_t)K->n_terms * T->n_depth; ++i)
+            if (T->c1[i] < 0.0f) return false;
+        for (int64_t i = 0; i < (int64_t)T->n_theta * T->n_adepth; ++i)
+            if (T->A[i] < 0.0f) return false;
+        return true;
+    }
+    for (int i = 0; i < K->n_terms; ++i)
+        if (K->weight[i] < 0.0) return false;
+    for (int i = 0; i < K->n_pdd; ++i)
+        if (K->pdd[i] < 0.0f) return false;
+    return true;
+}
+
+bool erf_args_bounded(const fspb_kernel *K, const fspb_beam *beams, int32_t n_beams)
+{
+    double half = 0.0;
+    for (int32_t b = 0; b < n_beams; ++b) half = std::max(half, 0.5 * std::max(beams[b].beamlet_a, beams[b].beamlet_b));
+    const double per_unit = fspb::kErfIntervals / (double)fspb::kErfMax;    // table intervals per unit of argument
+    const double limit = (fspb::kErfIntervals - 24) / per_unit;
+    double worst = 0.0;
+    if (const fspb_kernel_tables *T = K->tables) {
+        for (int i = 0; i < K->n_terms; ++i)
+            for (int m = 0; m < T->n_depth; ++m) {
+                const size_t q = (size_t)i * T->n_depth + m;
+                worst = std::max(worst, (double)T->c2[q] * half / (std::sqrt(2.0) * (double)T->c3[q]));
+            }
+    } else {
+        for (int i = 0; i < K->n_terms; ++i)
+            worst = std::max(worst, K->width_scale[i] * half / (std::sqrt(2.0) * K->sigma0[i]));
+    }
+    return worst < limit;
+}
+
+/*
  * The fill's erf table form for a plan (fspb::choose_erf_form), remembered per
  * device, kernel shape and LDS size: plans of one geometry share the answer.
  */
 std::mutex g_form_mu;
-std::map<std::array<int64_t, 4>, int> g_form;
+std::map<std::array<int64_t, 5>, int> g_form;
 
 int erf_form(const fspb::PlanDev &h, int device)
 {
-    const std::array<int64_t, 4> key{device, h.n_terms, h.gen, (int64_t)fspb::fill_shared_bytes(h, false)};
+    const std::array<int64_t, 5> key{device, h.n_terms, h.gen, fspb::mirrored_erf_mode(h),
+                                     (int64_t)fspb::fill_shared_bytes(h, false)};
     std::lock_guard<std::mutex> lk(g_form_mu);
     auto it = g_form.find(key);
     if (it != g_form.end()) return it->second;
@@ -681,7 +737,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     L.rec = take(sizeof(BeamletRec) * (size_t)nbl);
     L.tile_beamlet = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
     L.pdd = take(sizeof(float) * (size_t)K->n_pdd);
-    L.erf = take(sizeof(float2) * fspb::kErfIntervals);
+    L.erf = take(sizeof(float2) * 3 * fspb::kErfIntervals);
     if (K->tables) {
         L.ctab = take(sizeof(float) * 3 * (size_t)K->n_terms * K->tables->n_depth);
         L.atab = take(sizeof(float) * (size_t)K->tables->n_theta * K->tables->n_adepth);
@@ -737,6 +793,11 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     // fspb_raytrace or fspb_batch_create copies it on its stream
     int dev = 0;
     FSPB_HIP(hipGetDevice(&dev), "get device");
+    h.erf_nc = erf_args_bounded(K, beams, n_beams) ? 1 : 0;
+    h.d_floor = nonnegative_kernel(K) ? 0.0f : -HUGE_VALF;
+    h.erf_square = 1;
+    for (int32_t b = 0; b < n_beams; ++b)
+        if (beams[b].beamlet_a != beams[b].beamlet_b) h.erf_square = 0;
     if (K->flags & FSPB_ERF_MIRRORED) {
         if (fspb::fill_shared_bytes(h, true) > 64 * 1024)
             return fail(FSPB_ERR_INVALID, "FSPB_ERF_MIRRORED: the fill would need %zu bytes of LDS (64 KB at most)",
@@ -747,6 +808,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     } else {
         h.erf_mirrored = erf_form(h, dev);
     }
+    h.erf_mode = h.erf_mirrored ? fspb::mirrored_erf_mode(h) : 0;
     FSPB_HIP(hipEventCreateWithFlags(&p->nnz_ready, hipEventDisableTiming), "create count event");
     st = slot_acquire(&p->nnz_host);
     if (st != FSPB_OK) return st;

@@ -501,6 +501,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const PlanDev *__restrict__
 
 /* ---------------------------------------------------------------- fill */
 
+/* Word 3 of a raw (unformatted, stride 0) gfx9 buffer descriptor. */
+constexpr int kRawBufferWord3 = 0x00020000;
+
 /* A wave-uniform 64-bit value moved to scalar registers (keeps address arithmetic scalar). */
 __device__ inline int64_t uniform64(int64_t v)
 {
@@ -520,77 +523,117 @@ __device__ inline gptr<T> as_global(T *p)
 }
 
 /*
- * erf(z) at the table coordinate x = z kErfScale: linear interpolation in the
- * LDS copy of the table on [0, kErfMax] (one 8-byte (value, difference) read),
- * sign restored by odd symmetry, held at +-erf(kErfMax) beyond the table.
+ * erf(z) at the table coordinate x = z kErfScale from the LDS copy of the
+ * fill's table: linear interpolation between nodes 1/256 apart, each interval
+ * k stored as the line through its two end nodes in the table coordinate,
+ * (intercept c_k, slope s_k), so that erf ~ x s_k + c_k is one FMA of the
+ * (clamped) argument and no fractional part is taken.
  *
- * The fill stages the table in one of two forms: this one (8 KB), or mirrored
- * onto [-kErfMax, kErfMax] (16 KB, arguments offset by kErfIntervals), where a
- * signed argument needs no absolute value or sign restore.  The mirrored form
- * saves four instructions per coefficient of a two-term kernel and is used
- * wherever its larger LDS footprint does not cost the fill a workgroup per CU.
+ * Two forms: compact (8 KB, the intervals of [0, kErfMax]; odd symmetry gives
+ * negative arguments) and mirrored (16 KB, the intervals of [-kErfMax,
+ * kErfMax], arguments offset by kErfIntervals, read with their sign).  The
+ * mirrored form's first interval is constant erf(-kErfMax) (slope 0), so an
+ * argument below the table reads that entry through a saturating conversion
+ * and needs no clamp; beyond the last node the argument is clamped.
  */
 constexpr float kErfScale = (float)kErfIntervals / kErfMax;
-constexpr int kErfLdsFloats = 2 * kErfIntervals;
-constexpr float kErfTopSigned = 2.0f * kErfIntervals - 1.0f / 1024.0f;   // below 2 kErfIntervals, fract < 1
+constexpr float kErfTop = (float)kErfIntervals - 1.0f / 1024.0f;            // below kErfIntervals
+constexpr float kErfTopSigned = 2.0f * kErfIntervals - 1.0f / 1024.0f;      // below 2 kErfIntervals
 
-__device__ inline float erf_lds(const float *__restrict__ tab, float x)
+/* compact form, any sign */
+__device__ inline float erf_lds(const float2 *__restrict__ tab, float x)
 {
-    const float xc = fminf(fabsf(x), (float)kErfIntervals - 1.0f / 1024.0f);
-    const int k = (int)xc;
-    const float f = __builtin_amdgcn_fractf(xc);
-    const float2 q = reinterpret_cast<const float2 *>(tab)[k];
-    return copysignf(fmaf(q.y, f, q.x), x);
+    const float xc = fminf(fabsf(x), kErfTop);
+    const float2 q = tab[(int)xc];
+    return copysignf(fmaf(xc, q.y, q.x), x);
 }
 
-/* erf_lds for an argument known to be >= 0 (no sign to restore); SE: in the
- * mirrored table, offset included. */
-template <bool SE = false>
-__device__ inline float erf_lds_pos(const float *__restrict__ tab, float x)
+/* compact form, x >= 0 */
+__device__ inline float erf_lds_pos(const float2 *__restrict__ tab, float x)
 {
-    const float xc = fminf(x, SE ? kErfTopSigned : (float)kErfIntervals - 1.0f / 1024.0f);
-    const int k = (int)xc;
-    const float f = __builtin_amdgcn_fractf(xc);
-    const float2 q = reinterpret_cast<const float2 *>(tab)[k];
-    return fmaf(q.y, f, q.x);
+    const float xc = fminf(x, kErfTop);
+    const float2 q = tab[(int)xc];
+    return fmaf(xc, q.y, q.x);
 }
 
-/* erf in the mirrored table at x + kErfIntervals (the offset is part of the argument). */
-__device__ inline float erf_lds_signed(const float *__restrict__ tab, float xo)
+/* mirrored form, clamped on both sides */
+__device__ inline float erf_m(const float2 *__restrict__ tab, float x)
 {
-    const float xc = __builtin_amdgcn_fmed3f(xo, 0.0f, kErfTopSigned);
-    const int k = (int)xc;
-    const float f = __builtin_amdgcn_fractf(xc);
-    const float2 q = reinterpret_cast<const float2 *>(tab)[k];
-    return fmaf(q.y, f, q.x);
+    const float xc = __builtin_amdgcn_fmed3f(x, 0.0f, kErfTopSigned);
+    const float2 q = tab[(int)xc];
+    return fmaf(xc, q.y, q.x);
 }
+
+/* mirrored form, x >= 0: clamped above */
+__device__ inline float erf_m_hi(const float2 *__restrict__ tab, float x)
+{
+    const float xc = fminf(x, kErfTopSigned);
+    const float2 q = tab[(int)xc];
+    return fmaf(xc, q.y, q.x);
+}
+
+/* mirrored form, x known to lie below the last node: v_cvt_u32_f32 saturates a
+ * negative argument to entry 0, the constant erf(-kErfMax) (x times a zero slope) */
+__device__ inline float erf_m_lo(const float2 *__restrict__ tab, float x)
+{
+    uint32_t k;
+    __asm__("v_cvt_u32_f32 %0, %1" : "=v"(k) : "v"(x));
+    const float2 q = tab[k];
+    return fmaf(x, q.y, q.x);
+}
+
+/*
+ * How the fill reads erf (a plan-level choice, made on the host):
+ *   0  compact table (odd symmetry for negative arguments);
+ *   1  mirrored table, both arguments of a bracket clamped;
+ *   2  mirrored table, the first argument known to stay below the table's top
+ *      (the plan's widest beamlet over its narrowest sigma): no clamp on it;
+ *   3  as 2, with square beamlets (a = b), so the u and v brackets of a term
+ *      share their offsets, and the second argument read through erf(z) =
+ *      -erf(-z) so that it too can only leave the table below (no clamp at
+ *      all, and a saturated bracket is exactly 0); in the analytic form the
+ *      first term's weight is folded into the staged depth dose.  Only for
+ *      kernels with D >= 0 (non-negative weights and depth dose).
+ */
+constexpr bool erf_mirrored_mode(int em) { return em >= 1; }
 
 /*
  * One bracket of Eq. 3, erf((h - x) is) + erf((h + x) is), with
  * is = 1/(sqrt2 sigma): isk = is kErfScale and hk = h isk put both arguments
  * in table coordinates.  The bracket is even in x, so it is evaluated at |x|,
- * where the second argument is never negative (h > 0).  SE: mirrored table,
- * hk already offset by kErfIntervals.
+ * where the second argument is never negative (h > 0).  Mirrored modes: hk
+ * already offset by kErfIntervals.
  */
-template <bool SE>
-__device__ inline float edge_pair(const float *__restrict__ tab, float x, float hk, float isk)
+template <int EM>
+__device__ inline float edge_pair(const float2 *__restrict__ tab, float x, float hk, float isk)
 {
     const float ax = fabsf(x);
-    if (SE) return erf_lds_signed(tab, fmaf(-ax, isk, hk)) + erf_lds_pos<true>(tab, fmaf(ax, isk, hk));
-    return erf_lds(tab, fmaf(-ax, isk, hk)) + erf_lds_pos(tab, fmaf(ax, isk, hk));
+    const float x1 = fmaf(-ax, isk, hk), x2 = fmaf(ax, isk, hk);
+    if (EM >= 2) return erf_m_lo(tab, x1) + erf_m_hi(tab, x2);
+    if (EM == 1) return erf_m(tab, x1) + erf_m_hi(tab, x2);
+    return erf_lds(tab, x1) + erf_lds_pos(tab, x2);
+}
+
+/* Mode 3: the bracket from hk = h isk + n and hk2 = n - h isk (n = kErfIntervals):
+ * erf(x1) - erf(mirror of (h + |x|) is), both read below the table's top. */
+__device__ inline float edge_pair_sq(const float2 *__restrict__ tab, float x, float hk, float hk2, float isk)
+{
+    const float ax = fabsf(x);
+    return erf_m_lo(tab, fmaf(-ax, isk, hk)) - erf_m_lo(tab, fmaf(-ax, isk, hk2));
 }
 
 /* hk of the bracket: h isk, plus the mirrored table's offset */
-template <bool SE>
+template <int EM>
 __device__ inline float edge_offset(float h, float isk)
 {
-    return SE ? fmaf(h, isk, (float)kErfIntervals) : h * isk;
+    return EM >= 1 ? fmaf(h, isk, (float)kErfIntervals) : h * isk;
 }
 
 /* Per-beamlet constants of the fill, held in registers. */
 template <int K>
 struct FillConst {
-    float sad, tA, inv_step, tau_max, pdd_inv, pdd_max;
+    float tA, inv_step, tau_max, pdd_inv, pdd_max;
+    bool floor0;                 // D >= 0 holds exactly: negative rounding residue is cut to 0
     int n_terms;
     float w4[K], ha[K], hb[K];
     float sig0[K], sig1[K];      // sigma law divided by kIsScale: 1/sigma' = isk
@@ -602,54 +645,69 @@ struct FillConst {
 // is kErfScale = kIsScale / sigma
 constexpr float kIsScale = 0.70710678118654752f * kErfScale;
 
-template <int K, bool GUARD, bool SE>
+/*
+ * D of one VOI voxel at s = t' - tA, with U' = (P - S).eu' SAD and
+ * V' = (P - S).ev' SAD (the lateral offsets scaled by SAD in advance), so that
+ * with r = 1/t' the iso-plane offsets are u = U' r, v = V' r and the inverse
+ * square (SAD/t')^2 = SAD^2 r^2 has its SAD^2 folded into the LDS depth dose.
+ */
+template <int K, bool GUARD, int EM>
 __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restrict__ tab,
-                                   const float2 *__restrict__ pdd, const float *__restrict__ etab,
+                                   const float2 *__restrict__ pdd, const float2 *__restrict__ etab,
                                    float s, float U, float V)
 {
-    const float tp = s + c.tA;                      // t' = |SO'|
-    const float g = c.sad * __builtin_amdgcn_rcpf(tp);   // SAD / t'
-    const float u = U * g, v = V * g;
+    const float r = __builtin_amdgcn_rcpf(s + c.tA);   // 1 / t'
+    const float u = U * r, v = V * r;
     // radiological depth at O': linear interpolation in the table (last entry has slope 0)
     const float tau = __builtin_amdgcn_fmed3f(s * c.inv_step, 0.0f, c.tau_max);
     const float2 q = tab[(int)tau];
     const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
-    // depth dose, held at the last node
+    // depth dose times SAD^2, held at the last node
     const float x = __builtin_amdgcn_fmed3f(d * c.pdd_inv, 0.0f, c.pdd_max);
     const float2 qp = pdd[(int)x];
-    const float A = fmaf(__builtin_amdgcn_fractf(x), qp.y, qp.x) * g * g;
+    const float A = fmaf(__builtin_amdgcn_fractf(x), qp.y, qp.x) * r * r;
     // lateral profile, Eq. 3
     float L = 0.0f;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         if (GUARD && i >= c.n_terms) break;
         const float isk = __builtin_amdgcn_rcpf(fmaf(c.sig1[i], d, c.sig0[i]));
-        const float eu = edge_pair<SE>(etab, u, edge_offset<SE>(c.ha[i], isk), isk);
-        const float ev = edge_pair<SE>(etab, v, edge_offset<SE>(c.hb[i], isk), isk);
-        L = i == 0 ? c.w4[0] * eu * ev : fmaf(c.w4[i] * eu, ev, L);   // no add of 0 for the first term
+        if (EM == 3) {
+            // square beamlets; the first term's weight is in the depth dose, c.w4 relative to it
+            const float hk = fmaf(c.ha[i], isk, (float)kErfIntervals), hk2 = fmaf(-c.ha[i], isk, (float)kErfIntervals);
+            const float eu = edge_pair_sq(etab, u, hk, hk2, isk), ev = edge_pair_sq(etab, v, hk, hk2, isk);
+            L = i == 0 ? eu * ev : fmaf(c.w4[i] * eu, ev, L);
+        } else {
+            const float eu = edge_pair<EM>(etab, u, edge_offset<EM>(c.ha[i], isk), isk);
+            const float ev = edge_pair<EM>(etab, v, edge_offset<EM>(c.hb[i], isk), isk);
+            L = i == 0 ? c.w4[0] * eu * ev : fmaf(c.w4[i] * eu, ev, L);   // no add of 0 for the first term
+        }
     }
-    return A * L;
+    // with non-negative weights and depth dose D is >= 0 (every bracket is); the table's
+    // rounding could otherwise leave a -1e-8-sized value where both brackets saturate
+    const float D = A * L;
+    if (EM == 3) return fmaxf(D, 0.0f);   // mode 3 implies such a kernel
+    return c.floor0 ? fmaxf(D, 0.0f) : D;
 }
 
 /*
- * Eq. 2-3 in their general form: A(theta_j, d) from the beamlet's LDS row
- * (already interpolated in theta), c1, c2, c3 of each term from LDS depth
+ * Eq. 2-3 in their general form: A(theta_j, d) SAD^2 from the beamlet's LDS
+ * row (already interpolated in theta), c1, c2, c3 of each term from LDS depth
  * tables (value, slope) laid out [c][term][node].
  */
-template <int K, bool SE>
+template <int K, int EM>
 __device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__restrict__ tab,
                                        const float2 *__restrict__ sA, const float2 *__restrict__ sc,
-                                       const float *__restrict__ etab, float s, float U, float V)
+                                       const float2 *__restrict__ etab, float s, float U, float V)
 {
-    const float tp = s + c.tA;
-    const float g = c.sad * __builtin_amdgcn_rcpf(tp);
-    const float u = U * g, v = V * g;
+    const float r = __builtin_amdgcn_rcpf(s + c.tA);
+    const float u = U * r, v = V * r;
     const float tau = __builtin_amdgcn_fmed3f(s * c.inv_step, 0.0f, c.tau_max);
     const float2 q = tab[(int)tau];
     const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
     const float xa = __builtin_amdgcn_fmed3f(d * c.a_inv, 0.0f, c.a_max);
     const float2 qa = sA[(int)xa];
-    const float A = fmaf(__builtin_amdgcn_fractf(xa), qa.y, qa.x) * g * g;
+    const float A = fmaf(__builtin_amdgcn_fractf(xa), qa.y, qa.x) * r * r;
     const float xc = __builtin_amdgcn_fmed3f(d * c.c_inv, 0.0f, c.c_max);
     const int kc = (int)xc;
     const float fc = __builtin_amdgcn_fractf(xc);
@@ -659,11 +717,21 @@ __device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__re
         const float2 q1 = sc[i * c.nc + kc], q2 = sc[(K + i) * c.nc + kc], q3 = sc[(2 * K + i) * c.nc + kc];
         const float c1 = fmaf(fc, q1.y, q1.x), c2 = fmaf(fc, q2.y, q2.x), c3 = fmaf(fc, q3.y, q3.x);
         const float isk = kIsScale * __builtin_amdgcn_rcpf(c3);
-        const float eu = edge_pair<SE>(etab, u, edge_offset<SE>(c2 * c.half_a, isk), isk);
-        const float ev = edge_pair<SE>(etab, v, edge_offset<SE>(c2 * c.half_b, isk), isk);
+        float eu, ev;
+        if (EM == 3) {
+            const float h = c2 * c.half_a;
+            const float hk = fmaf(h, isk, (float)kErfIntervals), hk2 = fmaf(-h, isk, (float)kErfIntervals);
+            eu = edge_pair_sq(etab, u, hk, hk2, isk);
+            ev = edge_pair_sq(etab, v, hk, hk2, isk);
+        } else {
+            eu = edge_pair<EM>(etab, u, edge_offset<EM>(c2 * c.half_a, isk), isk);
+            ev = edge_pair<EM>(etab, v, edge_offset<EM>(c2 * c.half_b, isk), isk);
+        }
         L = i == 0 ? 0.25f * c1 * eu * ev : fmaf(0.25f * c1 * eu, ev, L);
     }
-    return A * L;
+    const float D = A * L;
+    if (EM == 3) return fmaxf(D, 0.0f);   // mode 3 implies such a kernel
+    return c.floor0 ? fmaxf(D, 0.0f) : D;
 }
 
 /* Entries of the depth-dose region of the fill's LDS: the PDD, or the general
@@ -680,9 +748,9 @@ __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readla
  * tables, then each wave takes tiles of 64 grid rows; a tile's VOI candidates
  * are flattened across its rows, 64 per chunk, members compacted by ballot.
  * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K);
- * SE: mirrored erf table.
+ * EM: how erf is read (erf_mirrored_mode).
  */
-template <int K, int W, bool GUARD, bool SURR, bool GEN = false, bool SE = false>
+template <int K, int W, bool GUARD, bool SURR, bool GEN = false, int EM = 0>
 __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem)
 {
     const BeamletRec &R = P.rec[j];
@@ -690,22 +758,25 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     if (n_tiles == 0) return;
     constexpr int kB = W * kWave;
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = lane_id();
+    constexpr bool SE = erf_mirrored_mode(EM);
+    // mode 3, analytic form: term weights relative to the first, whose weight the depth dose carries
+    constexpr bool FOLD_W = EM == 3 && !GEN;
 
     // ---- constants into registers
     const int n_table = R.n_table, n_pdd = lds_pdd_pairs(P), tile0 = R.tile0;
     const int iy0 = R.iy0, n_iy = R.n_iy, iz0 = R.iz0, n_rows = R.n_iy * R.n_iz;
     const int nx = P.nx, ny = P.ny, wpr = P.wpr;
     FillConst<K> c;
-    c.sad = R.sad_f;
     c.tA = R.tA_f;
     c.inv_step = R.inv_step_f;
     c.tau_max = R.tau_max_f;
     c.pdd_inv = P.pdd_inv_step;
     c.pdd_max = P.pdd_max;
+    c.floor0 = P.d_floor == 0.0f;
     c.n_terms = P.n_terms;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        c.w4[i] = P.w4[i];
+        c.w4[i] = FOLD_W ? P.w4[i] / P.w4[0] : P.w4[i];
         c.sig0[i] = P.sig0[i] * (1.0f / kIsScale);
         c.sig1[i] = P.sig1[i] * (1.0f / kIsScale);
         c.ha[i] = R.ha[i];
@@ -720,9 +791,11 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         c.half_b = R.half_b;
         c.nc = P.n_cdepth;
     }
-    const double tA = R.tA;
-    const double t1 = P.sp[0] * R.e[0], u1 = P.sp[0] * R.eu[0], v1 = P.sp[0] * R.ev[0];
-    const float t1f = R.t1_f, U1f = R.U1_f, V1f = R.V1_f;
+    const float sad_f = R.sad_f;
+    const double tA = R.tA, sad = R.sad;
+    // per voxel step along x: t' in float, U and V scaled by SAD (rounded once from FP64)
+    const double t1 = P.sp[0] * R.e[0], u1 = P.sp[0] * R.eu[0] * sad, v1 = P.sp[0] * R.ev[0] * sad;
+    const float t1f = R.t1_f, U1f = (float)u1, V1f = (float)v1;
     const gptr<const uint32_t> bits = as_global<const uint32_t>(P.bits);
     const gptr<const int32_t> tile_count = as_global<const int32_t>(P.tile_count);
     const gptr<int32_t> out_idx = as_global<int32_t>(O.indices);
@@ -730,16 +803,16 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const int64_t capacity = O.capacity;
     const int64_t row_base = uniform64(O.indptr[j] - O.indptr[O.row0]);
 
-    // ---- LDS: erf table, depth table, depth dose, tile prefix
-    float *s_erf = reinterpret_cast<float *>(smem);
-    constexpr int kErfFloats = SE ? 2 * kErfLdsFloats : kErfLdsFloats;
-    float2 *s_tab = reinterpret_cast<float2 *>(s_erf + kErfFloats);
+    // ---- LDS: erf table, depth table, depth dose (times SAD^2), tile prefix
+    float2 *s_erf = reinterpret_cast<float2 *>(smem);
+    constexpr int kErfPairs = SE ? 2 * kErfIntervals : kErfIntervals;
+    float2 *s_tab = s_erf + kErfPairs;
     float2 *s_pdd = s_tab + P.max_table;
     int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
     __shared__ int wsum[W];
     // surrogate: per-wave h1 tile after the tile prefix, and W2 fragments in registers
     uint16_t *s_h1 = reinterpret_cast<uint16_t *>(
-        smem + ((sizeof(float) * kErfFloats + sizeof(float2) * ((size_t)P.max_table + n_pdd) +
+        smem + ((sizeof(float2) * ((size_t)kErfPairs + P.max_table + n_pdd) +
                  sizeof(int) * ((size_t)P.max_tiles + 1) + 15) & ~(size_t)15)) + wave * (64 * mlp::kH1Stride);
     mlp::W2Frags wf;
     if (SURR) mlp::load_w2_frags(P.mlp_w2, wf);
@@ -747,29 +820,18 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const bool mlp_ok = SURR && R.mlp_ok;
 
     {
-        const float2 *et = P.erf_tab;
-        if (SE) {
-            // [0, n): erf on [-kErfMax, 0) from the odd symmetry; [n, 2n): the table
-            for (int i = tid; i < 2 * kErfIntervals; i += kB) {
-                float2 q;
-                if (i >= kErfIntervals) {
-                    q = et[i - kErfIntervals];
-                } else {
-                    const float2 m = et[kErfIntervals - 1 - i];
-                    q = make_float2(-(m.x + m.y), m.y);
-                }
-                reinterpret_cast<float2 *>(s_erf)[i] = q;
-            }
-        } else {
-            for (int i = tid; i < kErfIntervals; i += kB) reinterpret_cast<float2 *>(s_erf)[i] = et[i];
-        }
+        // the erf table in the form this fill reads (compact, or mirrored after it)
+        const float4 *__restrict__ et = reinterpret_cast<const float4 *>(P.erf_tab + (SE ? kErfIntervals : 0));
+        float4 *se4 = reinterpret_cast<float4 *>(s_erf);
+        for (int i = tid; i < kErfPairs / 2; i += kB) se4[i] = et[i];
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
         for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
             s_tab[i] = make_float2(d0, (i + 1 < n_table ? tab[i + 1] : d0) - d0);
         }
+        const float sad2 = sad_f * sad_f;
         if (GEN) {
-            // this beamlet's A row (interpolated in theta), then the c tables
+            // this beamlet's A row (interpolated in theta, times SAD^2), then the c tables
             const int na = P.n_adepth, k0 = R.theta_k, k1 = min(R.theta_k + 1, P.n_theta - 1);
             const float ft = R.theta_f;
             const gptr<const float> a0 = as_global<const float>(P.atab + (size_t)k0 * na);
@@ -777,7 +839,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             for (int i = tid; i < na; i += kB) {
                 const float v0 = fmaf(ft, a1[i] - a0[i], a0[i]);
                 const float v1 = i + 1 < na ? fmaf(ft, a1[i + 1] - a0[i + 1], a0[i + 1]) : v0;
-                s_pdd[i] = make_float2(v0, v1 - v0);
+                s_pdd[i] = make_float2(v0 * sad2, (v1 - v0) * sad2);
             }
             const int nc = P.n_cdepth, ntab = 3 * P.n_terms * nc;
             const gptr<const float> ct = as_global<const float>(P.ctab);
@@ -788,9 +850,10 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             }
         } else {
             const gptr<const float> pd = as_global<const float>(P.pdd);
+            const float scale = FOLD_W ? sad2 * P.w4[0] : sad2;
             for (int i = tid; i < n_pdd; i += kB) {
                 const float p0 = pd[i];
-                s_pdd[i] = make_float2(p0, (i + 1 < n_pdd ? pd[i + 1] : p0) - p0);
+                s_pdd[i] = make_float2(p0 * scale, ((i + 1 < n_pdd ? pd[i + 1] : p0) - p0) * scale);
             }
         }
     }
@@ -812,11 +875,13 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     }
 
     for (int tl = wave; tl < n_tiles; tl += W) {
-        if (tile_count[tile0 + tl] == 0) continue;
+        const int members = __builtin_amdgcn_readfirstlane(tile_count[tile0 + tl]);
+        if (members == 0) continue;
         const int64_t out0 = row_base + __builtin_amdgcn_readfirstlane(s_tpre[tl]);
-        // lane = grid row of this tile: its VOI interval and FP32 start values
+        // lane = grid row of this tile: its VOI interval and FP32 start values; the column
+        // of candidate k of the row is cb + k, its mask word wb + ((lo + k) >> 5)
         const int r = tl * kRowsPerTile + lane;
-        int lo = 0, hi = -1, grow = 0;
+        int lo = 0, hi = -1, cb = 0, wb = 0;
         float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
         if (r < n_rows) {
             const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
@@ -824,11 +889,13 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             const RowGeom G = row_geom(P, R);
             bool holes;
             if (row_span(G, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
-                grow = iz * ny + iy;
+                const int grow = iz * ny + iy;
+                cb = grow * nx + lo;
+                wb = grow * wpr;
                 const double x = (double)lo;
                 s_lo = (float)(a.t0 + x * t1 - tA);
-                U_lo = (float)(a.U0 + x * u1);
-                V_lo = (float)(a.V0 + x * v1);
+                U_lo = (float)(fma(x, P.sp[0] * R.eu[0], a.U0) * sad);
+                V_lo = (float)(fma(x, P.sp[0] * R.ev[0], a.V0) * sad);
             } else {
                 lo = 0;
                 hi = -1;
@@ -843,7 +910,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             const int a = dst << 2;
             lo = __builtin_amdgcn_ds_permute(a, lo);
             cnt = __builtin_amdgcn_ds_permute(a, cnt);
-            grow = __builtin_amdgcn_ds_permute(a, grow);
+            cb = __builtin_amdgcn_ds_permute(a, cb);
+            wb = __builtin_amdgcn_ds_permute(a, wb);
             s_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(s_lo)));
             U_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(U_lo)));
             V_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(V_lo)));
@@ -857,40 +925,53 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         // the first candidate of the next chunk)
         int rcur = 0;
         int64_t written = out0;
-        // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
         // a tile whose counted members equal its candidates (no masked voxel inside its rows)
         // takes every candidate: no mask read, and member lanes are the low ones of the chunk
-        const bool dense = tile_count[tile0 + tl] == total;
-        auto chunk = [&](const int p, const int rr, auto dense_tag) {
+        const bool dense = members == total;
+        // the tile's entries fit the caller's arrays: no per-chunk capacity test, and they are
+        // written through buffer descriptors over exactly the tile's entries (32-bit offsets:
+        // the lane's slot in a VGPR, the chunk's start in an SGPR)
+        const bool fits = out0 + members <= capacity;
+        const __amdgpu_buffer_rsrc_t rs_idx =
+            __builtin_amdgcn_make_buffer_rsrc(O.indices + out0, 0, members * 4, kRawBufferWord3);
+        const __amdgpu_buffer_rsrc_t rs_val =
+            __builtin_amdgcn_make_buffer_rsrc(O.values + out0, 0, members * 4, kRawBufferWord3);
+        // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
+        auto chunk = [&](const int p, const int rr, auto dense_tag, auto fits_tag) {
             constexpr bool DENSE = decltype(dense_tag)::value;
-            const int k = p - __shfl(excl, rr, kWave);
-            const int ix = __shfl(lo, rr, kWave) + k;
-            const int gr = __shfl(grow, rr, kWave);
+            constexpr bool FITS = decltype(fits_tag)::value;
+            // row rr's values, fetched by lane (rr < 64: the byte address needs no wrap)
+            const int ra = rr << 2;
+            auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
+            auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
+            const int k = p - from_row(excl);
+            const int col = from_row(cb) + k;
             bool member = false;
             if (DENSE) {
                 member = p < total;
-            } else if (p < total) {
-                const uint32_t wo = ((uint32_t)(gr * wpr) + ((uint32_t)ix >> 5)) << 2;   // byte offset
-                member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
+            } else {
+                const int wr = from_row(wb), ix = from_row(lo) + k;
+                if (p < total) {
+                    const uint32_t wo = ((uint32_t)wr + ((uint32_t)ix >> 5)) << 2;   // byte offset
+                    member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
+                }
             }
             const uint64_t mask = __ballot(member);
             const uint32_t slot = DENSE ? (uint32_t)lane : (uint32_t)mbcnt64(mask);
-            const float sl = __shfl(s_lo, rr, kWave);
-            const float ul = __shfl(U_lo, rr, kWave);
-            const float vl = __shfl(V_lo, rr, kWave);
+            const float sl = from_row_f(s_lo);
+            const float ul = from_row_f(U_lo);
+            const float vl = from_row_f(V_lo);
             // this chunk's entries go to [written, written + popcount); the bases are wave-uniform
             const gptr<char> ip = (gptr<char>)(out_idx + written);
             const gptr<char> vp = (gptr<char>)(out_val + written);
-            // slots below `avail` fit in the caller's arrays (scalar: no 64-bit compare per lane)
-            const int64_t left = capacity - written;
-            const uint32_t avail = left >= kWave ? (uint32_t)kWave : (left > 0 ? (uint32_t)left : 0u);
             float D = 0.0f;
             if (SURR) {
                 // the network runs on all 64 lanes (matrix cores need the whole wave)
                 const float kf = (float)k;
                 const float sv = fmaf(kf, t1f, sl), Uv = fmaf(kf, U1f, ul), Vv = fmaf(kf, V1f, vl);
-                const float g = c.sad * __builtin_amdgcn_rcpf(sv + c.tA);
-                const float au = fabsf(Uv * g), av = fabsf(Vv * g);
+                const float rr_ = __builtin_amdgcn_rcpf(sv + c.tA);
+                const float g = sad_f * rr_;
+                const float au = fabsf(Uv * rr_), av = fabsf(Vv * rr_);
                 const float tau = __builtin_amdgcn_fmed3f(sv * c.inv_step, 0.0f, c.tau_max);
                 const float2 q = s_tab[(int)tau];
                 const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
@@ -900,26 +981,35 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                 if (in_box) mlp::features(d, au, av, a_f, x);
                 const float y = mlp::forward_wave(P.mlp_p, wf, x, s_h1);
                 if (in_box) D = y * g * g;
-                else if (member) D = dose_value<K, GUARD, SE>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
+                else if (member) D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
             }
             if (member) {
                 const float kf = (float)k;
                 if (GEN)
-                    D = dose_value_gen<K, SE>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
-                                          fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
+                    D = dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                                                  fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
                 else if (!SURR)
-                    D = dose_value<K, GUARD, SE>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
-                                             fmaf(kf, V1f, vl));
-                if (slot < avail) {
-                    *(gptr<int32_t>)(ip + (slot << 2)) = gr * nx + ix;
-                    *(gptr<float>)(vp + (slot << 2)) = D;
+                    D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                                     fmaf(kf, V1f, vl));
+                if (FITS) {
+                    const int so = (int)(written - out0) << 2;
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, (int)(slot << 2), so, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D), rs_val, (int)(slot << 2), so, 0);
                 } else {
-                    *O.overflow = 1;
+                    // slots below `avail` fit in the caller's arrays
+                    const int64_t left = capacity - written;
+                    const uint32_t avail = left >= kWave ? (uint32_t)kWave : (left > 0 ? (uint32_t)left : 0u);
+                    if (slot < avail) {
+                        *(gptr<int32_t>)(ip + (slot << 2)) = col;
+                        *(gptr<float>)(vp + (slot << 2)) = D;
+                    } else {
+                        *O.overflow = 1;
+                    }
                 }
             }
             written += __popcll(mask);
         };
-        auto walk2 = [&](auto dense_tag) {
+        auto walk2 = [&](auto dense_tag, auto fits_tag) {
             // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane.
             // Bit b of (mhi:mlo) marks a row starting at candidate c0 + b (0 < b < 128);
             // a lane's row is rcur plus the row starts at or below its candidate, a
@@ -940,14 +1030,18 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rcur));
                 const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rcur + __popcll(nlo))));
-                chunk(c0 + lane, r1, dense_tag);
-                chunk(c0 + kWave + lane, r2, dense_tag);
+                chunk(c0 + lane, r1, dense_tag, fits_tag);
+                chunk(c0 + kWave + lane, r2, dense_tag, fits_tag);
                 rcur = rnext;
             }
         };
         if (!SURR) {
-            if (dense) walk2(std::true_type{});
-            else walk2(std::false_type{});
+            if (fits) {
+                if (dense) walk2(std::true_type{}, std::true_type{});
+                else walk2(std::false_type{}, std::true_type{});
+            } else {
+                walk2(std::false_type{}, std::false_type{});
+            }
         } else {
             for (int c0 = 0; c0 < total; c0 += kWave) {
                 while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
@@ -958,20 +1052,20 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                     if (eq > c0 + kWave - 1) break;
                     if (p >= eq) rr = q;
                 }
-                chunk(p, rr, std::false_type{});
+                chunk(p, rr, std::false_type{}, std::false_type{});
             }
         }
     }
 }
 
-template <int K, bool SURR, bool GEN, bool SE>
+template <int K, bool SURR, bool GEN, int EM>
 __global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     // launched before the host has read the plan's total: write nothing if it does not fit
     if (outs[0].check_nnz && *plans[0].nnz > outs[0].capacity) return;
-    fill_beamlet<K, kWavesPerBlock, false, SURR, GEN, SE>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
+    fill_beamlet<K, kWavesPerBlock, false, SURR, GEN, EM>(plans[0], outs[0], outs[0].row0 + (int)blockIdx.x, smem);
 }
 
 /* ------------------------------------------------------------ batches */
@@ -1015,6 +1109,8 @@ __global__ __launch_bounds__(kScanBlock) void kp_scan(const PlanDev *const *__re
     scan_plan(*plans[blockIdx.x], outs[blockIdx.x].indptr);
 }
 
+// amdgpu_waves_per_eu(4): a register budget that leaves room for at least four waves per SIMD
+// (it is a lower bound on occupancy, not a cap)
 template <int K, int W>
 __global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(4))) void kp_fill(const PlanDev *const *__restrict__ plans,
                                                      const OutDev *__restrict__ outs,
@@ -1032,8 +1128,12 @@ __global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(4))) 
         const int2 it = items[w];
         const PlanDev &P = *plans[it.x];
         // each plan in the erf table form of its own fill (identical results to it)
-        if (P.erf_mirrored && !P.use_mlp) fill_beamlet<K, W, true, false, false, true>(P, outs[it.x], it.y, smem);
-        else fill_beamlet<K, W, true, false>(P, outs[it.x], it.y, smem);
+        switch (P.erf_mode) {
+        case 3: fill_beamlet<K, W, true, false, false, 3>(P, outs[it.x], it.y, smem); break;
+        case 2: fill_beamlet<K, W, true, false, false, 2>(P, outs[it.x], it.y, smem); break;
+        case 1: fill_beamlet<K, W, true, false, false, 1>(P, outs[it.x], it.y, smem); break;
+        default: fill_beamlet<K, W, true, false, false, 0>(P, outs[it.x], it.y, smem); break;
+        }
         __syncthreads();
     }
 }
@@ -1081,7 +1181,8 @@ hipError_t launch_scan(const PlanDev *dplan, const OutDev *dout, const PlanDev &
 
 size_t fill_shared_bytes(const PlanDev &h, bool mirrored_erf)
 {
-    size_t b = sizeof(float) * (mirrored_erf ? 2 * kErfLdsFloats : kErfLdsFloats) + sizeof(float2) * ((size_t)h.max_table + (size_t)lds_pdd_pairs(h)) +
+    size_t b = sizeof(float2) * ((mirrored_erf ? 2 * kErfIntervals : kErfIntervals) + (size_t)h.max_table +
+                                 (size_t)lds_pdd_pairs(h)) +
                sizeof(int) * ((size_t)h.max_tiles + 1);
     if (h.use_mlp) b = ((b + 15) & ~(size_t)15) + sizeof(uint16_t) * 64 * mlp::kH1Stride * kWavesPerBlock;
     return b;
@@ -1094,14 +1195,31 @@ size_t fill_shared_bytes(const PlanDev &h)
 
 bool fill_mirrored_erf(const PlanDev &h) { return h.erf_mirrored && !h.use_mlp; }
 
+int mirrored_erf_mode(const PlanDev &h)
+{
+    if (!h.erf_nc) return 1;
+    return h.erf_square && h.d_floor == 0.0f && (h.gen || h.w4[0] != 0.0f) ? 3 : 2;
+}
+
+template <int K, bool GEN>
+static const void *fill_kernel_ptr_k(int em)
+{
+    switch (em) {
+    case 3: return (const void *)k_fill<K, false, GEN, 3>;
+    case 2: return (const void *)k_fill<K, false, GEN, 2>;
+    case 1: return (const void *)k_fill<K, false, GEN, 1>;
+    default: return (const void *)k_fill<K, false, GEN, 0>;
+    }
+}
+
 template <bool GEN>
-static const void *fill_kernel_ptr(int K, bool se)
+static const void *fill_kernel_ptr(int K, int em)
 {
     switch (K) {
-    case 1: return se ? (const void *)k_fill<1, false, GEN, true> : (const void *)k_fill<1, false, GEN, false>;
-    case 2: return se ? (const void *)k_fill<2, false, GEN, true> : (const void *)k_fill<2, false, GEN, false>;
-    case 3: return se ? (const void *)k_fill<3, false, GEN, true> : (const void *)k_fill<3, false, GEN, false>;
-    default: return se ? (const void *)k_fill<4, false, GEN, true> : (const void *)k_fill<4, false, GEN, false>;
+    case 1: return fill_kernel_ptr_k<1, GEN>(em);
+    case 2: return fill_kernel_ptr_k<2, GEN>(em);
+    case 3: return fill_kernel_ptr_k<3, GEN>(em);
+    default: return fill_kernel_ptr_k<4, GEN>(em);
     }
 }
 
@@ -1138,8 +1256,9 @@ int choose_erf_form(const PlanDev &h)
         (void)hipGetLastError();
         return 0;
     }
-    const void *fm = h.gen ? fill_kernel_ptr<true>(h.n_terms, true) : fill_kernel_ptr<false>(h.n_terms, true);
-    const void *fs = h.gen ? fill_kernel_ptr<true>(h.n_terms, false) : fill_kernel_ptr<false>(h.n_terms, false);
+    const int em = mirrored_erf_mode(h);
+    const void *fm = h.gen ? fill_kernel_ptr<true>(h.n_terms, em) : fill_kernel_ptr<false>(h.n_terms, em);
+    const void *fs = h.gen ? fill_kernel_ptr<true>(h.n_terms, 0) : fill_kernel_ptr<false>(h.n_terms, 0);
     const int nm = fill_groups_per_cu(fm, lds_m, lds_cu), ns = fill_groups_per_cu(fs, lds_s, lds_cu);
     return nm > 0 && nm >= ns ? 1 : 0;
 }
@@ -1201,15 +1320,15 @@ hipError_t launch_fill(const PlanDev *dplan, const OutDev *dout, const PlanDev &
     const size_t lds = fill_shared_bytes(h);
     if (h.use_mlp) {
         switch (h.n_terms) {
-        case 1: hipLaunchKernelGGL((k_fill<1, true, false, false>), grid, block, lds, s, dplan, dout); break;
-        case 2: hipLaunchKernelGGL((k_fill<2, true, false, false>), grid, block, lds, s, dplan, dout); break;
-        case 3: hipLaunchKernelGGL((k_fill<3, true, false, false>), grid, block, lds, s, dplan, dout); break;
-        default: hipLaunchKernelGGL((k_fill<4, true, false, false>), grid, block, lds, s, dplan, dout); break;
+        case 1: hipLaunchKernelGGL((k_fill<1, true, false, 0>), grid, block, lds, s, dplan, dout); break;
+        case 2: hipLaunchKernelGGL((k_fill<2, true, false, 0>), grid, block, lds, s, dplan, dout); break;
+        case 3: hipLaunchKernelGGL((k_fill<3, true, false, 0>), grid, block, lds, s, dplan, dout); break;
+        default: hipLaunchKernelGGL((k_fill<4, true, false, 0>), grid, block, lds, s, dplan, dout); break;
         }
         return hipGetLastError();
     }
-    const void *f = h.gen ? fill_kernel_ptr<true>(h.n_terms, fill_mirrored_erf(h))
-                          : fill_kernel_ptr<false>(h.n_terms, fill_mirrored_erf(h));
+    const int em = h.erf_mode;
+    const void *f = h.gen ? fill_kernel_ptr<true>(h.n_terms, em) : fill_kernel_ptr<false>(h.n_terms, em);
     void *args[] = {const_cast<PlanDev **>(&dplan), const_cast<OutDev **>(&dout)};
     return hipLaunchKernel(f, grid, block, args, lds, s);
 }

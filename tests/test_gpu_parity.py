@@ -137,6 +137,22 @@ def test_erf_table_forms(torch_gpu, oracle_lib, pdd_step):
          f"{'mirrored' if auto.desc.fill_lds_bytes >= 16384 + pairs else 'compact'} form")
 
 
+def test_negative_weight_term(torch_gpu, oracle_lib):
+    """A kernel whose second term has a negative weight (c1 = 1.15, -0.15, sigma2 = 2 sigma1):
+    D may be negative in the tails, so no zero floor applies; parity with the oracle, and
+    the sign of every entry above 1e-6 of the maximum in magnitude agrees with it."""
+    g = fi.slab_phantom(45, n=(44, 40, 30), spacing=(0.5, 0.5, 0.5), lung_side=(3, 6), bone_side=(1, 2))
+    k = fi.default_kernel(45)
+    k.weight = [1.15, -0.15]
+    prob = fi.Problem("negw", g, fi.coplanar_beams(3, (0.11, -0.07, 0.13), 100.0, 1.0, 1.0, 4, 3), k)
+    plan, csr, ora, r = _full_compare(oracle_lib, prob)
+    _, _, oval = ora.full()
+    v = csr.values.double().cpu().numpy()
+    big = np.abs(oval) > 1e-6 * np.abs(oval).max()
+    assert np.array_equal(np.sign(v[big]), np.sign(oval[big]))
+    _say(f"  nnz={csr.nnz} negative={(oval < 0).sum()} max_rel={r['max_rel']:.2e} band={r['band_mismatches']}")
+
+
 def test_water_axes_on_voxel_faces(torch_gpu, oracle_lib):
     """Axes along voxel faces and through voxel edges (gantry 0/90/180/270, v = 0 row)."""
     g = fi.water_phantom((40, 40, 12), (0.5, 0.5, 0.5))

@@ -133,7 +133,8 @@ def test_fallback_outside_the_training_box(torch_gpu, oracle_lib):
     r = compare_plan(oracle_lib.OraclePlan(prob), b)
     print(f"\n  fallback fill vs oracle: rows={r['rows']} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e}", flush=True)
     av, bv = av.double().cpu().numpy(), b.values.double().cpu().numpy()
-    np.testing.assert_allclose(bv, av, rtol=1e-5, atol=1e-7 * av.max())
+    # the two erf table forms agree to 1e-6 of the maximum (as in test_erf_table_forms)
+    np.testing.assert_allclose(bv, av, rtol=1e-5, atol=1e-6 * av.max())
     # a plan with other kernel parameters is refused
     import paper_0908_4417_amd as m
     other = Plan(fi.Problem("o", g, prob.beams, fi.default_kernel(4)), "cuda:0")
