@@ -173,6 +173,12 @@ typedef struct {
                                     fill's workgroups per CU on this device), the longest depth
                                     table and the depth dose as (value, slope) pairs, and the
                                     tile offsets of the beamlet with most tiles */
+    int32_t fill_erf_mode;       /* how the fill reads erf: 0 the 8 KB table (sign by odd
+                                    symmetry); 1 the mirrored table with clamped arguments;
+                                    2 mirrored, the first argument of each bracket unclamped
+                                    (the plan's widest beamlet over its narrowest sigma keeps
+                                    it inside the table); 3 as 2 with square beamlets and a
+                                    non-negative kernel, no argument clamped */
 } fspb_plan_desc;
 
 /*

@@ -83,7 +83,8 @@ SURROGATE_PARAMS = 4545
 
 class FspbPlanDesc(C.Structure):
     _fields_ = [("n_beamlets", C.c_int32), ("n_voxels", C.c_int32), ("table_entries", C.c_int64),
-                ("n_tiles", C.c_int64), ("max_table", C.c_int32), ("fill_lds_bytes", C.c_int32)]
+                ("n_tiles", C.c_int64), ("max_table", C.c_int32), ("fill_lds_bytes", C.c_int32),
+                ("fill_erf_mode", C.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol include/fspb.h declares

@@ -1029,6 +1029,7 @@ fspb_status fspb_plan_info(const fspb_plan *p, fspb_plan_desc *d)
     d->n_tiles = p->h.n_tiles;
     d->max_table = p->h.max_table;
     d->fill_lds_bytes = (int32_t)fspb::fill_shared_bytes(p->h);
+    d->fill_erf_mode = p->h.use_mlp ? 0 : p->h.erf_mode;
     return FSPB_OK;
 }
 

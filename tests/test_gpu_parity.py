@@ -137,6 +137,41 @@ def test_erf_table_forms(torch_gpu, oracle_lib, pdd_step):
          f"{'mirrored' if auto.desc.fill_lds_bytes >= 16384 + pairs else 'compact'} form")
 
 
+@pytest.mark.parametrize("form,mode", [("compact", 0), ("mirrored", 1)])
+def test_wide_beamlets_clamped_erf(torch_gpu, oracle_lib, form, mode):
+    """Beamlets 2.5 cm wide over a first-term sigma of 0.15 cm: the first argument of a
+    bracket can pass the top of the erf table, so the fill clamps it (mode 1 in the
+    mirrored table; mode 0 in the compact one).  Every row against the oracle."""
+    from paper_0908_4417_amd import Plan
+    g = fi.slab_phantom(46, n=(44, 40, 30), spacing=(0.5, 0.5, 0.5), lung_side=(3, 6), bone_side=(1, 2))
+    k = fi.default_kernel(46)
+    k.sigma0 = [0.15, 0.3]
+    beams = fi.coplanar_beams(2, (0.11, -0.07, 0.13), 100.0, 2.5, 2.5, 3, 2)
+    prob = fi.Problem("wide", g, beams, k)
+    plan = Plan(prob, "cuda:0", erf_form=form)
+    assert plan.desc.fill_erf_mode == mode
+    csr = plan.compute()
+    r = compare_plan(oracle_lib.OraclePlan(prob), csr)
+    _say(f"  {form}: mode={plan.desc.fill_erf_mode} nnz={csr.nnz} max_rel={r['max_rel']:.2e} "
+         f"band={r['band_mismatches']}")
+
+
+def test_erf_modes_of_the_parity_cases(torch_gpu):
+    """Which erf mode the parity problems above run in: square beamlets with a
+    non-negative kernel take mode 3, rectangular ones or a negative weight mode 2."""
+    from paper_0908_4417_amd import Plan
+    g = fi.water_phantom((20, 20, 16), (0.5, 0.5, 0.5))
+    sq = Plan(fi.Problem("sq", g, fi.coplanar_beams(1, (0.1, 0, 0), 100.0, 1.0, 1.0, 2, 2), fi.default_kernel(1)),
+              "cuda:0", erf_form="mirrored")
+    rect = Plan(fi.Problem("re", g, fi.coplanar_beams(1, (0.1, 0, 0), 100.0, 0.7, 0.9, 2, 2), fi.default_kernel(1)),
+                "cuda:0", erf_form="mirrored")
+    k = fi.default_kernel(1)
+    k.weight = [1.1, -0.1]
+    neg = Plan(fi.Problem("ng", g, fi.coplanar_beams(1, (0.1, 0, 0), 100.0, 1.0, 1.0, 2, 2), k), "cuda:0",
+               erf_form="mirrored")
+    assert (sq.desc.fill_erf_mode, rect.desc.fill_erf_mode, neg.desc.fill_erf_mode) == (3, 2, 2)
+
+
 def test_negative_weight_term(torch_gpu, oracle_lib):
     """A kernel whose second term has a negative weight (c1 = 1.15, -0.15, sigma2 = 2 sigma1):
     D may be negative in the tails, so no zero floor applies; parity with the oracle, and
