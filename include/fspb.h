@@ -149,12 +149,12 @@ typedef struct {
 
 /*
  * kernel.flags: the form in which the fill stages its erf table (linear
- * interpolation between 1025 nodes on [0, 4], the same interpolant in both
+ * interpolation between 961 nodes on [0, 3.75], the same interpolant in both
  * forms, so the coefficients agree to rounding).  By default plan creation
- * takes the mirrored form (16 KB, the table extended onto [-4, 4] so that a
+ * takes the mirrored form (15 KB, the table extended onto [-3.75, 3.75] so that a
  * signed argument is read directly) unless its larger LDS footprint would
  * cost the fill workgroups per CU on the current device, and the compact form
- * (8 KB on [0, 4], the sign restored by odd symmetry) otherwise.  These flags
+ * (7.5 KB on [0, 3.75], the sign restored by odd symmetry) otherwise.  These flags
  * force one form; FSPB_ERF_MIRRORED fails with FSPB_ERR_INVALID when the
  * fill's LDS would then exceed 64 KB.
  */
@@ -168,12 +168,12 @@ typedef struct {
     int64_t table_entries;       /* sum of depth-table lengths */
     int64_t n_tiles;             /* units of work of the count and fill kernels */
     int32_t max_table;           /* longest depth table */
-    int32_t fill_lds_bytes;      /* LDS of one fill workgroup: the erf table (8 KB on [0, 4], or
-                                    16 KB mirrored onto [-4, 4] where that does not lower the
+    int32_t fill_lds_bytes;      /* LDS of one fill workgroup: the erf table (7.5 KB on [0, 3.75],
+                                    or 15 KB mirrored onto [-3.75, 3.75] where that does not lower the
                                     fill's workgroups per CU on this device), the longest depth
                                     table and the depth dose as (value, slope) pairs, and the
                                     tile offsets of the beamlet with most tiles */
-    int32_t fill_erf_mode;       /* how the fill reads erf: 0 the 8 KB table (sign by odd
+    int32_t fill_erf_mode;       /* how the fill reads erf: 0 the compact table (sign by odd
                                     symmetry); 1 the mirrored table with clamped arguments;
                                     2 mirrored, the first argument of each bracket unclamped
                                     (the plan's widest beamlet over its narrowest sigma keeps

@@ -20,12 +20,13 @@ constexpr int kErfcIntervals = 512;
 constexpr float kErfcMax = 4.0f;
 // erf on [0, kErfMax] by linear interpolation between kErfIntervals + 1 equally
 // spaced nodes, 256 per unit of argument (the fill; held at +-erf(kErfMax)
-// beyond the last node).  The table holds each interval as (intercept, slope) in
+// beyond the last node: erfc(3.75) = 1.1e-7, below 1e-5 of any bracket of Eq. 3
+// that enters a coefficient above 1 % of the maximum).  The table holds each interval as (intercept, slope) in
 // the table coordinate: kErfIntervals entries on [0, kErfMax] (compact form, odd
 // symmetry for negative arguments), then 2 kErfIntervals on [-kErfMax, kErfMax]
 // (mirrored form, coordinate offset by kErfIntervals, first entry constant)
-constexpr int kErfIntervals = 1024;
-constexpr float kErfMax = 4.0f;
+constexpr int kErfIntervals = 960;
+constexpr float kErfMax = 3.75f;
 
 /* Per-beamlet record, built in FP64 on the host (Fig. 1 geometry). */
 struct alignas(16) BeamletRec {
@@ -130,7 +131,7 @@ bool fill_mirrored_erf(const PlanDev &h);
 /* The erf mode of the plan's fill when it stages the mirrored table (1, 2 or 3). */
 int mirrored_erf_mode(const PlanDev &h);
 /* 1 when the mirrored erf table keeps the plan's fill at the same workgroups per CU as the
- * 8 KB table (occupancy query for the current device); 0 otherwise. */
+ * compact table (occupancy query for the current device); 0 otherwise. */
 int choose_erf_form(const PlanDev &h);
 
 /* Eq. 1 and its adjoint on a CSR. */

@@ -529,8 +529,8 @@ __device__ inline gptr<T> as_global(T *p)
  * (intercept c_k, slope s_k), so that erf ~ x s_k + c_k is one FMA of the
  * (clamped) argument and no fractional part is taken.
  *
- * Two forms: compact (8 KB, the intervals of [0, kErfMax]; odd symmetry gives
- * negative arguments) and mirrored (16 KB, the intervals of [-kErfMax,
+ * Two forms: compact (7.5 KB, the intervals of [0, kErfMax]; odd symmetry gives
+ * negative arguments) and mirrored (15 KB, the intervals of [-kErfMax,
  * kErfMax], arguments offset by kErfIntervals, read with their sign).  The
  * mirrored form's first interval is constant erf(-kErfMax) (slope 0), so an
  * argument below the table reads that entry through a saturating conversion

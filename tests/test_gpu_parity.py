@@ -125,7 +125,8 @@ def test_erf_table_forms(torch_gpu, oracle_lib, pdd_step):
         csr = plan.compute()
         r = compare_plan(ora, csr)
         lds = plan.desc.fill_lds_bytes
-        assert (lds >= 16384 + pairs) == (form == "mirrored"), (form, lds, pairs)
+        assert (lds >= 15360 + pairs) == (form == "mirrored"), (form, lds, pairs)   # 960 float2 per side
+        assert (plan.desc.fill_erf_mode >= 1) == (form == "mirrored")
         vals[form] = (csr.indices.clone(), csr.values.double().clone())
         _say(f"  {form}: lds={lds} nnz={csr.nnz} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e} "
              f"band={r['band_mismatches']}")
@@ -134,7 +135,7 @@ def test_erf_table_forms(torch_gpu, oracle_lib, pdd_step):
     assert float(((va - vb).abs() / va.abs().max()).max()) <= 1e-6
     auto = Plan(prob, "cuda:0")
     _say(f"  {len(k.pdd)} depth-dose nodes: plan creation chose the "
-         f"{'mirrored' if auto.desc.fill_lds_bytes >= 16384 + pairs else 'compact'} form")
+         f"{'mirrored' if auto.desc.fill_erf_mode >= 1 else 'compact'} form (mode {auto.desc.fill_erf_mode})")
 
 
 @pytest.mark.parametrize("form,mode", [("compact", 0), ("mirrored", 1)])
