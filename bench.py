@@ -61,6 +61,9 @@ def parse():
                     help="plans in flight: step k runs on stream k mod P with its own workspace and "
                          "outputs, so one plan's trace and count overlap another's fill")
     ap.add_argument("--no-eq1", action="store_true", help="skip the Eq. 1 (dose, gradient, transpose) timings")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the pelvis and 32-plan batch measurements beside the default workload "
+                         "(profiling runs of the headline plan)")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the trilinear-table, tabulated-kernel and chunked-computation timings")
     ap.add_argument("--table1", action="store_true",
@@ -651,7 +654,7 @@ def main():
         out["eq1"] = eq1_timings(csr[0], csr[1], csr[2], n_vox, n_rows)
     del csr
     torch.cuda.empty_cache()
-    if args.workload == 1:
+    if args.workload == 1 and not args.headline_only:
         # the other two workloads of the metric, measured by the same code
         pel, _, _ = plan_workload(2, args.steps, args.warmup, args.pipeline)
         pel.pop("wall_s")

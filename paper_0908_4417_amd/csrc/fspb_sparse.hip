@@ -6,12 +6,16 @@
  *     k_fluence_gradient  g_j = sum_i D_ij r_i, fixed order      -- one wave per row
  *   voxel-row CSR (row i = voxel, columns = beamlets): the transpose, a stable
  *   sort of the row-major entries by column
- *     k_key_count + scan                        voxel-row pointers
+ *     k_run_count         per row: runs (stretches within one 32-column bucket),
+ *                         the unsorted flag, entries per column as a difference
+ *                         array (two atomics per stretch of consecutive columns)
+ *     scans               entries per column, voxel-row pointers, run pointers
+ *     k_run_sizes         the path flag
  *     run path (the default for D, whose rows are long stretches of columns):
- *       k_run_count + scan, k_run_sizes        stretches of each row within one
- *                                              32-column bucket; the path flag
- *       k_run_emit, k_key_count + scan         run records, bucket pointers
+ *       k_run_emit                             run records
  *       k_rs_hist, scan, k_rs_scatter          stable LSD radix sort of the runs by bucket
+ *       k_bucket_bounds, k_run_gather          bucket pointers; each sorted run's
+ *                                              first entry and length
  *       k_bucket_place                         one wave per bucket places its runs'
  *                                              entries by a counting sort on the column
  *     entry path (short stretches):
@@ -271,19 +275,6 @@ __global__ __launch_bounds__(kBlock) void k_expand_rows(const int64_t *__restric
     for (int64_t e = e0 + lane_id(); e < e1; e += kWave) rows[e] = j;
 }
 
-/* counts[k] += 1 for every key k in [0, n_valid) among the first n keys; other keys are skipped. */
-__global__ __launch_bounds__(kBlock) void k_key_count(const int32_t *__restrict__ keys, Count n_keys, int n_valid,
-                                                      uint32_t *__restrict__ counts, Gate g)
-{
-    if (gate_closed(g)) return;
-    const int64_t n = count_of(n_keys);
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
-        const uint32_t i = (uint32_t)keys[e];
-        if (i < (uint32_t)n_valid) atomicAdd(counts + i, 1u);
-    }
-}
-
 /* Scan, phase 1: sum of each kScanChunk-value chunk (grid-stride over chunks). */
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ in, Count n_in,
                                                         uint32_t *__restrict__ partial, Gate g)
@@ -344,11 +335,11 @@ __global__ __launch_bounds__(kScanTop) void k_scan_top(uint32_t *__restrict__ pa
     }
 }
 
-/* Scan, phase 3: exclusive scan within each chunk plus its chunk offset (grid-stride). */
-template <typename OUT>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *__restrict__ in, Count n_in,
-                                                      const uint32_t *__restrict__ partial, OUT *__restrict__ out,
-                                                      Gate g)
+/* Scan, phase 3: exclusive (INCL: inclusive) scan within each chunk plus its chunk
+ * offset (grid-stride); out may be in (each chunk is read before it is written). */
+template <typename OUT, bool INCL>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, Count n_in, const uint32_t *__restrict__ partial,
+                                                      OUT *out, Gate g)
 {
     if (gate_closed(g)) return;
     __shared__ uint32_t s_w[kWavesPerBlock];
@@ -366,8 +357,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *__restrict
         uint32_t run = partial[c] + block_excl_scan(sum, s_w, &total);
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
+            run += INCL ? v[k] : 0u;
             if (base + k < n) out[base + k] = (OUT)run;
-            run += v[k];
+            run += INCL ? 0u : v[k];
         }
     }
 }
@@ -542,62 +534,91 @@ namespace {
 
 /*
  * Run transpose.  A run is a maximal stretch of consecutive entries of one row
- * whose columns share a bucket of kBucketCols columns (col >> kBucketShift;
- * a column outside [0, n_voxels) takes the sentinel bucket n_buckets).  The
- * transpose sorts the runs by bucket (stably, so a bucket's runs keep row
- * order), then one wave per bucket walks its runs' entries in that order and
- * places each with a stable counting sort on the column's low bits: the
- * output is the stable sort of the row-major entries by column, as the radix
- * path gives, for about two reads and one write of the matrix.  Buckets of 32
- * columns: with 128 the slab's transpose took 29 ms, with 32 20 ms, with 16 19 ms
- * (the pelvis 22, 14 and 17 ms; the radix path 30 and 18 ms); staging each batch
- * of runs in LDS brought the 32-column case to 12.6 ms (pelvis 11.9 ms).
+ * whose columns share a bucket of kBucketCols columns (col >> kBucketShift);
+ * entries whose column lies outside [0, n_voxels) form runs of their own,
+ * flagged (row id with its top bit set) and never placed.  The transpose sorts
+ * the runs by bucket (stably, so a bucket's runs keep row order), then one wave
+ * per bucket walks its runs' entries in that order and places each with a
+ * stable counting sort on the column's low bits: the output is the stable sort
+ * of the row-major entries by column, as the radix path gives, for about two
+ * reads and one write of the matrix.
  */
 constexpr int kBucketShift = 5;
 constexpr int kBucketCols = 1 << kBucketShift;
+constexpr uint32_t kRunFlag = 0x80000000u;   // run of invalid columns (in the run's row id)
+constexpr int kRowChunks = 4;                // chunks of 64 entries whose loads are in flight together
 
-__device__ inline int bucket_key(int col, int n_voxels, int n_buckets)
+/* Run key of a column: its bucket, or -2 (outside [0, n_voxels)); -1 marks "no entry before". */
+__device__ inline int run_key(int col, int n_voxels)
 {
-    return (uint32_t)col < (uint32_t)n_voxels ? (col >> kBucketShift) : n_buckets;
+    return (uint32_t)col < (uint32_t)n_voxels ? (col >> kBucketShift) : -2;
 }
 
-/* run_cnt[j] = runs of row j; one wave per row.  *unsorted is set when a row's
- * columns are not strictly ascending. */
+/*
+ * Per row (one wave, kRowChunks chunks of 64 entries loaded together): the
+ * number of runs (run_cnt[j]); *unsorted when the row's columns are not
+ * strictly ascending; and the row's entries per column as a difference array:
+ * every maximal stretch of entries with consecutive valid columns c .. c+m-1
+ * adds 1 at c and -1 at c+m (two atomics per stretch, where one per entry
+ * would be needed otherwise; a plan's D has stretches of tens of entries).
+ */
 __global__ __launch_bounds__(kBlock) void k_run_count(const int64_t *__restrict__ indptr,
                                                       const int32_t *__restrict__ indices, int n_rows, int n_voxels,
-                                                      int n_buckets, uint32_t *__restrict__ run_cnt,
-                                                      int32_t *__restrict__ unsorted)
+                                                      uint32_t *__restrict__ run_cnt, int32_t *__restrict__ unsorted,
+                                                      uint32_t *__restrict__ diff)
 {
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
     const int lane = lane_id();
     const int64_t e0 = indptr[j], e1 = indptr[j + 1];
     uint32_t runs = 0;
-    int prev_col = 0, prev_b = -1;                     // entry before the chunk (bucket -1: none)
+    int prev_col = 0, prev_k = -1;                     // entry before the chunk (key -1: none)
     bool down = false;
-    for (int64_t c = e0; c < e1; c += kWave) {
-        const int64_t e = c + lane;
-        const bool in = e < e1;
-        const int col = in ? indices[e] : 0;
-        const int b = bucket_key(col, n_voxels, n_buckets);
-        int cp = __shfl_up(col, 1, kWave), bp = __shfl_up(b, 1, kWave);
-        if (lane == 0) {
-            cp = prev_col;
-            bp = prev_b;
+    for (int64_t c = e0; c < e1; c += kRowChunks * kWave) {
+        int cols[kRowChunks];
+#pragma unroll
+        for (int u = 0; u < kRowChunks; ++u) {
+            const int64_t e = c + u * kWave + lane;
+            cols[u] = e < e1 ? indices[e] : 0;
         }
-        runs += (uint32_t)__popcll(__ballot(in && b != bp));
-        down = down || (in && bp >= 0 && col <= cp);
-        prev_col = __shfl(col, kWave - 1, kWave);
-        prev_b = __shfl(b, kWave - 1, kWave);
+        // first entry after this group (uniform address)
+        const int64_t en = c + kRowChunks * kWave;
+        const int after = en < e1 ? indices[en] : 0;
+#pragma unroll
+        for (int u = 0; u < kRowChunks; ++u) {
+            const int64_t e = c + u * kWave + lane;
+            const bool in = e < e1;
+            const int col = cols[u];
+            const int k = in ? run_key(col, n_voxels) : -3;
+            int cp = __shfl_up(col, 1, kWave), kp = __shfl_up(k, 1, kWave);
+            if (lane == 0) {
+                cp = prev_col;
+                kp = prev_k;
+            }
+            int cn = __shfl_down(col, 1, kWave), kn = __shfl_down(k, 1, kWave);
+            if (lane == kWave - 1) {
+                const int nx = u + 1 < kRowChunks ? __builtin_amdgcn_readlane(cols[u + 1 < kRowChunks ? u + 1 : u], 0)
+                                                  : after;
+                cn = nx;
+                kn = e + 1 < e1 ? run_key(nx, n_voxels) : -3;
+            }
+            runs += (uint32_t)__popcll(__ballot(in && k != kp));
+            down = down || (in && kp != -1 && col <= cp);
+            const bool valid = in && k >= 0;
+            if (valid && !(kp >= 0 && col == cp + 1)) atomicAdd(diff + col, 1u);
+            if (valid && !(kn >= 0 && cn == col + 1)) atomicAdd(diff + col + 1, 0xffffffffu);
+            prev_col = __shfl(col, kWave - 1, kWave);
+            prev_k = __shfl(k, kWave - 1, kWave);
+        }
     }
     if (lane == 0) run_cnt[j] = runs;
     if (__ballot(down) && lane == 0) *unsorted = 1;
 }
 
 /*
- * The path flag: the run transpose when the runs are at most half the entries
- * (a plan's D has tens of entries per run), else the radix sort of the
- * entries; and the length of the run sort's digit histograms.  One thread.
+ * The path flag: the run transpose when the runs are at most half the entries,
+ * else the radix sort of the entries; and the length of the run sort's digit
+ * histograms.  One thread.
  */
 __global__ void k_run_sizes(const int64_t *__restrict__ n_runs, int64_t nnz, int32_t *__restrict__ use_runs,
                             int64_t *__restrict__ hist_len)
@@ -607,12 +628,13 @@ __global__ void k_run_sizes(const int64_t *__restrict__ n_runs, int64_t nnz, int
     *hist_len = (int64_t)kRadix * ((R + kSortTile - 1) / kSortTile);
 }
 
-/* Records of every run (row-major run ids from run_ptr): its bucket, row, id
- * (as the value payload of the run sort) and first entry. */
+/* Records of every run (row-major run ids from run_ptr): its bucket (an invalid
+ * run takes the bucket of its column clamped into the grid), row (flagged when
+ * invalid), id (as the value payload of the run sort) and first entry. */
 __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__ indptr,
                                                      const int32_t *__restrict__ indices, int n_rows, int n_voxels,
-                                                     int n_buckets, const int64_t *__restrict__ run_ptr,
-                                                     uint32_t *__restrict__ run_key, int32_t *__restrict__ run_row,
+                                                     const int64_t *__restrict__ run_ptr,
+                                                     uint32_t *__restrict__ run_bucket, int32_t *__restrict__ run_row,
                                                      float *__restrict__ run_id, uint32_t *__restrict__ run_src,
                                                      Gate g)
 {
@@ -622,29 +644,79 @@ __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__
     const int lane = lane_id();
     const int64_t e0 = indptr[j], e1 = indptr[j + 1];
     uint32_t r = (uint32_t)run_ptr[j];
-    int prev_b = -1;                                   // bucket of the entry before the chunk
-    for (int64_t c = e0; c < e1; c += kWave) {
-        const int64_t e = c + lane;
-        const bool in = e < e1;
-        const int col = in ? indices[e] : 0;
-        const int b = bucket_key(col, n_voxels, n_buckets);
-        int bp = __shfl_up(b, 1, kWave);
-        if (lane == 0) bp = prev_b;
-        const bool start = in && b != bp;
-        const uint64_t m = __ballot(start);
-        if (start) {
-            const uint32_t id = r + (uint32_t)mbcnt64(m);
-            run_key[id] = (uint32_t)b;
-            run_row[id] = j;
-            run_id[id] = __uint_as_float(id);
-            run_src[id] = (uint32_t)e;
+    int prev_k = -1;                                   // run key of the entry before the chunk
+    for (int64_t c = e0; c < e1; c += kRowChunks * kWave) {
+        int cols[kRowChunks];
+#pragma unroll
+        for (int u = 0; u < kRowChunks; ++u) {
+            const int64_t e = c + u * kWave + lane;
+            cols[u] = e < e1 ? indices[e] : 0;
         }
-        r += (uint32_t)__popcll(m);
-        prev_b = __shfl(b, kWave - 1, kWave);
+#pragma unroll
+        for (int u = 0; u < kRowChunks; ++u) {
+            const int64_t e = c + u * kWave + lane;
+            const bool in = e < e1;
+            const int col = cols[u];
+            const int k = in ? run_key(col, n_voxels) : -3;
+            int kp = __shfl_up(k, 1, kWave);
+            if (lane == 0) kp = prev_k;
+            const bool start = in && k != kp;
+            const uint64_t m = __ballot(start);
+            if (start) {
+                const uint32_t id = r + (uint32_t)mbcnt64(m);
+                const int clamped = col < 0 ? 0 : (col >= n_voxels ? n_voxels - 1 : col);
+                run_bucket[id] = (uint32_t)(clamped >> kBucketShift);
+                run_row[id] = k >= 0 ? j : (int32_t)((uint32_t)j | kRunFlag);
+                run_id[id] = __uint_as_float(id);
+                run_src[id] = (uint32_t)e;
+            }
+            r += (uint32_t)__popcll(m);
+            prev_k = __shfl(k, kWave - 1, kWave);
+        }
+    }
+}
+
+/* Bucket pointers from the sorted bucket keys: b_ptr[b] = first run of bucket b
+ * (b_ptr[n_buckets] = R).  Keys ascend, so each b is written once. */
+__global__ __launch_bounds__(kBlock) void k_bucket_bounds(const uint32_t *__restrict__ keys, Count n_runs,
+                                                          int n_buckets, int64_t *__restrict__ b_ptr, Gate g)
+{
+    if (gate_closed(g)) return;
+    const int64_t R = count_of(n_runs);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q <= R; q += stride) {
+        const int64_t kq = q < R ? (int64_t)keys[q] : n_buckets;
+        const int64_t kp = q > 0 ? (int64_t)keys[q - 1] : -1;
+        for (int64_t b = kp + 1; b <= kq; ++b) b_ptr[b] = q;
+    }
+}
+
+/* Sorted run q: its first entry and length (0 for an invalid run), and its row
+ * without the flag; the length runs to the next run of the row or the row's end. */
+__global__ __launch_bounds__(kBlock) void k_run_gather(const float *__restrict__ b_ids, int32_t *__restrict__ b_rows,
+                                                       const uint32_t *__restrict__ run_src,
+                                                       const int64_t *__restrict__ run_ptr,
+                                                       const int64_t *__restrict__ indptr, Count n_runs,
+                                                       uint32_t *__restrict__ b_src, uint32_t *__restrict__ b_len,
+                                                       Gate g)
+{
+    if (gate_closed(g)) return;
+    const int64_t R = count_of(n_runs);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < R; q += stride) {
+        const uint32_t id = __float_as_uint(b_ids[q]);
+        const uint32_t rw = (uint32_t)b_rows[q];
+        const int row = (int)(rw & ~kRunFlag);
+        const uint32_t src = run_src[id];
+        const uint32_t end = (int64_t)id + 1 < run_ptr[row + 1] ? run_src[id + 1] : (uint32_t)indptr[row + 1];
+        b_src[q] = src;
+        b_len[q] = (rw & kRunFlag) ? 0u : end - src;
+        b_rows[q] = row;
     }
 }
 
 constexpr int kColWaves = 2;                               // waves per workgroup of k_bucket_place
+constexpr int kStageUnroll = 8;                            // staging chunks whose loads are in flight together
 
 /* The runs of bucket b, taken 64 at a time: lane i holds run q0 + i (its row,
  * first entry and length), with the batch's exclusive prefix of lengths. */
@@ -653,9 +725,8 @@ struct RunBatch {
     uint32_t src, len, excl, total;
 };
 
-__device__ inline RunBatch load_runs(int64_t qb, int64_t q1, const int64_t *__restrict__ indptr,
-                                     const int64_t *__restrict__ run_ptr, const uint32_t *__restrict__ run_src,
-                                     const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+__device__ inline RunBatch load_runs(int64_t qb, int64_t q1, const int32_t *__restrict__ b_rows,
+                                     const uint32_t *__restrict__ b_src, const uint32_t *__restrict__ b_len,
                                      uint32_t max_len)
 {
     const int lane = lane_id();
@@ -663,10 +734,8 @@ __device__ inline RunBatch load_runs(int64_t qb, int64_t q1, const int64_t *__re
     RunBatch B{0, 0u, 0u, 0u, 0u};
     if (q < q1) {
         B.row = b_rows[q];
-        const uint32_t id = __float_as_uint(b_ids[q]);
-        B.src = run_src[id];
-        const uint32_t end = (int64_t)id + 1 < run_ptr[B.row + 1] ? run_src[id + 1] : (uint32_t)indptr[B.row + 1];
-        B.len = min(end - B.src, max_len);
+        B.src = b_src[q];
+        B.len = min(b_len[q], max_len);
     }
     uint32_t incl = B.len;
 #pragma unroll
@@ -698,15 +767,14 @@ __device__ inline int run_of(const RunBatch &B, uint32_t c0, int &rcur)
  * Placement for rows with strictly ascending columns, column by column.  A
  * batch of 64 runs of the bucket (rows ascending; each at most 32 entries,
  * one per column) is first copied into LDS, the runs' entries flattened over
- * the lanes so that all loads are independent; then each lane holds one run
- * and, at column c, the lanes whose next entry has column c write it, ranked
- * by lane, so each column's entries from the batch go out as one contiguous
- * stretch.
+ * the lanes, kStageUnroll chunks of 64 at a time with all their loads issued
+ * together; then each lane holds one run and, at column c, the lanes whose
+ * next entry has column c write it, ranked by lane, so each column's entries
+ * from the batch go out as one contiguous stretch.
  */
-__device__ void place_columns(int b, int wave, const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices,
-                              const float *__restrict__ values, int n_voxels, const int64_t *__restrict__ run_ptr,
-                              const uint32_t *__restrict__ run_src, const int64_t *__restrict__ b_ptr,
-                              const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+__device__ void place_columns(int b, int wave, const int32_t *__restrict__ indices, const float *__restrict__ values,
+                              int n_voxels, const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows,
+                              const uint32_t *__restrict__ b_src, const uint32_t *__restrict__ b_len,
                               const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
                               float *__restrict__ t_values)
 {
@@ -725,17 +793,36 @@ __device__ void place_columns(int b, int wave, const int64_t *__restrict__ indpt
     const int col0 = b << kBucketShift;
     const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1];
     for (int64_t qb = q0; qb < q1; qb += kWave) {
-        const RunBatch B = load_runs(qb, q1, indptr, run_ptr, run_src, b_rows, b_ids, kBucketCols);
+        const RunBatch B = load_runs(qb, q1, b_rows, b_src, b_len, kBucketCols);
         // stage: entry p of the batch -> LDS
         int rcur = 0;
-        for (uint32_t c0 = 0; c0 < B.total; c0 += kWave) {
-            const uint32_t p = c0 + lane;
-            const int rr = run_of(B, c0, rcur);
-            // shuffles on every lane: the source lane rr may be past the end of the batch's entries
-            const uint32_t e = __shfl(B.src, rr, kWave) + (p - __shfl(B.excl, rr, kWave));
-            if (p < B.total) {
-                sc[p] = (uint8_t)(indices[e] - col0);
-                sv[p] = values[e];
+        for (uint32_t g0 = 0; g0 < B.total; g0 += kStageUnroll * kWave) {
+            uint32_t e[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const uint32_t c0 = g0 + u * kWave;
+                e[u] = 0u;
+                if (c0 < B.total) {
+                    const int rr = run_of(B, c0, rcur);
+                    // shuffles on every lane: the source lane rr may be past the end of the batch's entries
+                    e[u] = __shfl(B.src, rr, kWave) + (c0 + lane - __shfl(B.excl, rr, kWave));
+                }
+            }
+            int cols[kStageUnroll];
+            float vals[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const bool in = g0 + u * kWave + lane < B.total;
+                cols[u] = in ? indices[e[u]] : col0;
+                vals[u] = in ? values[e[u]] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const uint32_t p = g0 + u * kWave + lane;
+                if (p < B.total) {
+                    sc[p] = (uint8_t)(cols[u] - col0);
+                    sv[p] = vals[u];
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -772,10 +859,9 @@ __device__ void place_columns(int b, int wave, const int64_t *__restrict__ indpt
  * counted per column in LDS.  Equal columns within a 64-entry chunk are
  * ranked by lane with five ballots over the column's low bits.
  */
-__device__ void place_any(int b, int wave, const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices,
-                          const float *__restrict__ values, int n_voxels, const int64_t *__restrict__ run_ptr,
-                          const uint32_t *__restrict__ run_src, const int64_t *__restrict__ b_ptr,
-                          const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
+__device__ void place_any(int b, int wave, const int32_t *__restrict__ indices, const float *__restrict__ values,
+                          int n_voxels, const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows,
+                          const uint32_t *__restrict__ b_src, const uint32_t *__restrict__ b_len,
                           const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
                           float *__restrict__ t_values)
 {
@@ -792,7 +878,7 @@ __device__ void place_any(int b, int wave, const int64_t *__restrict__ indptr, c
     const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes under this one
     for (int64_t qb = q0; qb < q1; qb += kWave) {
-        const RunBatch B = load_runs(qb, q1, indptr, run_ptr, run_src, b_rows, b_ids, 0xffffffffu);
+        const RunBatch B = load_runs(qb, q1, b_rows, b_src, b_len, 0xffffffffu);
         int rcur = 0;
         for (uint32_t c0 = 0; c0 < B.total; c0 += kWave) {
             const uint32_t p = c0 + lane;
@@ -824,31 +910,29 @@ __device__ void place_any(int b, int wave, const int64_t *__restrict__ indptr, c
     }
 }
 
-/* One wave per bucket of columns (buckets below n_buckets; the sentinel
- * bucket of invalid columns is not placed). */
+/* One wave per bucket of columns. */
 __global__ __launch_bounds__(kColWaves * kWave) void k_bucket_place(
-    const int64_t *__restrict__ indptr, const int32_t *__restrict__ indices, const float *__restrict__ values,
-    int n_voxels, int n_buckets, const int64_t *__restrict__ run_ptr, const uint32_t *__restrict__ run_src,
-    const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows, const float *__restrict__ b_ids,
-    const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
-    float *__restrict__ t_values, const int32_t *__restrict__ unsorted, Gate g)
+    const int32_t *__restrict__ indices, const float *__restrict__ values, int n_voxels, int n_buckets,
+    const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows, const uint32_t *__restrict__ b_src,
+    const uint32_t *__restrict__ b_len, const int64_t *__restrict__ t_indptr, uint32_t nnz,
+    int32_t *__restrict__ t_indices, float *__restrict__ t_values, const int32_t *__restrict__ unsorted, Gate g)
 {
     if (gate_closed(g)) return;
     const int wave = threadIdx.x >> 6;
     const int b = blockIdx.x * kColWaves + wave;
     if (b >= n_buckets) return;
     if (*unsorted)
-        place_any(b, wave, indptr, indices, values, n_voxels, run_ptr, run_src, b_ptr, b_rows, b_ids, t_indptr, nnz,
-                  t_indices, t_values);
+        place_any(b, wave, indices, values, n_voxels, b_ptr, b_rows, b_src, b_len, t_indptr, nnz, t_indices,
+                  t_values);
     else
-        place_columns(b, wave, indptr, indices, values, n_voxels, run_ptr, run_src, b_ptr, b_rows, b_ids, t_indptr,
-                      nnz, t_indices, t_values);
+        place_columns(b, wave, indices, values, n_voxels, b_ptr, b_rows, b_src, b_len, t_indptr, nnz, t_indices,
+                      t_values);
 }
 
 }  // namespace
 
 struct TransposeLayout {
-    size_t key[2], row[2], val[2], hist, offs, partial, counts, bcnt, bptr, scal, run_cnt, run_ptr, total;
+    size_t key[2], row[2], val[2], hist, offs, partial, counts, bptr, scal, run_cnt, run_ptr, total;
 };
 
 static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
@@ -874,9 +958,8 @@ static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
     L.hist = take(sizeof(uint32_t) * (size_t)n_hist);
     L.offs = take(sizeof(uint32_t) * (size_t)n_hist);
     L.partial = take(sizeof(uint32_t) * (size_t)((n_scan + kScanChunk - 1) / kScanChunk + 1));
-    L.counts = take(sizeof(uint32_t) * (size_t)n_voxels);
-    L.bcnt = take(sizeof(uint32_t) * (size_t)(nb + 1));     // buckets and the sentinel
-    L.bptr = take(sizeof(int64_t) * (size_t)(nb + 2));
+    L.counts = take(sizeof(uint32_t) * ((size_t)n_voxels + 1));   // difference array, then counts
+    L.bptr = take(sizeof(int64_t) * (size_t)(nb + 1));
     L.scal = take(64);   // unsorted-rows flag, path flag, run histogram length
     L.run_cnt = take(sizeof(uint32_t) * (size_t)(n_rows > 0 ? n_rows : 1));
     L.run_ptr = take(sizeof(int64_t) * ((size_t)n_rows + 1));
@@ -903,17 +986,18 @@ static unsigned stride_grid(int64_t items)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, 4096));
 }
 
-/* Exclusive scan of n uint32 values in -> out (OUT = uint32_t or int64_t); n is a
- * host count or, with n.dev, a device count at most n_max.  partial[nblocks]
- * receives the total, and *total64 too when given. */
-template <typename OUT>
+/* Exclusive (inclusive with INCL) scan of n uint32 values in -> out (OUT =
+ * uint32_t or int64_t; out may be in); n is a host count or, with n.dev, a
+ * device count at most n_max.  partial[nblocks] receives the total, and
+ * *total64 too when given. */
+template <typename OUT, bool INCL = false>
 static hipError_t scan_excl(const uint32_t *in, Count n, int64_t n_max, uint32_t *partial, OUT *out,
                             int64_t *total64, Gate g, hipStream_t s)
 {
     const unsigned nb = stride_grid((n_max + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, partial, g);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, partial, n, total64, g);
-    hipLaunchKernelGGL((k_scan_down<OUT>), dim3(nb), dim3(kBlock), 0, s, in, n, partial, out, g);
+    hipLaunchKernelGGL((k_scan_down<OUT, INCL>), dim3(nb), dim3(kBlock), 0, s, in, n, partial, out, g);
     return hipGetLastError();
 }
 
@@ -921,13 +1005,15 @@ static hipError_t scan_excl(const uint32_t *in, Count n, int64_t n_max, uint32_t
  * One stable LSD radix sort of (key, row, value) triples by key: `passes`
  * passes of 8 bits, keys above clamp sorted as clamp, ping-pong through
  * (k1, r1, v1) and (k0, r0, v0) (the input may be separate), the last pass
- * writing rows and values to (rows_out, vals_out).  n is a host or device
- * count, at most n_max.
+ * writing rows and values to (rows_out, vals_out), and with keys_out its keys
+ * to the pass's own key buffer (*keys_out = that buffer).  n is a host or
+ * device count, at most n_max.
  */
 static hipError_t radix_sort(const uint32_t *keys, const int32_t *rows, const float *vals, Count n, int64_t n_max,
                              uint32_t clamp, int passes, uint32_t *k0, int32_t *r0, float *v0, uint32_t *k1,
-                             int32_t *r1, float *v1, int32_t *rows_out, float *vals_out, uint32_t *hist,
-                             uint32_t *offs, uint32_t *partial, int64_t *hist_len_dev, Gate g, hipStream_t s)
+                             int32_t *r1, float *v1, int32_t *rows_out, float *vals_out, uint32_t **keys_out,
+                             uint32_t *hist, uint32_t *offs, uint32_t *partial, int64_t *hist_len_dev, Gate g,
+                             hipStream_t s)
 {
     const int64_t tiles_max = (n_max + kSortTile - 1) / kSortTile;
     const unsigned grid = stride_grid(tiles_max);
@@ -939,7 +1025,8 @@ static hipError_t radix_sort(const uint32_t *keys, const int32_t *rows, const fl
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
         const bool last = p == passes - 1;
-        uint32_t *kout = last ? nullptr : ((p & 1) ? k0 : k1);
+        uint32_t *kbuf = (p & 1) ? k0 : k1;
+        uint32_t *kout = last ? (keys_out ? kbuf : nullptr) : kbuf;
         int32_t *rout = last ? rows_out : ((p & 1) ? r0 : r1);
         float *vout = last ? vals_out : ((p & 1) ? v0 : v1);
         hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(kBlock), 0, s, kin, n, clamp, shift, hist, g);
@@ -949,6 +1036,7 @@ static hipError_t radix_sort(const uint32_t *keys, const int32_t *rows, const fl
         hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(kBlock), 0, s, kin, rin, vin, n, clamp, shift, offs, kout,
                            rout, vout, g);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (last && keys_out) *keys_out = kout;
         kin = kout;
         rin = rout;
         vin = vout;
@@ -972,26 +1060,28 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
     int32_t *unsorted = reinterpret_cast<int32_t *>(ws + L.scal);
     int32_t *use_runs = unsorted + 1;
     int64_t *hist_len = reinterpret_cast<int64_t *>(ws + L.scal + 8);
+    uint32_t *run_cnt = reinterpret_cast<uint32_t *>(ws + L.run_cnt);
+    int64_t *run_ptr = reinterpret_cast<int64_t *>(ws + L.run_ptr);
     const Gate always{nullptr, 0};
     hipError_t e;
 
-    // voxel-row pointers: valid entries per voxel, exclusive scan, total at t_indptr[n_voxels]
-    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of(n_voxels, kBlock)), dim3(kBlock), 0, s, counts, (int64_t)n_voxels);
-    if (nnz > 0)
-        hipLaunchKernelGGL(k_key_count, dim3(stride_grid(blocks_of(nnz, kBlock))), dim3(kBlock), 0, s, indices,
-                           Count{nnz, nullptr}, n_voxels, counts, always);
+    // runs of every row, the unsorted flag and the entries per column as a difference
+    // array; then entries per column (inclusive scan) and the voxel-row pointers
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of((int64_t)n_voxels + 1, kBlock)), dim3(kBlock), 0, s, counts,
+                       (int64_t)n_voxels + 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(unsorted), (int64_t)1);
+    if (nnz > 0 && n_rows > 0)
+        hipLaunchKernelGGL(k_run_count, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
+                           n_rows, n_voxels, run_cnt, unsorted, counts);
+    if ((e = scan_excl<uint32_t, true>(counts, Count{n_voxels, nullptr}, n_voxels, partial, counts, nullptr, always,
+                                       s)) != hipSuccess)
+        return e;
     if ((e = scan_excl<int64_t>(counts, Count{n_voxels, nullptr}, n_voxels, partial, t_indptr, t_indptr + n_voxels,
                                 always, s)) != hipSuccess)
         return e;
     if (nnz == 0 || n_rows == 0) return hipSuccess;
 
-    // runs (stretches of a row within one bucket of columns) and the path flag
     const int nb = (n_voxels + kBucketCols - 1) >> kBucketShift;
-    uint32_t *run_cnt = reinterpret_cast<uint32_t *>(ws + L.run_cnt);
-    int64_t *run_ptr = reinterpret_cast<int64_t *>(ws + L.run_ptr);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(unsorted), (int64_t)1);
-    hipLaunchKernelGGL(k_run_count, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
-                       n_rows, n_voxels, nb, run_cnt, unsorted);
     if ((e = scan_excl<int64_t>(run_cnt, Count{n_rows, nullptr}, n_rows, partial, run_ptr, run_ptr + n_rows, always,
                                 s)) != hipSuccess)
         return e;
@@ -999,8 +1089,9 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
     const Gate runs{use_runs, 1}, entries{use_runs, 0};
 
     // run path: at most nnz / 2 runs.  Run records in the first half of key[0], row[0],
-    // val[0]; first entries and the sorted runs from `half` on; the sort's other buffers
-    // are key/row/val[1]
+    // val[0]; first entries and the sorted rows and ids from `half` on; the sort's other
+    // buffers are key/row/val[1]; after the sort, each run's first entry and length go to
+    // row[1] and val[1] (free then: the sorted keys are in key[0] or key[1])
     {
         const int64_t half = (nnz + 1) / 2;
         uint32_t *rkey = key[0];
@@ -1009,25 +1100,25 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
         uint32_t *rsrc = key[0] + half;
         int32_t *brow = row[0] + half;
         float *bid = val[0] + half;
-        uint32_t *bcnt = reinterpret_cast<uint32_t *>(ws + L.bcnt);
+        uint32_t *bsrc = reinterpret_cast<uint32_t *>(row[1]);
+        uint32_t *blen = reinterpret_cast<uint32_t *>(val[1]);
         int64_t *bptr = reinterpret_cast<int64_t *>(ws + L.bptr);
         const Count n_runs{0, run_ptr + n_rows};
         hipLaunchKernelGGL(k_run_emit, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
-                           n_rows, n_voxels, nb, run_ptr, rkey, rrow, rid, rsrc, runs);
-        hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of(nb + 1, kBlock)), dim3(kBlock), 0, s, bcnt, (int64_t)(nb + 1));
-        hipLaunchKernelGGL(k_key_count, dim3(stride_grid(blocks_of(half, kBlock))), dim3(kBlock), 0, s,
-                           reinterpret_cast<const int32_t *>(rkey), n_runs, nb + 1, bcnt, runs);
-        if ((e = scan_excl<int64_t>(bcnt, Count{nb + 1, nullptr}, nb + 1, partial, bptr, bptr + nb + 1, runs, s)) !=
+                           n_rows, n_voxels, run_ptr, rkey, rrow, rid, rsrc, runs);
+        // stable sort of the runs by bucket
+        uint32_t *skeys = nullptr;
+        if ((e = radix_sort(rkey, rrow, rid, n_runs, half, 0xffffffffu, transpose_passes(nb), key[0], row[0], val[0],
+                            key[1], row[1], val[1], brow, bid, &skeys, hist, offs, partial, hist_len, runs, s)) !=
             hipSuccess)
             return e;
-        // stable sort of the runs by bucket (the sentinel bucket last)
-        if ((e = radix_sort(rkey, rrow, rid, n_runs, half, (uint32_t)nb, transpose_passes(nb + 1), key[0], row[0],
-                            val[0], key[1], row[1], val[1], brow, bid, hist, offs, partial, hist_len, runs, s)) !=
-            hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_bucket_place, dim3(blocks_of(nb, kColWaves)), dim3(kColWaves * kWave), 0, s, indptr,
-                           indices, values, n_voxels, nb, run_ptr, rsrc, bptr, brow, bid, t_indptr, (uint32_t)nnz,
-                           t_indices, t_values, unsorted, runs);
+        hipLaunchKernelGGL(k_bucket_bounds, dim3(stride_grid(blocks_of(half + 1, kBlock))), dim3(kBlock), 0, s, skeys,
+                           n_runs, nb, bptr, runs);
+        hipLaunchKernelGGL(k_run_gather, dim3(stride_grid(blocks_of(half, kBlock))), dim3(kBlock), 0, s, bid, brow,
+                           rsrc, run_ptr, indptr, n_runs, bsrc, blen, runs);
+        hipLaunchKernelGGL(k_bucket_place, dim3(blocks_of(nb, kColWaves)), dim3(kColWaves * kWave), 0, s, indices,
+                           values, n_voxels, nb, bptr, brow, bsrc, blen, t_indptr, (uint32_t)nnz, t_indices, t_values,
+                           unsorted, runs);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
 
@@ -1037,7 +1128,7 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
                        row[0], entries);
     return radix_sort(reinterpret_cast<const uint32_t *>(indices), row[0], values, Count{nnz, nullptr}, nnz,
                       (uint32_t)n_voxels, transpose_passes(n_voxels + 1), key[0], row[0], val[0], key[1], row[1],
-                      val[1], t_indices, t_values, hist, offs, partial, nullptr, entries, s);
+                      val[1], t_indices, t_values, nullptr, hist, offs, partial, nullptr, entries, s);
 }
 
 /*
