@@ -6,20 +6,20 @@
  *     k_fluence_gradient  g_j = sum_i D_ij r_i, fixed order      -- one wave per row
  *   voxel-row CSR (row i = voxel, columns = beamlets): the transpose, a stable
  *   sort of the row-major entries by column
- *     k_run_count         per row: runs (stretches within one 32-column bucket),
- *                         the unsorted flag, entries per column as a difference
- *                         array (two atomics per stretch of consecutive columns)
- *     scans               entries per column, voxel-row pointers, run pointers
- *     k_run_sizes         the path flag
+ *     k_run_count, scan, k_run_sizes   runs of each row (stretches within one
+ *                                      32-column bucket), their pointers, the
+ *                                      path flags
  *     run path (the default for D, whose rows are long stretches of columns):
- *       k_run_emit                             run records
- *       k_rs_hist, scan, k_rs_scatter          stable LSD radix sort of the runs by bucket
- *       k_bucket_bounds, k_run_gather          bucket pointers; each sorted run's
- *                                              first entry and length
- *       k_bucket_place                         one wave per bucket places its runs'
- *                                              entries by a counting sort on the column
- *     entry path (short stretches):
- *       k_expand_rows, then k_rs_hist, scan, k_rs_scatter per 8 bits of the column
+ *       k_run_emit                     run records: bucket, row, first entry and a
+ *                                      32-bit column mask (ascending rows) or length
+ *       k_rs_hist, scan, k_rs_scatter  stable LSD radix sort of the runs by bucket
+ *       k_bucket_bounds                bucket pointers
+ *       rows ascending:   scan of the lengths, k_place_sorted -- one wave per
+ *                         bucket: column counts from the masks (the voxel-row
+ *                         pointers), batches reordered in LDS and written out
+ *       rows in any order: k_key_count + scan (pointers), k_place_any
+ *     entry path (short stretches): k_key_count + scan, k_expand_rows, then
+ *       k_rs_hist, scan, k_rs_scatter per 8 bits of the column
  *     k_voxel_dose        dose_i = sum_j D_ij w_j, fixed order  -- 16 lanes per voxel row
  *
  * Both sorts are stable and the input rows are in ascending beamlet order, so
@@ -275,7 +275,9 @@ __global__ __launch_bounds__(kBlock) void k_expand_rows(const int64_t *__restric
     for (int64_t e = e0 + lane_id(); e < e1; e += kWave) rows[e] = j;
 }
 
-/* Scan, phase 1: sum of each kScanChunk-value chunk (grid-stride over chunks). */
+/* Scan, phase 1: sum of each kScanChunk-value chunk (grid-stride over chunks); with
+ * POPC the values scanned are the popcounts of the inputs (here and in phase 3). */
+template <bool POPC>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ in, Count n_in,
                                                         uint32_t *__restrict__ partial, Gate g)
 {
@@ -286,7 +288,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restri
         const int64_t base = c * kScanChunk + (int64_t)threadIdx.x * kScanItems;
         uint32_t v = 0;
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) v += base + k < n ? in[base + k] : 0u;
+        for (int k = 0; k < kScanItems; ++k) {
+            const uint32_t x = base + k < n ? in[base + k] : 0u;
+            v += POPC ? (uint32_t)__popc(x) : x;
+        }
         v = wave_sum(v);
         if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
         __syncthreads();
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(kScanTop) void k_scan_top(uint32_t *__restrict__ pa
 
 /* Scan, phase 3: exclusive (INCL: inclusive) scan within each chunk plus its chunk
  * offset (grid-stride); out may be in (each chunk is read before it is written). */
-template <typename OUT, bool INCL>
+template <typename OUT, bool INCL, bool POPC>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, Count n_in, const uint32_t *__restrict__ partial,
                                                       OUT *out, Gate g)
 {
@@ -351,6 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, Count 
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             v[k] = base + k < n ? in[base + k] : 0u;
+            if (POPC) v[k] = (uint32_t)__popc(v[k]);
             sum += v[k];
         }
         uint32_t total;
@@ -390,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *__restrict__
 }
 
 /*
- * Radix pass, phase 2: stable scatter.  Wave w of a block owns the w-th
+ * Radix pass, phase 2: stable scatter (of a fourth uint32 payload too with XTRA).  Wave w of a block owns the w-th
  * quarter of the tile (kSortItems rounds of 64 consecutive entries) and
  * ranks it on its own: in a round, ballots on the 8 digit bits group the
  * lanes holding the same digit, a lane's rank is the number of lower peers,
@@ -401,18 +407,22 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *__restrict__
  * order, so each digit's run goes to consecutive addresses.  keys_out may be
  * NULL (last pass).  Grid-stride over the tiles.
  */
+template <bool XTRA>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restrict__ keys_in,
                                                        const int32_t *__restrict__ rows_in,
-                                                       const float *__restrict__ vals_in, Count n_in, uint32_t clamp,
+                                                       const float *__restrict__ vals_in,
+                                                       const uint32_t *__restrict__ xs_in, Count n_in, uint32_t clamp,
                                                        int shift, const uint32_t *__restrict__ offs,
                                                        uint32_t *__restrict__ keys_out,
                                                        int32_t *__restrict__ rows_out,
-                                                       float *__restrict__ vals_out, Gate g)
+                                                       float *__restrict__ vals_out, uint32_t *__restrict__ xs_out,
+                                                       Gate g)
 {
     if (gate_closed(g)) return;
     __shared__ uint32_t s_key[kSortTile];
     __shared__ int32_t s_row[kSortTile];
     __shared__ float s_val[kSortTile];
+    __shared__ uint32_t s_x[XTRA ? kSortTile : 1];
     __shared__ uint32_t cnt[kWavesPerBlock][kRadix];   // per wave: digit counts, then first tile-local slot
     __shared__ uint32_t goff[kRadix];                  // global slot of tile-local slot 0 of each digit's run
     __shared__ uint32_t s_w[kWavesPerBlock];
@@ -426,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
         for (int w = 0; w < kWavesPerBlock; ++w) cnt[w][t] = 0u;
         __syncthreads();
 
-        uint32_t key[kSortItems], pos[kSortItems];
+        uint32_t key[kSortItems], pos[kSortItems], xv[kSortItems];
         int32_t row[kSortItems];
         float val[kSortItems];
 #pragma unroll
@@ -436,6 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
             key[r] = valid ? min(keys_in[i], clamp) : 0u;
             row[r] = valid ? rows_in[i] : 0;
             val[r] = valid ? vals_in[i] : 0.0f;
+            xv[r] = (XTRA && valid) ? xs_in[i] : 0u;
             const uint32_t d = (key[r] >> shift) & (kRadix - 1);
             uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -478,6 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
                 s_key[lp] = key[r];
                 s_row[lp] = row[r];
                 s_val[lp] = val[r];
+                if (XTRA) s_x[lp] = xv[r];
             }
         }
         __syncthreads();
@@ -489,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *__restric
             if (keys_out) keys_out[p] = key_;
             rows_out[p] = s_row[lp];
             vals_out[p] = s_val[lp];
+            if (XTRA) xs_out[p] = s_x[lp];
         }
         __syncthreads();
     }
@@ -529,43 +542,67 @@ hipError_t launch_voxel_dose(const int64_t *t_indptr, const int32_t *t_indices, 
     return hipGetLastError();
 }
 
-/* Workspace layout of the transpose (offsets from a 256-byte aligned base). */
 namespace {
 
 /*
  * Run transpose.  A run is a maximal stretch of consecutive entries of one row
  * whose columns share a bucket of kBucketCols columns (col >> kBucketShift);
  * entries whose column lies outside [0, n_voxels) form runs of their own,
- * flagged (row id with its top bit set) and never placed.  The transpose sorts
- * the runs by bucket (stably, so a bucket's runs keep row order), then one wave
- * per bucket walks its runs' entries in that order and places each with a
+ * flagged (row id with its top bit set) and never placed.  The runs are
+ * sorted by bucket (stably, so a bucket's runs keep row order) and the
+ * entries of each bucket are then placed by one wave, in that order, with a
  * stable counting sort on the column's low bits: the output is the stable sort
- * of the row-major entries by column, as the radix path gives, for about two
- * reads and one write of the matrix.
+ * of the row-major entries by column, as the radix path gives.
+ *
+ * When every row's columns ascend strictly (a plan's D) a run holds at most
+ * one entry per column of its bucket, so a 32-bit mask of its columns
+ * describes it: its length is the mask's popcount, its k-th entry lies in the
+ * column of the mask's k-th set bit, and the entries of a bucket that fall in
+ * column c are counted by popcounts of masks.  The placement then reads only
+ * the values, and the voxel-row pointers come from the bucket counts.
  */
 constexpr int kBucketShift = 5;
 constexpr int kBucketCols = 1 << kBucketShift;
 constexpr uint32_t kRunFlag = 0x80000000u;   // run of invalid columns (in the run's row id)
 constexpr int kRowChunks = 4;                // chunks of 64 entries whose loads are in flight together
+constexpr int kXcds = 8;                     // workgroups are handed to the 8 XCDs in turn
 
-/* Run key of a column: its bucket, or -2 (outside [0, n_voxels)); -1 marks "no entry before". */
+/* Run key of a column: its bucket, or -2 (outside [0, n_voxels)). */
 __device__ inline int run_key(int col, int n_voxels)
 {
     return (uint32_t)col < (uint32_t)n_voxels ? (col >> kBucketShift) : -2;
 }
 
-/*
- * Per row (one wave, kRowChunks chunks of 64 entries loaded together): the
- * number of runs (run_cnt[j]); *unsorted when the row's columns are not
- * strictly ascending; and the row's entries per column as a difference array:
- * every maximal stretch of entries with consecutive valid columns c .. c+m-1
- * adds 1 at c and -1 at c+m (two atomics per stretch, where one per entry
- * would be needed otherwise; a plan's D has stretches of tens of entries).
- */
+/* Flags the transpose computes on the device (one 64-byte slot of the workspace). */
+struct Flags {
+    int32_t unsorted;      // some row's columns do not ascend strictly
+    int32_t use_runs;      // runs are at most half the entries: a run path
+    int64_t hist_len;      // digit-histogram length of the run sort
+    int32_t need_counts;   // entries per column counted by atomics (entry path, unsorted rows)
+    int32_t sorted;        // run path with masks (rows ascending)
+    int32_t any;           // run path for rows in any column order
+    int32_t pad;
+    int64_t total;         // placed entries (sorted run path)
+};
+
+/* counts[k] += 1 for every key k in [0, n_valid) among the first n keys; other keys are skipped. */
+__global__ __launch_bounds__(kBlock) void k_key_count(const int32_t *__restrict__ keys, int64_t n, int n_valid,
+                                                      uint32_t *__restrict__ counts, Gate g)
+{
+    if (gate_closed(g)) return;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
+        const uint32_t i = (uint32_t)keys[e];
+        if (i < (uint32_t)n_valid) atomicAdd(counts + i, 1u);
+    }
+}
+
+/* Per row (one wave, kRowChunks chunks of 64 entries loaded together): the
+ * number of runs (run_cnt[j]), and the unsorted flag when the row's columns do
+ * not ascend strictly. */
 __global__ __launch_bounds__(kBlock) void k_run_count(const int64_t *__restrict__ indptr,
                                                       const int32_t *__restrict__ indices, int n_rows, int n_voxels,
-                                                      uint32_t *__restrict__ run_cnt, int32_t *__restrict__ unsorted,
-                                                      uint32_t *__restrict__ diff)
+                                                      uint32_t *__restrict__ run_cnt, Flags *__restrict__ fl)
 {
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
@@ -581,9 +618,6 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const int64_t *__restrict_
             const int64_t e = c + u * kWave + lane;
             cols[u] = e < e1 ? indices[e] : 0;
         }
-        // first entry after this group (uniform address)
-        const int64_t en = c + kRowChunks * kWave;
-        const int after = en < e1 ? indices[en] : 0;
 #pragma unroll
         for (int u = 0; u < kRowChunks; ++u) {
             const int64_t e = c + u * kWave + lane;
@@ -595,56 +629,58 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const int64_t *__restrict_
                 cp = prev_col;
                 kp = prev_k;
             }
-            int cn = __shfl_down(col, 1, kWave), kn = __shfl_down(k, 1, kWave);
-            if (lane == kWave - 1) {
-                const int nx = u + 1 < kRowChunks ? __builtin_amdgcn_readlane(cols[u + 1 < kRowChunks ? u + 1 : u], 0)
-                                                  : after;
-                cn = nx;
-                kn = e + 1 < e1 ? run_key(nx, n_voxels) : -3;
-            }
             runs += (uint32_t)__popcll(__ballot(in && k != kp));
             down = down || (in && kp != -1 && col <= cp);
-            const bool valid = in && k >= 0;
-            if (valid && !(kp >= 0 && col == cp + 1)) atomicAdd(diff + col, 1u);
-            if (valid && !(kn >= 0 && cn == col + 1)) atomicAdd(diff + col + 1, 0xffffffffu);
-            prev_col = __shfl(col, kWave - 1, kWave);
-            prev_k = __shfl(k, kWave - 1, kWave);
+            prev_col = __builtin_amdgcn_readlane(col, kWave - 1);
+            prev_k = __builtin_amdgcn_readlane(k, kWave - 1);
         }
     }
     if (lane == 0) run_cnt[j] = runs;
-    if (__ballot(down) && lane == 0) *unsorted = 1;
+    if (__ballot(down) && lane == 0) fl->unsorted = 1;
+}
+
+/* The path flags (one thread): a run path when the runs are at most half the
+ * entries, with masks when the rows ascend; else the radix sort of the entries. */
+__global__ void k_run_sizes(const int64_t *__restrict__ n_runs, int64_t nnz, Flags *__restrict__ fl)
+{
+    const int64_t R = *n_runs;
+    const int32_t use = 2 * R <= nnz ? 1 : 0, uns = fl->unsorted ? 1 : 0;
+    fl->use_runs = use;
+    fl->hist_len = (int64_t)kRadix * ((R + kSortTile - 1) / kSortTile);
+    fl->need_counts = (!use || uns) ? 1 : 0;
+    fl->sorted = (use && !uns) ? 1 : 0;
+    fl->any = (use && uns) ? 1 : 0;
 }
 
 /*
- * The path flag: the run transpose when the runs are at most half the entries,
- * else the radix sort of the entries; and the length of the run sort's digit
- * histograms.  One thread.
+ * Records of every run (row-major run ids from run_ptr): its bucket key (an
+ * invalid run takes the bucket of its column clamped into the grid), row
+ * (flagged when invalid), first entry, and an auxiliary word: with ascending
+ * rows the mask of its columns (OR of 1 << (col mod 32) over its entries, 0 for
+ * an invalid run), else its length (0 for an invalid run).  A lane's run
+ * starts at the highest start lane at or below it, or in an earlier chunk
+ * (carried); when the columns from that start to the lane are consecutive, as
+ * they are on a VOI row without holes, the lane's partial mask is a range of
+ * bits, else a segmented OR over the lanes gives it.
  */
-__global__ void k_run_sizes(const int64_t *__restrict__ n_runs, int64_t nnz, int32_t *__restrict__ use_runs,
-                            int64_t *__restrict__ hist_len)
-{
-    const int64_t R = *n_runs;
-    *use_runs = 2 * R <= nnz ? 1 : 0;
-    *hist_len = (int64_t)kRadix * ((R + kSortTile - 1) / kSortTile);
-}
-
-/* Records of every run (row-major run ids from run_ptr): its bucket (an invalid
- * run takes the bucket of its column clamped into the grid), row (flagged when
- * invalid), id (as the value payload of the run sort) and first entry. */
 __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__ indptr,
                                                      const int32_t *__restrict__ indices, int n_rows, int n_voxels,
-                                                     const int64_t *__restrict__ run_ptr,
-                                                     uint32_t *__restrict__ run_bucket, int32_t *__restrict__ run_row,
-                                                     float *__restrict__ run_id, uint32_t *__restrict__ run_src,
+                                                     const int64_t *__restrict__ run_ptr, const Flags *__restrict__ fl,
+                                                     uint32_t *__restrict__ run_key_out, int32_t *__restrict__ run_row,
+                                                     float *__restrict__ run_src, uint32_t *__restrict__ run_aux,
                                                      Gate g)
 {
     if (gate_closed(g)) return;
     const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (j >= n_rows) return;
+    const bool masks = fl->unsorted == 0;
     const int lane = lane_id();
+    const uint64_t upto_lane = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);   // lanes <= this one
     const int64_t e0 = indptr[j], e1 = indptr[j + 1];
     uint32_t r = (uint32_t)run_ptr[j];
     int prev_k = -1;                                   // run key of the entry before the chunk
+    int open_first = 0;                                // run open at the chunk start: its first column,
+    uint32_t open_len = 0, open_mask = 0;              // its entries and mask so far
     for (int64_t c = e0; c < e1; c += kRowChunks * kWave) {
         int cols[kRowChunks];
 #pragma unroll
@@ -652,6 +688,8 @@ __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__
             const int64_t e = c + u * kWave + lane;
             cols[u] = e < e1 ? indices[e] : 0;
         }
+        const int64_t en = c + kRowChunks * kWave;     // first entry after this group (uniform address)
+        const int after = en < e1 ? indices[en] : 0;
 #pragma unroll
         for (int u = 0; u < kRowChunks; ++u) {
             const int64_t e = c + u * kWave + lane;
@@ -660,18 +698,58 @@ __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__
             const int k = in ? run_key(col, n_voxels) : -3;
             int kp = __shfl_up(k, 1, kWave);
             if (lane == 0) kp = prev_k;
-            const bool start = in && k != kp;
-            const uint64_t m = __ballot(start);
-            if (start) {
-                const uint32_t id = r + (uint32_t)mbcnt64(m);
-                const int clamped = col < 0 ? 0 : (col >= n_voxels ? n_voxels - 1 : col);
-                run_bucket[id] = (uint32_t)(clamped >> kBucketShift);
-                run_row[id] = k >= 0 ? j : (int32_t)((uint32_t)j | kRunFlag);
-                run_id[id] = __uint_as_float(id);
-                run_src[id] = (uint32_t)e;
+            int kn = __shfl_down(k, 1, kWave);
+            if (lane == kWave - 1) {
+                const int nx = u + 1 < kRowChunks ? __builtin_amdgcn_readlane(cols[u + 1 < kRowChunks ? u + 1 : u], 0)
+                                                  : after;
+                kn = e + 1 < e1 ? run_key(nx, n_voxels) : -3;
             }
+            const bool start = in && k != kp;
+            const bool end = in && kn != k;
+            const uint64_t m = __ballot(start);
+            const uint64_t upto = m & upto_lane;
+            const int sl = upto ? kWave - 1 - (int)__builtin_clzll(upto) : -1;   // start lane of this lane's run
+            const int fc_here = __shfl(col, sl < 0 ? 0 : sl, kWave);
+            const int fc = sl >= 0 ? fc_here : open_first;
+            const uint32_t len = sl >= 0 ? (uint32_t)(lane - sl + 1) : open_len + (uint32_t)lane + 1u;
+            uint32_t x = 0u;
+            if (masks) {
+                const bool valid = in && k >= 0;
+                const bool ok = !valid || col - fc + 1 == (int)len;
+                if (__ballot(!ok) == 0) {
+                    // columns fc .. col of the bucket
+                    const uint32_t hi = (2u << (col & (kBucketCols - 1))) - 1u;
+                    const uint32_t lo = (1u << (fc & (kBucketCols - 1))) - 1u;
+                    x = valid ? (hi & ~lo) : 0u;
+                } else {
+                    // segmented inclusive OR over the lanes, segments opened by run starts
+                    x = valid ? 1u << (col & (kBucketCols - 1)) : 0u;
+                    int f = start ? 1 : 0;
+#pragma unroll
+                    for (int d = 1; d < kWave; d <<= 1) {
+                        const uint32_t y = __shfl_up(x, d, kWave);
+                        const int fy = __shfl_up(f, d, kWave);
+                        if (lane >= d && !f) {
+                            x |= y;
+                            f = fy;
+                        }
+                    }
+                    if (!f) x |= open_mask;            // no start at or below this lane: the open run
+                }
+            }
+            const uint32_t id = r + (uint32_t)mbcnt64(m) + (start ? 1u : 0u) - 1u;
+            if (start) {
+                const int clamped = col < 0 ? 0 : (col >= n_voxels ? n_voxels - 1 : col);
+                run_key_out[id] = (uint32_t)(clamped >> kBucketShift);
+                run_row[id] = k >= 0 ? j : (int32_t)((uint32_t)j | kRunFlag);
+                run_src[id] = __uint_as_float((uint32_t)e);
+            }
+            if (end) run_aux[id] = masks ? x : (k >= 0 ? len : 0u);
+            open_first = __builtin_amdgcn_readlane(fc, kWave - 1);
+            open_len = (uint32_t)__builtin_amdgcn_readlane((int)len, kWave - 1);
+            open_mask = (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
             r += (uint32_t)__popcll(m);
-            prev_k = __shfl(k, kWave - 1, kWave);
+            prev_k = __builtin_amdgcn_readlane(k, kWave - 1);
         }
     }
 }
@@ -691,32 +769,184 @@ __global__ __launch_bounds__(kBlock) void k_bucket_bounds(const uint32_t *__rest
     }
 }
 
-/* Sorted run q: its first entry and length (0 for an invalid run), and its row
- * without the flag; the length runs to the next run of the row or the row's end. */
-__global__ __launch_bounds__(kBlock) void k_run_gather(const float *__restrict__ b_ids, int32_t *__restrict__ b_rows,
-                                                       const uint32_t *__restrict__ run_src,
-                                                       const int64_t *__restrict__ run_ptr,
-                                                       const int64_t *__restrict__ indptr, Count n_runs,
-                                                       uint32_t *__restrict__ b_src, uint32_t *__restrict__ b_len,
-                                                       Gate g)
+/* Bucket handled by workgroup blockIdx.x: groups of kXcdGroup consecutive
+ * buckets go to one XCD (workgroups are dealt to the XCDs in turn), so that
+ * the runs of neighbouring buckets, which share cache lines of a row, meet in
+ * one L2; the groups themselves are dealt to the XCDs in turn, which keeps the
+ * XCDs evenly loaded when the entries crowd into part of the grid. */
+constexpr int kXcdGroup = 16;
+__device__ inline int xcd_bucket()
 {
-    if (gate_closed(g)) return;
-    const int64_t R = count_of(n_runs);
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < R; q += stride) {
-        const uint32_t id = __float_as_uint(b_ids[q]);
-        const uint32_t rw = (uint32_t)b_rows[q];
-        const int row = (int)(rw & ~kRunFlag);
-        const uint32_t src = run_src[id];
-        const uint32_t end = (int64_t)id + 1 < run_ptr[row + 1] ? run_src[id + 1] : (uint32_t)indptr[row + 1];
-        b_src[q] = src;
-        b_len[q] = (rw & kRunFlag) ? 0u : end - src;
-        b_rows[q] = row;
-    }
+    const int x = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
+    return ((k / kXcdGroup) * kXcds + x) * kXcdGroup + k % kXcdGroup;
+}
+static unsigned xcd_grid(int n_buckets)
+{
+    const int per = kXcds * kXcdGroup;
+    return (unsigned)(((n_buckets + per - 1) / per) * per);
 }
 
-constexpr int kColWaves = 2;                               // waves per workgroup of k_bucket_place
-constexpr int kStageUnroll = 8;                            // staging chunks whose loads are in flight together
+constexpr int kPlaceCap = 1024;     // entries of one batch staged in LDS
+constexpr int kStageUnroll = 8;     // staging chunks whose loads are in flight together
+
+/*
+ * Placement for rows with ascending columns, one wave per bucket.
+ *
+ * First the bucket's entries per column: popcounts of ballots over the run
+ * masks; their prefix from the bucket's first entry (the exclusive sum of the
+ * lengths of all earlier runs) gives the voxel-row pointers of its columns.
+ * Then batches of runs (in row order, at most kPlaceCap entries): for column c,
+ * the ballot of the runs holding c ranks them, so the entry of run r in column
+ * c goes to position (entries of the batch in columns below c) + (runs below r
+ * holding c) of the batch's LDS image, which lists the batch's entries column
+ * by column.  The image is then written out: each column's part is contiguous
+ * after the entries of that column from earlier batches.
+ */
+__global__ __launch_bounds__(kWave) void k_place_sorted(
+    const float *__restrict__ values, int n_voxels, int n_buckets, const int64_t *__restrict__ b_ptr,
+    const int32_t *__restrict__ b_rows, const float *__restrict__ b_src, const uint32_t *__restrict__ b_mask,
+    const uint32_t *__restrict__ b_off, const Flags *__restrict__ fl, int64_t *__restrict__ t_indptr, uint32_t nnz,
+    int32_t *__restrict__ t_indices, float *__restrict__ t_values, Gate g)
+{
+    if (gate_closed(g)) return;
+    const int b = xcd_bucket();
+    if (b >= n_buckets) return;
+    __shared__ uint16_t s_ent[kPlaceCap];        // batch entry p: (run lane << 5) | column
+    __shared__ int32_t s_orow[kPlaceCap];        // LDS image, column by column
+    __shared__ float s_oval[kPlaceCap];
+    __shared__ uint8_t s_ocol[kPlaceCap];
+    __shared__ uint64_t s_cm[kBucketCols];       // runs of the batch holding column c
+    __shared__ uint32_t s_cst[kBucketCols];      // first image position of column c
+    __shared__ uint32_t s_pos[kBucketCols];      // next output position of column c
+    const int lane = lane_id();
+    const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1], R = b_ptr[n_buckets];
+    const uint32_t total = (uint32_t)fl->total;
+    const uint32_t base = q0 < R ? b_off[q0] : total;
+
+    // entries per column of the bucket (lane c), the voxel-row pointers
+    uint32_t acc = 0;
+    for (int64_t qb = q0; qb < q1; qb += kWave) {
+        const uint32_t mask = qb + lane < q1 ? b_mask[qb + lane] : 0u;
+#pragma unroll
+        for (int c = 0; c < kBucketCols; ++c) {
+            const uint32_t n = (uint32_t)__popcll(__ballot((mask >> c) & 1u));
+            acc += lane == c ? n : 0u;
+        }
+    }
+    uint32_t incl = acc;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
+    if (lane < kBucketCols) {
+        const uint32_t pos = base + incl - acc;
+        s_pos[lane] = pos;
+        const int col = (b << kBucketShift) + lane;
+        if (col < n_voxels) t_indptr[col] = pos;
+    }
+    if (b == n_buckets - 1 && lane == 0) t_indptr[n_voxels] = total;
+    __builtin_amdgcn_wave_barrier();
+
+    for (int64_t qb = q0; qb < q1;) {
+        const int64_t q = qb + lane;
+        const bool have = q < q1;
+        const int row = have ? (int)((uint32_t)b_rows[q] & ~kRunFlag) : 0;
+        const uint32_t src = have ? __float_as_uint(b_src[q]) : 0u;
+        uint32_t mask = have ? b_mask[q] : 0u;   // 0 for an invalid run
+        uint32_t len = (uint32_t)__popc(mask);
+        uint32_t end = len;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(end, d, kWave);
+            if (lane >= d) end += y;
+        }
+        // the batch: the leading runs whose entries fit (at least one: a run holds <= 32)
+        const bool fit = have && end <= (uint32_t)kPlaceCap;
+        const int take = __popcll(__ballot(fit));
+        const uint32_t T = (uint32_t)__shfl(end, take - 1, kWave);
+        if (!fit) {
+            mask = 0u;
+            len = 0u;
+        }
+        const uint32_t excl = end - len;
+        // runs of the batch per column, and the columns' first image positions
+        uint64_t cm = 0;
+#pragma unroll
+        for (int c = 0; c < kBucketCols; ++c) {
+            const uint64_t m = __ballot((mask >> c) & 1u);
+            cm = lane == c ? m : cm;
+        }
+        const uint32_t cnt = (uint32_t)__popcll(cm);
+        uint32_t cinc = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(cinc, d, kWave);
+            if (lane >= d) cinc += y;
+        }
+        const uint32_t cst = cinc - cnt;
+        if (lane < kBucketCols) {
+            s_cm[lane] = cm;
+            s_cst[lane] = cst;
+        }
+        // batch entries in run order: entry excl + i of run `lane` is its mask's i-th column
+        {
+            uint32_t x = mask, p = excl;
+            while (__ballot(x != 0u)) {
+                if (x != 0u) {
+                    const uint32_t c = (uint32_t)__builtin_ctz(x);
+                    x &= x - 1u;
+                    s_ent[p] = (uint16_t)(((uint32_t)lane << kBucketShift) | c);
+                    ++p;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // stage the values into the image, kStageUnroll chunks of loads at a time
+        for (uint32_t g0 = 0; g0 < T; g0 += kStageUnroll * kWave) {
+            uint32_t ent[kStageUnroll];
+            float v[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const uint32_t p = g0 + u * kWave + lane;
+                const bool in = p < T;
+                ent[u] = in ? (uint32_t)s_ent[p] : 0u;
+                const int rr = (int)(ent[u] >> kBucketShift);
+                // shuffles on every lane; loads only for entries of the batch
+                const uint32_t e = __shfl(src, rr, kWave) + (p - __shfl(excl, rr, kWave));
+                v[u] = in ? values[e] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const uint32_t p = g0 + u * kWave + lane;
+                const int rr = (int)(ent[u] >> kBucketShift);
+                const int c = (int)(ent[u] & (kBucketCols - 1));
+                const int rowr = __shfl(row, rr, kWave);
+                if (p < T) {
+                    const uint64_t below = (1ull << rr) - 1ull;
+                    const uint32_t d = s_cst[c] + (uint32_t)__popcll(s_cm[c] & below);
+                    s_orow[d] = rowr;
+                    s_oval[d] = v[u];
+                    s_ocol[d] = (uint8_t)c;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // write the image out
+        for (uint32_t i = lane; i < T; i += kWave) {
+            const int c = s_ocol[i];
+            const uint32_t gp = s_pos[c] + (i - s_cst[c]);
+            if (gp < nnz) {   // always true for consistent runs; keeps every store in bounds
+                t_indices[gp] = s_orow[i];
+                t_values[gp] = s_oval[i];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < kBucketCols) s_pos[lane] += cnt;
+        __builtin_amdgcn_wave_barrier();
+        qb += take;
+    }
+}
 
 /* The runs of bucket b, taken 64 at a time: lane i holds run q0 + i (its row,
  * first entry and length), with the batch's exclusive prefix of lengths. */
@@ -726,16 +956,15 @@ struct RunBatch {
 };
 
 __device__ inline RunBatch load_runs(int64_t qb, int64_t q1, const int32_t *__restrict__ b_rows,
-                                     const uint32_t *__restrict__ b_src, const uint32_t *__restrict__ b_len,
-                                     uint32_t max_len)
+                                     const float *__restrict__ b_src, const uint32_t *__restrict__ b_len)
 {
     const int lane = lane_id();
     const int64_t q = qb + lane;
     RunBatch B{0, 0u, 0u, 0u, 0u};
     if (q < q1) {
-        B.row = b_rows[q];
-        B.src = b_src[q];
-        B.len = min(b_len[q], max_len);
+        B.row = (int)((uint32_t)b_rows[q] & ~kRunFlag);
+        B.src = __float_as_uint(b_src[q]);
+        B.len = b_len[q];   // 0 for an invalid run
     }
     uint32_t incl = B.len;
 #pragma unroll
@@ -764,121 +993,34 @@ __device__ inline int run_of(const RunBatch &B, uint32_t c0, int &rcur)
 }
 
 /*
- * Placement for rows with strictly ascending columns, column by column.  A
- * batch of 64 runs of the bucket (rows ascending; each at most 32 entries,
- * one per column) is first copied into LDS, the runs' entries flattened over
- * the lanes, kStageUnroll chunks of 64 at a time with all their loads issued
- * together; then each lane holds one run and, at column c, the lanes whose
- * next entry has column c write it, ranked by lane, so each column's entries
- * from the batch go out as one contiguous stretch.
+ * Placement for rows in any column order, one wave per bucket: the bucket's
+ * runs are taken 64 at a time, their entries flattened over the lanes in run
+ * order; an entry of column col goes to t_indptr[col] + (entries of col placed
+ * before it), counted per column in LDS.  Equal columns within a 64-entry
+ * chunk are ranked by lane with five ballots over the column's low bits.
  */
-__device__ void place_columns(int b, int wave, const int32_t *__restrict__ indices, const float *__restrict__ values,
-                              int n_voxels, const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows,
-                              const uint32_t *__restrict__ b_src, const uint32_t *__restrict__ b_len,
-                              const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
-                              float *__restrict__ t_values)
+__global__ __launch_bounds__(kWave) void k_place_any(
+    const int32_t *__restrict__ indices, const float *__restrict__ values, int n_voxels, int n_buckets,
+    const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows, const float *__restrict__ b_src,
+    const uint32_t *__restrict__ b_len, const int64_t *__restrict__ t_indptr, uint32_t nnz,
+    int32_t *__restrict__ t_indices, float *__restrict__ t_values, Gate g)
 {
-    constexpr int kStage = kWave * kBucketCols;            // 64 runs of at most 32 entries
-    __shared__ uint32_t s_pos[kColWaves][kBucketCols];
-    __shared__ float s_val[kColWaves][kStage];
-    __shared__ uint8_t s_col[kColWaves][kStage];
+    if (gate_closed(g)) return;
+    const int b = xcd_bucket();
+    if (b >= n_buckets) return;
+    __shared__ uint32_t base[kBucketCols];
+    __shared__ uint32_t cnt[kBucketCols];
     const int lane = lane_id();
-    uint32_t *pos = s_pos[wave];                           // next free position of each column's list
-    float *sv = s_val[wave];
-    uint8_t *sc = s_col[wave];
-    for (int c = lane; c < kBucketCols; c += kWave) {
-        const int col = (b << kBucketShift) + c;
-        pos[c] = col < n_voxels ? (uint32_t)t_indptr[col] : 0u;
-    }
-    const int col0 = b << kBucketShift;
-    const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1];
-    for (int64_t qb = q0; qb < q1; qb += kWave) {
-        const RunBatch B = load_runs(qb, q1, b_rows, b_src, b_len, kBucketCols);
-        // stage: entry p of the batch -> LDS
-        int rcur = 0;
-        for (uint32_t g0 = 0; g0 < B.total; g0 += kStageUnroll * kWave) {
-            uint32_t e[kStageUnroll];
-#pragma unroll
-            for (int u = 0; u < kStageUnroll; ++u) {
-                const uint32_t c0 = g0 + u * kWave;
-                e[u] = 0u;
-                if (c0 < B.total) {
-                    const int rr = run_of(B, c0, rcur);
-                    // shuffles on every lane: the source lane rr may be past the end of the batch's entries
-                    e[u] = __shfl(B.src, rr, kWave) + (c0 + lane - __shfl(B.excl, rr, kWave));
-                }
-            }
-            int cols[kStageUnroll];
-            float vals[kStageUnroll];
-#pragma unroll
-            for (int u = 0; u < kStageUnroll; ++u) {
-                const bool in = g0 + u * kWave + lane < B.total;
-                cols[u] = in ? indices[e[u]] : col0;
-                vals[u] = in ? values[e[u]] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < kStageUnroll; ++u) {
-                const uint32_t p = g0 + u * kWave + lane;
-                if (p < B.total) {
-                    sc[p] = (uint8_t)(cols[u] - col0);
-                    sv[p] = vals[u];
-                }
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // place: lane = run, its entries sc/sv[excl, excl + len)
-        uint32_t k = B.excl;
-        const uint32_t end = B.excl + B.len;
-        int ca = k < end ? (int)sc[k] : kBucketCols;
-        for (int c = 0; c < kBucketCols; ++c) {
-            const bool has = ca == c;
-            const uint64_t m = __ballot(has);
-            if (m == 0) continue;
-            const uint32_t p0 = pos[c];
-            if (has) {
-                const uint32_t p = p0 + (uint32_t)mbcnt64(m);
-                if (p < nnz) {   // always true for consistent runs; keeps every store in bounds
-                    t_indices[p] = B.row;
-                    t_values[p] = sv[k];
-                }
-                ++k;
-                ca = k < end ? (int)sc[k] : kBucketCols;
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) pos[c] = p0 + (uint32_t)__popcll(m);
-            __builtin_amdgcn_wave_barrier();
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
-/*
- * Placement for rows in any column order: the bucket's runs are taken 64 at a
- * time, their entries flattened over the lanes in run order; an entry of
- * column col goes to t_indptr[col] + (entries of col placed before it),
- * counted per column in LDS.  Equal columns within a 64-entry chunk are
- * ranked by lane with five ballots over the column's low bits.
- */
-__device__ void place_any(int b, int wave, const int32_t *__restrict__ indices, const float *__restrict__ values,
-                          int n_voxels, const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows,
-                          const uint32_t *__restrict__ b_src, const uint32_t *__restrict__ b_len,
-                          const int64_t *__restrict__ t_indptr, uint32_t nnz, int32_t *__restrict__ t_indices,
-                          float *__restrict__ t_values)
-{
-    __shared__ uint32_t s_base[kColWaves][kBucketCols];
-    __shared__ uint32_t s_cnt[kColWaves][kBucketCols];
-    const int lane = lane_id();
-    uint32_t *base = s_base[wave];
-    uint32_t *cnt = s_cnt[wave];
     for (int c = lane; c < kBucketCols; c += kWave) {
         const int col = (b << kBucketShift) + c;
         base[c] = col < n_voxels ? (uint32_t)t_indptr[col] : 0u;
         cnt[c] = 0u;
     }
+    __builtin_amdgcn_wave_barrier();
     const int64_t q0 = b_ptr[b], q1 = b_ptr[b + 1];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes under this one
     for (int64_t qb = q0; qb < q1; qb += kWave) {
-        const RunBatch B = load_runs(qb, q1, b_rows, b_src, b_len, 0xffffffffu);
+        const RunBatch B = load_runs(qb, q1, b_rows, b_src, b_len);
         int rcur = 0;
         for (uint32_t c0 = 0; c0 < B.total; c0 += kWave) {
             const uint32_t p = c0 + lane;
@@ -910,29 +1052,11 @@ __device__ void place_any(int b, int wave, const int32_t *__restrict__ indices, 
     }
 }
 
-/* One wave per bucket of columns. */
-__global__ __launch_bounds__(kColWaves * kWave) void k_bucket_place(
-    const int32_t *__restrict__ indices, const float *__restrict__ values, int n_voxels, int n_buckets,
-    const int64_t *__restrict__ b_ptr, const int32_t *__restrict__ b_rows, const uint32_t *__restrict__ b_src,
-    const uint32_t *__restrict__ b_len, const int64_t *__restrict__ t_indptr, uint32_t nnz,
-    int32_t *__restrict__ t_indices, float *__restrict__ t_values, const int32_t *__restrict__ unsorted, Gate g)
-{
-    if (gate_closed(g)) return;
-    const int wave = threadIdx.x >> 6;
-    const int b = blockIdx.x * kColWaves + wave;
-    if (b >= n_buckets) return;
-    if (*unsorted)
-        place_any(b, wave, indices, values, n_voxels, b_ptr, b_rows, b_src, b_len, t_indptr, nnz, t_indices,
-                  t_values);
-    else
-        place_columns(b, wave, indices, values, n_voxels, b_ptr, b_rows, b_src, b_len, t_indptr, nnz, t_indices,
-                      t_values);
-}
-
 }  // namespace
 
+/* Workspace layout of the transpose (offsets from a 256-byte aligned base). */
 struct TransposeLayout {
-    size_t key[2], row[2], val[2], hist, offs, partial, counts, bptr, scal, run_cnt, run_ptr, total;
+    size_t key[2], row[2], val[2], hist, offs, partial, counts, bptr, flags, run_cnt, run_ptr, total;
 };
 
 static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
@@ -947,8 +1071,7 @@ static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
     const int64_t n_tiles = (nnz + kSortTile - 1) / kSortTile;
     const int64_t n_hist = (int64_t)kRadix * (n_tiles > 0 ? n_tiles : 1);
     const int64_t nb = (n_voxels + kBucketCols - 1) >> kBucketShift;
-    int64_t n_scan = n_hist > n_voxels ? n_hist : n_voxels;
-    if (n_rows > n_scan) n_scan = n_rows;
+    int64_t n_scan = std::max<int64_t>(std::max<int64_t>(n_hist, n_voxels), std::max<int64_t>(n_rows, (nnz + 1) / 2));
     const size_t e = (size_t)(nnz > 0 ? nnz : 1);
     for (int b = 0; b < 2; ++b) {
         L.key[b] = take(sizeof(uint32_t) * e);
@@ -958,9 +1081,9 @@ static TransposeLayout transpose_layout(int64_t nnz, int n_voxels, int n_rows)
     L.hist = take(sizeof(uint32_t) * (size_t)n_hist);
     L.offs = take(sizeof(uint32_t) * (size_t)n_hist);
     L.partial = take(sizeof(uint32_t) * (size_t)((n_scan + kScanChunk - 1) / kScanChunk + 1));
-    L.counts = take(sizeof(uint32_t) * ((size_t)n_voxels + 1));   // difference array, then counts
+    L.counts = take(sizeof(uint32_t) * ((size_t)n_voxels + 1));
     L.bptr = take(sizeof(int64_t) * (size_t)(nb + 1));
-    L.scal = take(64);   // unsorted-rows flag, path flag, run histogram length
+    L.flags = take(sizeof(Flags));
     L.run_cnt = take(sizeof(uint32_t) * (size_t)(n_rows > 0 ? n_rows : 1));
     L.run_ptr = take(sizeof(int64_t) * ((size_t)n_rows + 1));
     L.total = off;
@@ -990,29 +1113,36 @@ static unsigned stride_grid(int64_t items)
  * uint32_t or int64_t; out may be in); n is a host count or, with n.dev, a
  * device count at most n_max.  partial[nblocks] receives the total, and
  * *total64 too when given. */
-template <typename OUT, bool INCL = false>
+template <typename OUT, bool INCL = false, bool POPC = false>
 static hipError_t scan_excl(const uint32_t *in, Count n, int64_t n_max, uint32_t *partial, OUT *out,
                             int64_t *total64, Gate g, hipStream_t s)
 {
     const unsigned nb = stride_grid((n_max + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, partial, g);
+    hipLaunchKernelGGL(k_scan_reduce<POPC>, dim3(nb), dim3(kBlock), 0, s, in, n, partial, g);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, partial, n, total64, g);
-    hipLaunchKernelGGL((k_scan_down<OUT, INCL>), dim3(nb), dim3(kBlock), 0, s, in, n, partial, out, g);
+    hipLaunchKernelGGL((k_scan_down<OUT, INCL, POPC>), dim3(nb), dim3(kBlock), 0, s, in, n, partial, out, g);
     return hipGetLastError();
 }
+
+/* Optional fourth payload of a radix sort: input, ping-pong buffers, output. */
+struct Extra {
+    const uint32_t *in;
+    uint32_t *b0, *b1, *out;
+};
 
 /*
  * One stable LSD radix sort of (key, row, value) triples by key: `passes`
  * passes of 8 bits, keys above clamp sorted as clamp, ping-pong through
  * (k1, r1, v1) and (k0, r0, v0) (the input may be separate), the last pass
  * writing rows and values to (rows_out, vals_out), and with keys_out its keys
- * to the pass's own key buffer (*keys_out = that buffer).  n is a host or
- * device count, at most n_max.
+ * to the pass's own key buffer (*keys_out = that buffer); with x.in a fourth
+ * payload rides along (through x.b1, x.b0, to x.out).  n is a host or device
+ * count, at most n_max.
  */
 static hipError_t radix_sort(const uint32_t *keys, const int32_t *rows, const float *vals, Count n, int64_t n_max,
                              uint32_t clamp, int passes, uint32_t *k0, int32_t *r0, float *v0, uint32_t *k1,
                              int32_t *r1, float *v1, int32_t *rows_out, float *vals_out, uint32_t **keys_out,
-                             uint32_t *hist, uint32_t *offs, uint32_t *partial, int64_t *hist_len_dev, Gate g,
+                             Extra x, uint32_t *hist, uint32_t *offs, uint32_t *partial, int64_t *hist_len_dev, Gate g,
                              hipStream_t s)
 {
     const int64_t tiles_max = (n_max + kSortTile - 1) / kSortTile;
@@ -1021,6 +1151,7 @@ static hipError_t radix_sort(const uint32_t *keys, const int32_t *rows, const fl
     const uint32_t *kin = keys;
     const int32_t *rin = rows;
     const float *vin = vals;
+    const uint32_t *xin = x.in;
     hipError_t e;
     for (int p = 0; p < passes; ++p) {
         const int shift = p * kRadixBits;
@@ -1029,17 +1160,23 @@ static hipError_t radix_sort(const uint32_t *keys, const int32_t *rows, const fl
         uint32_t *kout = last ? (keys_out ? kbuf : nullptr) : kbuf;
         int32_t *rout = last ? rows_out : ((p & 1) ? r0 : r1);
         float *vout = last ? vals_out : ((p & 1) ? v0 : v1);
+        uint32_t *xout = last ? x.out : ((p & 1) ? x.b0 : x.b1);
         hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(kBlock), 0, s, kin, n, clamp, shift, hist, g);
         if ((e = scan_excl<uint32_t>(hist, hn, (int64_t)kRadix * tiles_max, partial, offs, nullptr, g, s)) !=
             hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(kBlock), 0, s, kin, rin, vin, n, clamp, shift, offs, kout,
-                           rout, vout, g);
+        if (x.in)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3(grid), dim3(kBlock), 0, s, kin, rin, vin, xin, n, clamp, shift,
+                               offs, kout, rout, vout, xout, g);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3(grid), dim3(kBlock), 0, s, kin, rin, vin, nullptr, n, clamp,
+                               shift, offs, kout, rout, vout, nullptr, g);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (last && keys_out) *keys_out = kout;
         kin = kout;
         rin = rout;
         vin = vout;
+        xin = xout;
     }
     return hipSuccess;
 }
@@ -1057,68 +1194,74 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
     uint32_t *offs = reinterpret_cast<uint32_t *>(ws + L.offs);
     uint32_t *partial = reinterpret_cast<uint32_t *>(ws + L.partial);
     uint32_t *counts = reinterpret_cast<uint32_t *>(ws + L.counts);
-    int32_t *unsorted = reinterpret_cast<int32_t *>(ws + L.scal);
-    int32_t *use_runs = unsorted + 1;
-    int64_t *hist_len = reinterpret_cast<int64_t *>(ws + L.scal + 8);
+    Flags *fl = reinterpret_cast<Flags *>(ws + L.flags);
     uint32_t *run_cnt = reinterpret_cast<uint32_t *>(ws + L.run_cnt);
     int64_t *run_ptr = reinterpret_cast<int64_t *>(ws + L.run_ptr);
     const Gate always{nullptr, 0};
     hipError_t e;
 
-    // runs of every row, the unsorted flag and the entries per column as a difference
-    // array; then entries per column (inclusive scan) and the voxel-row pointers
-    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of((int64_t)n_voxels + 1, kBlock)), dim3(kBlock), 0, s, counts,
-                       (int64_t)n_voxels + 1);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(unsorted), (int64_t)1);
-    if (nnz > 0 && n_rows > 0)
-        hipLaunchKernelGGL(k_run_count, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
-                           n_rows, n_voxels, run_cnt, unsorted, counts);
-    if ((e = scan_excl<uint32_t, true>(counts, Count{n_voxels, nullptr}, n_voxels, partial, counts, nullptr, always,
-                                       s)) != hipSuccess)
-        return e;
-    if ((e = scan_excl<int64_t>(counts, Count{n_voxels, nullptr}, n_voxels, partial, t_indptr, t_indptr + n_voxels,
-                                always, s)) != hipSuccess)
-        return e;
-    if (nnz == 0 || n_rows == 0) return hipSuccess;
+    if (nnz == 0 || n_rows == 0) {   // empty voxel rows
+        hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of((int64_t)n_voxels + 1, kBlock)), dim3(kBlock), 0, s, counts,
+                           (int64_t)n_voxels + 1);
+        return scan_excl<int64_t>(counts, Count{n_voxels, nullptr}, n_voxels, partial, t_indptr, t_indptr + n_voxels,
+                                  always, s);
+    }
 
-    const int nb = (n_voxels + kBucketCols - 1) >> kBucketShift;
+    // runs of every row and the unsorted flag; run pointers; the path flags
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, s, reinterpret_cast<uint32_t *>(fl),
+                       (int64_t)(sizeof(Flags) / 4));
+    hipLaunchKernelGGL(k_run_count, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
+                       n_rows, n_voxels, run_cnt, fl);
     if ((e = scan_excl<int64_t>(run_cnt, Count{n_rows, nullptr}, n_rows, partial, run_ptr, run_ptr + n_rows, always,
                                 s)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_run_sizes, dim3(1), dim3(1), 0, s, run_ptr + n_rows, nnz, use_runs, hist_len);
-    const Gate runs{use_runs, 1}, entries{use_runs, 0};
+    hipLaunchKernelGGL(k_run_sizes, dim3(1), dim3(1), 0, s, run_ptr + n_rows, nnz, fl);
+    const Gate runs{&fl->use_runs, 1}, entries{&fl->use_runs, 0}, counted{&fl->need_counts, 1},
+        masked{&fl->sorted, 1}, any{&fl->any, 1};
 
-    // run path: at most nnz / 2 runs.  Run records in the first half of key[0], row[0],
-    // val[0]; first entries and the sorted rows and ids from `half` on; the sort's other
-    // buffers are key/row/val[1]; after the sort, each run's first entry and length go to
-    // row[1] and val[1] (free then: the sorted keys are in key[0] or key[1])
+    // entry path and unsorted rows: entries per column by atomics, the voxel-row pointers
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_of((int64_t)n_voxels + 1, kBlock)), dim3(kBlock), 0, s, counts,
+                       (int64_t)n_voxels + 1);
+    hipLaunchKernelGGL(k_key_count, dim3(stride_grid(blocks_of(nnz, kBlock))), dim3(kBlock), 0, s, indices, nnz,
+                       n_voxels, counts, counted);
+    if ((e = scan_excl<int64_t>(counts, Count{n_voxels, nullptr}, n_voxels, partial, t_indptr, t_indptr + n_voxels,
+                                counted, s)) != hipSuccess)
+        return e;
+
+    // run paths: at most nnz / 2 runs.  Run records (bucket, row, first entry, mask or
+    // length) in the first halves of key[0], row[0], val[0] and in key[0] + half; the
+    // sort's other buffers are the first halves of key/row/val[1] and key[1] + half; the
+    // sorted rows, first entries and masks or lengths go to row[0] + half, val[0] + half
+    // and row[1] + half, the entry offsets of the sorted runs to val[1] + half
+    const int nb = (n_voxels + kBucketCols - 1) >> kBucketShift;
     {
         const int64_t half = (nnz + 1) / 2;
-        uint32_t *rkey = key[0];
-        int32_t *rrow = row[0];
-        float *rid = val[0];
-        uint32_t *rsrc = key[0] + half;
         int32_t *brow = row[0] + half;
-        float *bid = val[0] + half;
-        uint32_t *bsrc = reinterpret_cast<uint32_t *>(row[1]);
-        uint32_t *blen = reinterpret_cast<uint32_t *>(val[1]);
+        float *bsrc = val[0] + half;
+        uint32_t *baux = reinterpret_cast<uint32_t *>(row[1]) + half;
+        uint32_t *boff = reinterpret_cast<uint32_t *>(val[1]) + half;
         int64_t *bptr = reinterpret_cast<int64_t *>(ws + L.bptr);
         const Count n_runs{0, run_ptr + n_rows};
         hipLaunchKernelGGL(k_run_emit, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr, indices,
-                           n_rows, n_voxels, run_ptr, rkey, rrow, rid, rsrc, runs);
+                           n_rows, n_voxels, run_ptr, fl, key[0], row[0], val[0], key[0] + half, runs);
         // stable sort of the runs by bucket
         uint32_t *skeys = nullptr;
-        if ((e = radix_sort(rkey, rrow, rid, n_runs, half, 0xffffffffu, transpose_passes(nb), key[0], row[0], val[0],
-                            key[1], row[1], val[1], brow, bid, &skeys, hist, offs, partial, hist_len, runs, s)) !=
-            hipSuccess)
+        const Extra aux{key[0] + half, key[0] + half, key[1] + half, baux};
+        if ((e = radix_sort(key[0], row[0], val[0], n_runs, half, 0xffffffffu, transpose_passes(nb), key[0], row[0],
+                            val[0], key[1], row[1], val[1], brow, bsrc, &skeys, aux, hist, offs, partial,
+                            &fl->hist_len, runs, s)) != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_bucket_bounds, dim3(stride_grid(blocks_of(half + 1, kBlock))), dim3(kBlock), 0, s, skeys,
                            n_runs, nb, bptr, runs);
-        hipLaunchKernelGGL(k_run_gather, dim3(stride_grid(blocks_of(half, kBlock))), dim3(kBlock), 0, s, bid, brow,
-                           rsrc, run_ptr, indptr, n_runs, bsrc, blen, runs);
-        hipLaunchKernelGGL(k_bucket_place, dim3(blocks_of(nb, kColWaves)), dim3(kColWaves * kWave), 0, s, indices,
-                           values, n_voxels, nb, bptr, brow, bsrc, blen, t_indptr, (uint32_t)nnz, t_indices, t_values,
-                           unsorted, runs);
+        // rows ascending: entry offset of every sorted run, then the placement (and the pointers)
+        if ((e = scan_excl<uint32_t, false, true>(baux, n_runs, half, partial, boff, &fl->total, masked, s)) !=
+            hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_place_sorted, dim3(xcd_grid(nb)), dim3(kWave), 0, s, values, n_voxels, nb, bptr, brow,
+                           bsrc, baux, boff, fl, t_indptr, (uint32_t)nnz, t_indices, t_values, masked);
+        // rows in any order
+        hipLaunchKernelGGL(k_place_any, dim3(xcd_grid(nb)), dim3(kWave), 0, s, indices, values, n_voxels, nb, bptr,
+                           brow, bsrc, baux, t_indptr, (uint32_t)nnz, t_indices, t_values, any);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
 
@@ -1128,7 +1271,8 @@ hipError_t launch_transpose(const int64_t *indptr, const int32_t *indices, const
                        row[0], entries);
     return radix_sort(reinterpret_cast<const uint32_t *>(indices), row[0], values, Count{nnz, nullptr}, nnz,
                       (uint32_t)n_voxels, transpose_passes(n_voxels + 1), key[0], row[0], val[0], key[1], row[1],
-                      val[1], t_indices, t_values, nullptr, hist, offs, partial, nullptr, entries, s);
+                      val[1], t_indices, t_values, nullptr, Extra{nullptr, nullptr, nullptr, nullptr}, hist, offs,
+                      partial, nullptr, entries, s);
 }
 
 /*
