@@ -814,10 +814,14 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     uint16_t *s_h1 = reinterpret_cast<uint16_t *>(
         smem + ((sizeof(float2) * ((size_t)kErfPairs + P.max_table + n_pdd) +
                  sizeof(int) * ((size_t)P.max_tiles + 1) + 15) & ~(size_t)15)) + wave * (64 * mlp::kH1Stride);
+    // and the layer-1 bias with this beamlet's width term folded in, after the W tiles
+    float *s_b1x = reinterpret_cast<float *>(s_h1 + (W - wave) * (64 * mlp::kH1Stride));
     mlp::W2Frags wf;
     if (SURR) mlp::load_w2_frags(P.mlp_w2, wf);
     const float a_f = R.a_f;
     const bool mlp_ok = SURR && R.mlp_ok;
+    if (SURR && tid < kMlpH)
+        s_b1x[tid] = fmaf(P.mlp_p[kOffW1 + tid * kMlpIn + 3], mlp::feature_a(a_f), P.mlp_p[kOffB1 + tid]);
 
     {
         // the erf table in the form this fill reads (compact, or mirrored after it)
@@ -979,7 +983,9 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                                     av <= kMlpUVMax;
                 float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
                 if (in_box) mlp::features(d, au, av, a_f, x);
-                const float y = mlp::forward_wave(P.mlp_p, wf, x, s_h1);
+                // the network only for chunks with a sample inside the training box
+                float y = 0.0f;
+                if (__ballot(in_box)) y = mlp::forward_wave<true>(P.mlp_p, s_b1x, wf, x, s_h1);
                 if (in_box) D = y * g * g;
                 else if (member) D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
             }
@@ -1184,7 +1190,9 @@ size_t fill_shared_bytes(const PlanDev &h, bool mirrored_erf)
     size_t b = sizeof(float2) * ((mirrored_erf ? 2 * kErfIntervals : kErfIntervals) + (size_t)h.max_table +
                                  (size_t)lds_pdd_pairs(h)) +
                sizeof(int) * ((size_t)h.max_tiles + 1);
-    if (h.use_mlp) b = ((b + 15) & ~(size_t)15) + sizeof(uint16_t) * 64 * mlp::kH1Stride * kWavesPerBlock;
+    if (h.use_mlp)
+        b = ((b + 15) & ~(size_t)15) + sizeof(uint16_t) * 64 * mlp::kH1Stride * kWavesPerBlock +
+            sizeof(float) * kMlpH;
     return b;
 }
 

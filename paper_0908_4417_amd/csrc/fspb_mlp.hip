@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev m, const float *__re
     float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (i < n)
         for (int k = 0; k < 4; ++k) x[k] = feats[4 * i + k];
-    const float y = forward_wave(m.p, wf, x, h1[w]);
+    const float y = forward_wave<false>(m.p, nullptr, wf, x, h1[w]);
     if (i < n) out[i] = y;
 }
 

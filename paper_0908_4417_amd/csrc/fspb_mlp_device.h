@@ -59,29 +59,33 @@ __device__ inline void load_w2_frags(const uint16_t *__restrict__ w2, W2Frags &f
 }
 
 /* Features of the training box, [-1, 1]^4 (square-root stretch of d, |u|, |v|). */
+__device__ inline float feature_a(float a) { return (a - 0.625f) * (1.0f / 0.375f); }
 __device__ inline void features(float d, float au, float av, float a, float x[4])
 {
     x[0] = 2.0f * __builtin_sqrtf(fmaxf(d, 0.0f) * (1.0f / 30.0f)) - 1.0f;
     x[1] = 2.0f * __builtin_sqrtf(au * (1.0f / 3.0f)) - 1.0f;
     x[2] = 2.0f * __builtin_sqrtf(av * (1.0f / 3.0f)) - 1.0f;
-    x[3] = (a - 0.625f) * (1.0f / 0.375f);
+    x[3] = feature_a(a);
 }
 
 /*
  * Forward pass of 64 samples, sample = lane, features x.  h1s: this wave's
- * [64][kH1Stride] BF16 LDS tile.  p: FP32 parameters.  Returns the output
- * for the lane's sample.  Every lane of the wave must call it.
+ * [64][kH1Stride] BF16 LDS tile.  p: FP32 parameters.  With FOLD the fourth
+ * feature is the same for every sample and b1x (LDS) holds the layer-1 bias
+ * with its term added, b1 + W1[:, 3] x[3]; x[3] is then not read.  Returns the
+ * output for the lane's sample.  Every lane of the wave must call it.
  */
-__device__ inline float forward_wave(const float *__restrict__ p, const W2Frags &wf, const float x[4],
-                                     uint16_t *h1s)
+template <bool FOLD>
+__device__ inline float forward_wave(const float *__restrict__ p, const float *b1x, const W2Frags &wf,
+                                     const float x[4], uint16_t *h1s)
 {
     const int l = lane();
     // layer 1 (FP32), h1 rounded to BF16 into the lane's row
 #pragma unroll 4
     for (int o = 0; o < kMlpH; o += 2) {
-        float z0 = p[kOffB1 + o], z1 = p[kOffB1 + o + 1];
+        float z0 = FOLD ? b1x[o] : p[kOffB1 + o], z1 = FOLD ? b1x[o + 1] : p[kOffB1 + o + 1];
 #pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) {
+        for (int k = 0; k < (FOLD ? kMlpIn - 1 : kMlpIn); ++k) {
             z0 = fmaf(p[kOffW1 + o * kMlpIn + k], x[k], z0);
             z1 = fmaf(p[kOffW1 + (o + 1) * kMlpIn + k], x[k], z1);
         }
