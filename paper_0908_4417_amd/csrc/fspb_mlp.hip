@@ -252,16 +252,30 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpDev m, const float *__restri
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_reduce(float *__restrict__ params, float *__restrict__ m1,
-                                                    float *__restrict__ m2, uint16_t *__restrict__ w2,
-                                                    uint16_t *__restrict__ w2t, const float *__restrict__ partials,
-                                                    int n_waves, int adam, float lr, float b1, float b2, float eps,
-                                                    float bc1, float bc2, float *__restrict__ grad_out)
+/*
+ * Sum of the waves' gradient partials (in wave order, one thread per
+ * parameter: a fixed summation order, so training stays deterministic) and
+ * the Adam step.  The loads of 32 partials are issued before they are added.
+ */
+constexpr int kReduceBlock = 64;
+constexpr int kReduceBatch = 32;
+__global__ __launch_bounds__(kReduceBlock) void k_mlp_reduce(
+    float *__restrict__ params, float *__restrict__ m1, float *__restrict__ m2, uint16_t *__restrict__ w2,
+    uint16_t *__restrict__ w2t, const float *__restrict__ partials, int n_waves, int adam, float lr, float b1,
+    float b2, float eps, float bc1, float bc2, float *__restrict__ grad_out)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.x * kReduceBlock + threadIdx.x;
     if (k > kMlpParams) return;
     float gsum = 0.0f;
-    for (int w = 0; w < n_waves; ++w) gsum += partials[(size_t)w * kPartialStride + k];
+    int w = 0;
+    for (; w + kReduceBatch <= n_waves; w += kReduceBatch) {
+        float v[kReduceBatch];
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) v[u] = partials[(size_t)(w + u) * kPartialStride + k];
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) gsum += v[u];
+    }
+    for (; w < n_waves; ++w) gsum += partials[(size_t)w * kPartialStride + k];
     if (grad_out) grad_out[k] = gsum;
     if (!adam || k == kMlpParams) return;
     const float mm = b1 * m1[k] + (1.0f - b1) * gsum;
@@ -321,8 +335,8 @@ hipError_t launch_mlp_reduce(float *params, float *m1, float *m2, uint16_t *w2, 
                              int n_waves, int adam, float lr, float b1, float b2, float eps, float bc1, float bc2,
                              float *grad_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, params, m1, m2, w2, w2t,
-                       partials, n_waves, adam, lr, b1, b2, eps, bc1, bc2, grad_out);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + kReduceBlock - 1) / kReduceBlock), dim3(kReduceBlock), 0,
+                       s, params, m1, m2, w2, w2t, partials, n_waves, adam, lr, b1, b2, eps, bc1, bc2, grad_out);
     return hipGetLastError();
 }
 
