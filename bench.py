@@ -481,7 +481,8 @@ def batch_workload(steps, warmup):
            "nnz": total, "graph_ms": round(dev_ms, 4), "ms_per_step_wall": round(1e3 * wall / steps, 4),
            "nnz_per_s": round(total / (dev_ms * 1e-3), 1),
            "tuned_fill": {"waves_per_group": cfg.waves_per_group, "groups_per_cu": cfg.groups_per_cu,
-                          "order": "longest-first" if cfg.order == 0 else "plan", "fill_ms": round(cfg.fill_ms, 4)},
+                          "order": "longest-first" if cfg.order == 0 else "plan", "tile_rows": cfg.tile_rows,
+                          "beamlets_per_item": cfg.beamlets_per_item, "fill_ms": round(cfg.fill_ms, 4)},
            "fill_roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "kp_fill",
                              "bytes_per_launch": 8.0 * total}}

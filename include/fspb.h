@@ -331,6 +331,10 @@ typedef struct {
     int32_t order;               /* 0: longest beamlet rows first, 1: plan order */
     int32_t tuned;               /* out: 1 if the shape came from fspb_batch_tune or its cache */
     float fill_ms;               /* out: fill time measured for this shape by the tuner (0 if none) */
+    int32_t tile_rows;           /* grid rows a wave takes per step through a beamlet's tiles of 64
+                                    rows: 64, 128 or 256 (0 = 64) */
+    int32_t beamlets_per_item;   /* beamlets a workgroup takes per fetch from the queue: 1, 2 or 4
+                                    (0 = 1) */
     int32_t reserved;
 } fspb_batch_config;
 
@@ -357,10 +361,12 @@ fspb_status fspb_batch_bind(fspb_batch *batch, int32_t plan, int64_t *indptr, in
                             float *values, int64_t capacity);
 
 /*
- * Time every fill launch shape on this batch (outputs must be bound), keep the
+ * Time fill launch shapes on this batch (outputs must be bound), keep the
  * fastest and remember it for batches of the same shape class in this process
  * (number of plans, beamlets and nonzeros rounded to two digits, term count).
- * Synchronises `stream`.
+ * First every workgroup size, grid and queue order (tile_rows 64, one beamlet
+ * per item), then every tile_rows and beamlets_per_item for the best of those.
+ * Every shape gives the same bits.  Synchronises `stream`.
  */
 fspb_status fspb_batch_tune(fspb_batch *batch, void *stream);
 

@@ -69,7 +69,8 @@ class FspbTiming(C.Structure):
 
 class FspbBatchConfig(C.Structure):
     _fields_ = [("waves_per_group", C.c_int32), ("groups_per_cu", C.c_int32), ("order", C.c_int32),
-                ("tuned", C.c_int32), ("fill_ms", C.c_float), ("reserved", C.c_int32)]
+                ("tuned", C.c_int32), ("fill_ms", C.c_float), ("tile_rows", C.c_int32),
+                ("beamlets_per_item", C.c_int32), ("reserved", C.c_int32)]
 
 
 class FspbTrainConfig(C.Structure):
@@ -262,8 +263,8 @@ def fspb_batch_get_config(batch):
     return c
 
 
-def fspb_batch_set_config(batch, waves_per_group, groups_per_cu, order):
-    c = FspbBatchConfig(waves_per_group, groups_per_cu, order, 0, 0.0, 0)
+def fspb_batch_set_config(batch, waves_per_group, groups_per_cu, order, tile_rows=64, beamlets_per_item=1):
+    c = FspbBatchConfig(waves_per_group, groups_per_cu, order, 0, 0.0, tile_rows, beamlets_per_item, 0)
     return _check(lib().fspb_batch_set_config(batch, C.byref(c)))
 
 

@@ -159,7 +159,9 @@ hipError_t launch_batch_wave(int stage, const PlanDev *const *plans, const int64
                              int grid, hipStream_t s);   // stage 0 prep, 1 raytrace, 2 count
 hipError_t launch_batch_scan(const PlanDev *const *plans, const OutDev *outs, int n_plans, hipStream_t s);
 hipError_t launch_batch_reset(int *counters, int n, hipStream_t s);
+/* per_item work items per queue fetch; tile_group consecutive tiles per wave step. */
 hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const OutDev *outs, const int2 *items,
-                             int n_items, int *counter, int grid, size_t lds, hipStream_t s);
+                             int n_items, int *counter, int per_item, int tile_group, int grid, size_t lds,
+                             hipStream_t s);
 
 }  // namespace fspb

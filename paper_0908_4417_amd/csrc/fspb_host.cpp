@@ -1110,7 +1110,7 @@ struct fspb_batch {
     int32_t max_terms = 1;
     size_t lds = 0;
     int cus = 256;
-    fspb_batch_config cfg{4, 4, 0, 0, 0.0f, 0};
+    fspb_batch_config cfg{4, 4, 0, 0, 0.0f, fspb::kRowsPerTile, 1, 0};
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1138,6 +1138,8 @@ int wave_grid(const fspb_batch *b, int64_t items)
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)b->cus * 16));
 }
 
+fspb_status launch_fill_only(fspb_batch *b, hipStream_t s, bool reset);
+
 fspb_status enqueue_stages(fspb_batch *b, hipStream_t s, bool with_fill)
 {
     FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
@@ -1148,20 +1150,23 @@ fspb_status enqueue_stages(fspb_batch *b, hipStream_t s, bool with_fill)
     }
     FSPB_HIP(fspb::launch_batch_scan(b->d_plans, b->d_outs, b->n, s), "launch batch scan");
     if (with_fill && b->n_items > 0) {
-        const int grid = std::max(1, std::min(b->n_items, b->cfg.groups_per_cu * b->cus));
-        FSPB_HIP(fspb::launch_batch_fill(b->max_terms, b->cfg.waves_per_group, b->d_plans, b->d_outs,
-                                         b->d_items[b->cfg.order], b->n_items, b->d_counter, grid, b->lds, s),
-                 "launch batch fill");
+        const fspb_status r = launch_fill_only(b, s, false);
+        if (r != FSPB_OK) return r;
     }
     return FSPB_OK;
 }
 
-fspb_status launch_fill_only(fspb_batch *b, hipStream_t s)
+/* The batched fill in the current shape (reset: clear the queue counter first). */
+fspb_status launch_fill_only(fspb_batch *b, hipStream_t s, bool reset)
 {
-    FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
-    const int grid = std::max(1, std::min(b->n_items, b->cfg.groups_per_cu * b->cus));
+    if (reset) FSPB_HIP(fspb::launch_batch_reset(b->d_counter, 1, s), "launch batch reset");
+    const int per_item = b->cfg.beamlets_per_item > 0 ? b->cfg.beamlets_per_item : 1;
+    const int tile_group = b->cfg.tile_rows > 0 ? b->cfg.tile_rows / fspb::kRowsPerTile : 1;
+    const int fetches = (b->n_items + per_item - 1) / per_item;
+    const int grid = std::max(1, std::min(fetches, b->cfg.groups_per_cu * b->cus));
     FSPB_HIP(fspb::launch_batch_fill(b->max_terms, b->cfg.waves_per_group, b->d_plans, b->d_outs,
-                                     b->d_items[b->cfg.order], b->n_items, b->d_counter, grid, b->lds, s),
+                                     b->d_items[b->cfg.order], b->n_items, b->d_counter, per_item, tile_group, grid,
+                                     b->lds, s),
              "launch batch fill");
     return FSPB_OK;
 }
@@ -1169,7 +1174,10 @@ fspb_status launch_fill_only(fspb_batch *b, hipStream_t s)
 bool valid_config(const fspb_batch_config &c)
 {
     return (c.waves_per_group == 2 || c.waves_per_group == 4 || c.waves_per_group == 8) && c.groups_per_cu >= 1 &&
-           c.groups_per_cu <= 16 && (c.order == 0 || c.order == 1);
+           c.groups_per_cu <= 16 && (c.order == 0 || c.order == 1) &&
+           (c.tile_rows == 0 || c.tile_rows == 64 || c.tile_rows == 128 || c.tile_rows == 256) &&
+           (c.beamlets_per_item == 0 || c.beamlets_per_item == 1 || c.beamlets_per_item == 2 ||
+            c.beamlets_per_item == 4);
 }
 
 BatchKey key_of(const fspb_batch *b)
@@ -1358,6 +1366,8 @@ fspb_status fspb_batch_set_config(fspb_batch *b, const fspb_batch_config *cfg)
     if (!b || !cfg) return fail(FSPB_ERR_INVALID, "batch or cfg is NULL");
     if (!valid_config(*cfg)) return fail(FSPB_ERR_INVALID, "invalid launch shape");
     b->cfg = *cfg;
+    if (b->cfg.tile_rows == 0) b->cfg.tile_rows = fspb::kRowsPerTile;
+    if (b->cfg.beamlets_per_item == 0) b->cfg.beamlets_per_item = 1;
     b->cfg.tuned = 0;
     b->cfg.fill_ms = 0.0f;
     b->drop_graph();
@@ -1376,31 +1386,49 @@ fspb_status fspb_batch_tune(fspb_batch *b, void *stream)
     hipEvent_t e0, e1;
     FSPB_HIP(hipEventCreate(&e0), "create event");
     FSPB_HIP(hipEventCreate(&e1), "create event");
-    const fspb_batch_config saved = b->cfg;
-    fspb_batch_config best = saved;
+    fspb_batch_config best = b->cfg;
     float best_ms = 1e30f;
-    for (int order = 0; order < 2; ++order)
+    auto trial = [&](const fspb_batch_config &c) -> fspb_status {
+        b->cfg = c;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            FSPB_HIP(hipEventRecord(e0, s), "record event");
+            const fspb_status r = launch_fill_only(b, s, true);
+            if (r != FSPB_OK) return r;
+            FSPB_HIP(hipEventRecord(e1, s), "record event");
+            FSPB_HIP(hipEventSynchronize(e1), "wait event");
+            float t = 0.0f;
+            FSPB_HIP(hipEventElapsedTime(&t, e0, e1), "elapsed");
+            ms = std::min(ms, t);
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        return FSPB_OK;
+    };
+    const fspb_batch_config saved = b->cfg;
+    // workgroup size, grid and queue order at the base tile shape
+    for (int order = 0; order < 2 && st == FSPB_OK; ++order)
         for (int w : {2, 4, 8})
-            for (int g : {1, 2, 4, 8}) {
-                b->cfg = fspb_batch_config{w, g, order, 0, 0.0f, 0};
-                float ms = 1e30f;
-                for (int rep = 0; rep < 2; ++rep) {
-                    FSPB_HIP(hipEventRecord(e0, s), "record event");
-                    st = launch_fill_only(b, s);
-                    if (st != FSPB_OK) return st;
-                    FSPB_HIP(hipEventRecord(e1, s), "record event");
-                    FSPB_HIP(hipEventSynchronize(e1), "wait event");
-                    float t = 0.0f;
-                    FSPB_HIP(hipEventElapsedTime(&t, e0, e1), "elapsed");
-                    ms = std::min(ms, t);
-                }
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = b->cfg;
-                }
-            }
+            for (int g : {1, 2, 4, 8})
+                if (st == FSPB_OK) st = trial(fspb_batch_config{w, g, order, 0, 0.0f, fspb::kRowsPerTile, 1, 0});
+    // then the tile rows per wave step and the beamlets per work item for that launch
+    const fspb_batch_config base = best;
+    for (int rows : {64, 128, 256})
+        for (int per : {1, 2, 4}) {
+            if (st != FSPB_OK || (rows == fspb::kRowsPerTile && per == 1)) continue;
+            fspb_batch_config c = base;
+            c.tile_rows = rows;
+            c.beamlets_per_item = per;
+            st = trial(c);
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (st != FSPB_OK) {
+        b->cfg = saved;
+        return st;
+    }
     best.tuned = 1;
     best.fill_ms = best_ms;
     b->cfg = best;

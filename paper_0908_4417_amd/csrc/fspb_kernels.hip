@@ -750,8 +750,9 @@ __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readla
  * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K);
  * EM: how erf is read (erf_mirrored_mode).
  */
+/* tile_group: consecutive 64-row tiles a wave takes per step (the batched fill's tuned shape). */
 template <int K, int W, bool GUARD, bool SURR, bool GEN = false, int EM = 0>
-__device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem)
+__device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem, int tile_group = 1)
 {
     const BeamletRec &R = P.rec[j];
     const int n_tiles = R.n_tiles;
@@ -878,7 +879,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         __syncthreads();
     }
 
-    for (int tl = wave; tl < n_tiles; tl += W) {
+    for (int tg = wave * tile_group; tg < n_tiles; tg += W * tile_group)
+    for (int tl = tg; tl < tg + tile_group && tl < n_tiles; ++tl) {
         const int members = __builtin_amdgcn_readfirstlane(tile_count[tile0 + tl]);
         if (members == 0) continue;
         const int64_t out0 = row_base + __builtin_amdgcn_readfirstlane(s_tpre[tl]);
@@ -1117,30 +1119,35 @@ __global__ __launch_bounds__(kScanBlock) void kp_scan(const PlanDev *const *__re
 
 // amdgpu_waves_per_eu(4): a register budget that leaves room for at least four waves per SIMD
 // (it is a lower bound on occupancy, not a cap)
+// Work items (plan, beamlet) come from a queue, per_item consecutive ones per fetch; a wave
+// takes tile_group consecutive tiles of a beamlet per step.
 template <int K, int W>
 __global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(4))) void kp_fill(const PlanDev *const *__restrict__ plans,
                                                      const OutDev *__restrict__ outs,
                                                      const int2 *__restrict__ items, int n_items,
-                                                     int *__restrict__ counter)
+                                                     int *__restrict__ counter, int per_item, int tile_group)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int w = s_item;
+        const int w0 = s_item * per_item;
         __syncthreads();
-        if (w >= n_items) break;
-        const int2 it = items[w];
-        const PlanDev &P = *plans[it.x];
-        // each plan in the erf table form of its own fill (identical results to it)
-        switch (P.erf_mode) {
-        case 3: fill_beamlet<K, W, true, false, false, 3>(P, outs[it.x], it.y, smem); break;
-        case 2: fill_beamlet<K, W, true, false, false, 2>(P, outs[it.x], it.y, smem); break;
-        case 1: fill_beamlet<K, W, true, false, false, 1>(P, outs[it.x], it.y, smem); break;
-        default: fill_beamlet<K, W, true, false, false, 0>(P, outs[it.x], it.y, smem); break;
+        if (w0 >= n_items) break;
+        const int w1 = min(n_items, w0 + per_item);
+        for (int w = w0; w < w1; ++w) {
+            const int2 it = items[w];
+            const PlanDev &P = *plans[it.x];
+            // each plan in the erf table form of its own fill (identical results to it)
+            switch (P.erf_mode) {
+            case 3: fill_beamlet<K, W, true, false, false, 3>(P, outs[it.x], it.y, smem, tile_group); break;
+            case 2: fill_beamlet<K, W, true, false, false, 2>(P, outs[it.x], it.y, smem, tile_group); break;
+            case 1: fill_beamlet<K, W, true, false, false, 1>(P, outs[it.x], it.y, smem, tile_group); break;
+            default: fill_beamlet<K, W, true, false, false, 0>(P, outs[it.x], it.y, smem, tile_group); break;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -1297,25 +1304,36 @@ hipError_t launch_batch_reset(int *counters, int n, hipStream_t s)
 
 template <int K>
 static hipError_t launch_kp_fill_k(int W, const PlanDev *const *plans, const OutDev *outs, const int2 *items,
-                                   int n_items, int *counter, int grid, size_t lds, hipStream_t s)
+                                   int n_items, int *counter, int per_item, int tile_group, int grid, size_t lds,
+                                   hipStream_t s)
 {
     const dim3 g(grid);
     switch (W) {
-    case 2: hipLaunchKernelGGL((kp_fill<K, 2>), g, dim3(2 * kWave), lds, s, plans, outs, items, n_items, counter); break;
-    case 8: hipLaunchKernelGGL((kp_fill<K, 8>), g, dim3(8 * kWave), lds, s, plans, outs, items, n_items, counter); break;
-    default: hipLaunchKernelGGL((kp_fill<K, 4>), g, dim3(4 * kWave), lds, s, plans, outs, items, n_items, counter); break;
+    case 2:
+        hipLaunchKernelGGL((kp_fill<K, 2>), g, dim3(2 * kWave), lds, s, plans, outs, items, n_items, counter, per_item,
+                           tile_group);
+        break;
+    case 8:
+        hipLaunchKernelGGL((kp_fill<K, 8>), g, dim3(8 * kWave), lds, s, plans, outs, items, n_items, counter, per_item,
+                           tile_group);
+        break;
+    default:
+        hipLaunchKernelGGL((kp_fill<K, 4>), g, dim3(4 * kWave), lds, s, plans, outs, items, n_items, counter, per_item,
+                           tile_group);
+        break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_batch_fill(int K, int W, const PlanDev *const *plans, const OutDev *outs, const int2 *items,
-                             int n_items, int *counter, int grid, size_t lds, hipStream_t s)
+                             int n_items, int *counter, int per_item, int tile_group, int grid, size_t lds,
+                             hipStream_t s)
 {
     switch (K) {
-    case 1: return launch_kp_fill_k<1>(W, plans, outs, items, n_items, counter, grid, lds, s);
-    case 2: return launch_kp_fill_k<2>(W, plans, outs, items, n_items, counter, grid, lds, s);
-    case 3: return launch_kp_fill_k<3>(W, plans, outs, items, n_items, counter, grid, lds, s);
-    default: return launch_kp_fill_k<4>(W, plans, outs, items, n_items, counter, grid, lds, s);
+    case 1: return launch_kp_fill_k<1>(W, plans, outs, items, n_items, counter, per_item, tile_group, grid, lds, s);
+    case 2: return launch_kp_fill_k<2>(W, plans, outs, items, n_items, counter, per_item, tile_group, grid, lds, s);
+    case 3: return launch_kp_fill_k<3>(W, plans, outs, items, n_items, counter, per_item, tile_group, grid, lds, s);
+    default: return launch_kp_fill_k<4>(W, plans, outs, items, n_items, counter, per_item, tile_group, grid, lds, s);
     }
 }
 

@@ -292,8 +292,8 @@ class Batch:
     def config(self):
         return L.fspb_batch_get_config(self.handle)
 
-    def set_config(self, waves_per_group, groups_per_cu, order):
-        L.fspb_batch_set_config(self.handle, waves_per_group, groups_per_cu, order)
+    def set_config(self, waves_per_group, groups_per_cu, order, tile_rows=64, beamlets_per_item=1):
+        L.fspb_batch_set_config(self.handle, waves_per_group, groups_per_cu, order, tile_rows, beamlets_per_item)
 
     def run(self, stream=None):
         L.fspb_batch_run(self.handle, self._stream(stream))

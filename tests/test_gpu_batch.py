@@ -76,15 +76,18 @@ def test_small_batch_equals_single_plans(torch_gpu, oracle_lib):
         for k, o in enumerate(batch.outputs()):
             assert torch.equal(o.indices, outs[k][1]) and torch.equal(o.values, outs[k][2]), (rep, k)
     # every launch shape gives the same bits
-    for w, g, order in [(2, 1, 1), (8, 8, 0), (4, 2, 1)]:
-        batch.set_config(w, g, order)
+    for w, g, order, rows, per in [(2, 1, 1, 64, 1), (8, 8, 0, 128, 2), (4, 2, 1, 256, 4), (4, 4, 0, 128, 1),
+                                   (2, 4, 0, 64, 4)]:
+        batch.set_config(w, g, order, rows, per)
         batch.run()
         torch.cuda.synchronize()
         for k, o in enumerate(batch.outputs()):
-            assert torch.equal(o.values, outs[k][2]), (w, g, order, k)
+            assert torch.equal(o.indices, outs[k][1]), (w, g, order, rows, per, k)
+            assert torch.equal(o.values, outs[k][2]), (w, g, order, rows, per, k)
     cfg = batch.tune()
     _say(f"  tuned: waves/group={cfg.waves_per_group} groups/CU={cfg.groups_per_cu} order={cfg.order} "
-         f"fill={cfg.fill_ms:.3f} ms")
+         f"tile rows={cfg.tile_rows} beamlets/item={cfg.beamlets_per_item} fill={cfg.fill_ms:.3f} ms")
+    assert cfg.tile_rows in (64, 128, 256) and cfg.beamlets_per_item in (1, 2, 4)
     assert cfg.tuned == 1
     batch.run()
     torch.cuda.synchronize()
