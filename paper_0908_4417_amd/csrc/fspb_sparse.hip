@@ -567,6 +567,10 @@ constexpr uint32_t kRunFlag = 0x80000000u;   // run of invalid columns (in the r
 constexpr int kRowChunks = 4;                // chunks of 64 entries whose loads are in flight together
 constexpr int kXcds = 8;                     // workgroups are handed to the 8 XCDs in turn
 
+/* Value of the lane below (above), through a whole-wave DPP shift; lane 0 (63) takes `edge`. */
+__device__ inline int from_lane_below(int v, int edge) { return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false); }
+__device__ inline int from_lane_above(int v, int edge) { return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false); }
+
 /* Run key of a column: its bucket, or -2 (outside [0, n_voxels)). */
 __device__ inline int run_key(int col, int n_voxels)
 {
@@ -624,11 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const int64_t *__restrict_
             const bool in = e < e1;
             const int col = cols[u];
             const int k = in ? run_key(col, n_voxels) : -3;
-            int cp = __shfl_up(col, 1, kWave), kp = __shfl_up(k, 1, kWave);
-            if (lane == 0) {
-                cp = prev_col;
-                kp = prev_k;
-            }
+            const int cp = from_lane_below(col, prev_col), kp = from_lane_below(k, prev_k);
             runs += (uint32_t)__popcll(__ballot(in && k != kp));
             down = down || (in && kp != -1 && col <= cp);
             prev_col = __builtin_amdgcn_readlane(col, kWave - 1);
@@ -696,14 +696,11 @@ __global__ __launch_bounds__(kBlock) void k_run_emit(const int64_t *__restrict__
             const bool in = e < e1;
             const int col = cols[u];
             const int k = in ? run_key(col, n_voxels) : -3;
-            int kp = __shfl_up(k, 1, kWave);
-            if (lane == 0) kp = prev_k;
-            int kn = __shfl_down(k, 1, kWave);
-            if (lane == kWave - 1) {
-                const int nx = u + 1 < kRowChunks ? __builtin_amdgcn_readlane(cols[u + 1 < kRowChunks ? u + 1 : u], 0)
-                                                  : after;
-                kn = e + 1 < e1 ? run_key(nx, n_voxels) : -3;
-            }
+            const int kp = from_lane_below(k, prev_k);
+            // key of the entry after lane 63 (the next chunk's first, or none at the row's end)
+            const int64_t e_next = c + (u + 1) * kWave;
+            const int nx = u + 1 < kRowChunks ? __builtin_amdgcn_readlane(cols[u + 1 < kRowChunks ? u + 1 : u], 0) : after;
+            const int kn = from_lane_above(k, e_next < e1 ? run_key(nx, n_voxels) : -3);
             const bool start = in && k != kp;
             const bool end = in && kn != k;
             const uint64_t m = __ballot(start);
