@@ -23,10 +23,11 @@ Printed as one JSON line.  Besides the contract fields it carries
 HIP-event duration, against 8 TB/s), `cpu_baseline` (the FP64 oracle on a
 bounded sample of the same workload, on this host's cores),
 `error_vs_oracle` (the timed plan's CSR against the oracle's rows of that
-sample), per-kernel times, and beside the default workload the pelvis
-(`pelvis`), the 32-plan batch (`batch32`), Eq. 1 (`eq1`), the rows beyond the
-plain path (`next_rows`) and the learned surrogate judged against the oracle
-(`surrogate`).
+sample, and its depth tables against the oracle's), per-kernel times, and
+beside the default workload the pelvis (`pelvis`, with its own error against
+the oracle over every row), the 32-plan batch (`batch32`), Eq. 1 (`eq1`),
+the rows beyond the plain path (`next_rows`) and the learned surrogate judged
+against the oracle (`surrogate`).
 """
 from __future__ import annotations
 
@@ -208,6 +209,17 @@ def cpu_baseline(prob, target_s, n_beamlets, gpu_csr=None):
         if err is not None:
             gi, gv, gc = _gpu_rows(indptr_h, gpu_csr[1], gpu_csr[2], sel.astype(np.int64))
             err.add(off, idx, val, gi, gv, gc)
+    table_err = None
+    if err is not None:
+        # the plan's depth tables (Sec. 2.2) against the oracle's, in cm
+        from paper_0908_4417_amd import Plan
+        plan = Plan(prob, "cuda:0")
+        plan.raytrace()
+        tab, toff = plan.tables()
+        otab, ooff = ora.tables()
+        if np.array_equal(toff, ooff):
+            table_err = float(f"{np.max(np.abs(tab.astype(np.float64) - otab)):.3e}")
+        del plan
     cores = oracle.max_threads()
     # the same oracle on one thread, over the first 64 rows of the same order
     sel = np.sort(order[:64])
@@ -224,7 +236,27 @@ def cpu_baseline(prob, target_s, n_beamlets, gpu_csr=None):
                      f"FP64 C oracle, OpenMP over rows",
            "one_thread": {"value": round(int(off[-1]) / dt1, 1), "unit": "D_ij nonzeros/s",
                           "sample": f"first 64 rows of the same order, {int(off[-1])} nonzeros in {dt1:.2f} s"}}
-    return out, (err.result() if err is not None else None)
+    res = None
+    if err is not None:
+        res = err.result()
+        res["max_table_err_cm"] = table_err      # None if the table layouts differ
+    return out, res
+
+
+def oracle_error(prob, gpu_csr):
+    """Every row of a plan's GPU CSR against the oracle's (64 rows at a time), as the
+    cpu_baseline leg does for the timed plan."""
+    import oracle
+    ora = oracle.OraclePlan(prob)
+    indptr_h = gpu_csr[0].cpu().numpy()
+    err = OracleError(float(gpu_csr[2].max().item()))
+    n = len(indptr_h) - 1
+    for j0 in range(0, n, 64):
+        sel = np.arange(j0, min(j0 + 64, n))
+        off, idx, val = ora.rows(sel, ora.counts_of(sel))
+        gi, gv, gc = _gpu_rows(indptr_h, gpu_csr[1], gpu_csr[2], sel.astype(np.int64))
+        err.add(off, idx, val, gi, gv, gc)
+    return err.result()
 
 
 def surrogate_comparison(epochs, cpu=True):
@@ -657,9 +689,12 @@ def main():
     torch.cuda.empty_cache()
     if args.workload == 1 and not args.headline_only:
         # the other two workloads of the metric, measured by the same code
-        pel, _, _ = plan_workload(2, args.steps, args.warmup, args.pipeline)
+        pel, pcsr, pprob = plan_workload(2, args.steps, args.warmup, args.pipeline)
         pel.pop("wall_s")
         pel["nnz_per_s"] = round(pel["nnz"] / (pel["ms_per_step"] * 1e-3), 1)
+        if not args.no_cpu_baseline and args.cpu_seconds > 0:
+            pel["error_vs_oracle"] = oracle_error(pprob, pcsr)
+        del pcsr
         out["pelvis"] = pel
         torch.cuda.empty_cache()
         out["batch32"] = batch_workload(max(args.steps // 2, 3), 1)[0]
