@@ -658,14 +658,15 @@ __device__ inline float dose_value(const FillConst<K> &c, const float2 *__restri
 {
     const float r = __builtin_amdgcn_rcpf(s + c.tA);   // 1 / t'
     const float u = U * r, v = V * r;
-    // radiological depth at O': linear interpolation in the table (last entry has slope 0)
+    // radiological depth at O': linear interpolation in the table, one FMA in the intercept form
+    // (last entry has slope 0)
     const float tau = __builtin_amdgcn_fmed3f(s * c.inv_step, 0.0f, c.tau_max);
     const float2 q = tab[(int)tau];
-    const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
+    const float d = fmaf(tau, q.y, q.x);
     // depth dose times SAD^2, held at the last node
     const float x = __builtin_amdgcn_fmed3f(d * c.pdd_inv, 0.0f, c.pdd_max);
     const float2 qp = pdd[(int)x];
-    const float A = fmaf(__builtin_amdgcn_fractf(x), qp.y, qp.x) * r * r;
+    const float A = fmaf(x, qp.y, qp.x) * r * r;
     // lateral profile, Eq. 3
     float L = 0.0f;
 #pragma unroll
@@ -704,10 +705,10 @@ __device__ inline float dose_value_gen(const FillConst<K> &c, const float2 *__re
     const float u = U * r, v = V * r;
     const float tau = __builtin_amdgcn_fmed3f(s * c.inv_step, 0.0f, c.tau_max);
     const float2 q = tab[(int)tau];
-    const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
+    const float d = fmaf(tau, q.y, q.x);
     const float xa = __builtin_amdgcn_fmed3f(d * c.a_inv, 0.0f, c.a_max);
     const float2 qa = sA[(int)xa];
-    const float A = fmaf(__builtin_amdgcn_fractf(xa), qa.y, qa.x) * r * r;
+    const float A = fmaf(xa, qa.y, qa.x) * r * r;
     const float xc = __builtin_amdgcn_fmed3f(d * c.c_inv, 0.0f, c.c_max);
     const int kc = (int)xc;
     const float fc = __builtin_amdgcn_fractf(xc);
@@ -804,7 +805,9 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const int64_t capacity = O.capacity;
     const int64_t row_base = uniform64(O.indptr[j] - O.indptr[O.row0]);
 
-    // ---- LDS: erf table, depth table, depth dose (times SAD^2), tile prefix
+    // ---- LDS: erf table, depth table, depth dose (times SAD^2), tile prefix; the depth table
+    // and the depth dose (or the general form's A row) as (intercept, slope) in their own
+    // table coordinate, value = x slope + intercept for x in [k, k + 1]
     float2 *s_erf = reinterpret_cast<float2 *>(smem);
     constexpr int kErfPairs = SE ? 2 * kErfIntervals : kErfIntervals;
     float2 *s_tab = s_erf + kErfPairs;
@@ -832,7 +835,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
         for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
-            s_tab[i] = make_float2(d0, (i + 1 < n_table ? tab[i + 1] : d0) - d0);
+            const float sl = (i + 1 < n_table ? tab[i + 1] : d0) - d0;
+            s_tab[i] = make_float2(fmaf(-(float)i, sl, d0), sl);
         }
         const float sad2 = sad_f * sad_f;
         if (GEN) {
@@ -844,7 +848,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             for (int i = tid; i < na; i += kB) {
                 const float v0 = fmaf(ft, a1[i] - a0[i], a0[i]);
                 const float v1 = i + 1 < na ? fmaf(ft, a1[i + 1] - a0[i + 1], a0[i + 1]) : v0;
-                s_pdd[i] = make_float2(v0 * sad2, (v1 - v0) * sad2);
+                const float sl = (v1 - v0) * sad2;
+                s_pdd[i] = make_float2(fmaf(-(float)i, sl, v0 * sad2), sl);
             }
             const int nc = P.n_cdepth, ntab = 3 * P.n_terms * nc;
             const gptr<const float> ct = as_global<const float>(P.ctab);
@@ -858,7 +863,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             const float scale = FOLD_W ? sad2 * P.w4[0] : sad2;
             for (int i = tid; i < n_pdd; i += kB) {
                 const float p0 = pd[i];
-                s_pdd[i] = make_float2(p0 * scale, ((i + 1 < n_pdd ? pd[i + 1] : p0) - p0) * scale);
+                const float sl = ((i + 1 < n_pdd ? pd[i + 1] : p0) - p0) * scale;
+                s_pdd[i] = make_float2(fmaf(-(float)i, sl, p0 * scale), sl);
             }
         }
     }
@@ -980,7 +986,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                 const float au = fabsf(Uv * rr_), av = fabsf(Vv * rr_);
                 const float tau = __builtin_amdgcn_fmed3f(sv * c.inv_step, 0.0f, c.tau_max);
                 const float2 q = s_tab[(int)tau];
-                const float d = fmaf(__builtin_amdgcn_fractf(tau), q.y, q.x);
+                const float d = fmaf(tau, q.y, q.x);
                 const bool in_box = member && mlp_ok && d <= kMlpDMax && au <= kMlpUVMax &&
                                     av <= kMlpUVMax;
                 float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
