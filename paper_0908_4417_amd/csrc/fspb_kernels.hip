@@ -1049,9 +1049,70 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
                 rcur = rnext;
             }
         };
+        // dense tiles whose entries fit: a lane takes two consecutive candidates of one row
+        // (pair slot q of a row holds its candidates 2q and 2q + 1), so that the row lookup,
+        // the row walk and the column arithmetic serve two entries; each entry's value is
+        // computed exactly as in a chunk of single candidates
+        auto pair_chunk = [&](const int q, const int rr, const int pexcl, const int ptotal) {
+            const int ra = rr << 2;
+            auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
+            auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
+            const int k0 = (q - from_row(pexcl)) << 1;
+            const int e0 = from_row(excl) + k0;            // tile-local entry of candidate k0
+            const int cn = from_row(cnt);
+            const int col = from_row(cb) + k0;
+            const float sl = from_row_f(s_lo), ul = from_row_f(U_lo), vl = from_row_f(V_lo);
+            if (q < ptotal) {
+                const bool two = k0 + 1 < cn;
+                auto value = [&](float kf) {
+                    if (GEN)
+                        return dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                                                     fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
+                    return dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                                    fmaf(kf, V1f, vl));
+                };
+                // the second candidate of a row's last, odd slot is evaluated at the first (and not stored)
+                const float D0 = value((float)k0), D1 = value((float)(two ? k0 + 1 : k0));
+                __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, e0 << 2, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D0), rs_val, e0 << 2, 0, 0);
+                if (two) {
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(col + 1), rs_idx, (e0 + 1) << 2, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D1), rs_val, (e0 + 1) << 2, 0, 0);
+                }
+            }
+        };
+        auto walk_pairs = [&]() {
+            // the row walk of walk2 over pair slots: bit b of (mhi:mlo) marks a row whose
+            // first pair slot is c0 + b
+            const int np = (cnt + 1) >> 1;
+            const int pincl = wave_incl_scan(np);
+            const int pexcl = pincl - np;
+            const int ptotal = readlane(pincl, kWave - 1);
+            int rc = 0;
+            for (int c0 = 0; c0 < ptotal; c0 += 2 * kWave) {
+                uint64_t mlo = 0, mhi = 0;
+                int rnext = rc;
+                for (int q = rc + 1; q < n_ne; ++q) {
+                    const int b = readlane(pexcl, q) - c0;
+                    if (b > 2 * kWave) break;
+                    rnext = q;
+                    if (b == 2 * kWave) break;
+                    if (b < kWave) mlo |= 1ull << b;
+                    else mhi |= 1ull << (b - kWave);
+                }
+                const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
+                const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rc));
+                const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rc + __popcll(nlo))));
+                pair_chunk(c0 + lane, r1, pexcl, ptotal);
+                pair_chunk(c0 + kWave + lane, r2, pexcl, ptotal);
+                rc = rnext;
+            }
+        };
         if (!SURR) {
             if (fits) {
-                if (dense) walk2(std::true_type{}, std::true_type{});
+                if (dense) walk_pairs();
                 else walk2(std::false_type{}, std::true_type{});
             } else {
                 walk2(std::false_type{}, std::false_type{});
