@@ -50,8 +50,8 @@ METRIC = "D_ij nonzeros/s + ms per 9-field plan; surrogate vs analytic at <=0.5%
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", type=int, default=1, choices=[1, 2, 3],
                     help="1: 128^3 slab (default); 2: 256x256x100 pelvis; "
                          "3: 32 uneven plans as one captured graph")
