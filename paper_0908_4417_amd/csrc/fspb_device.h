@@ -37,6 +37,13 @@ struct alignas(16) BeamletRec {
     double step;          // spacing of the table points on AB
     double sad;
     double cu_sad, cv_sad;  // cutoff / SAD: |U| <= cu_sad t', |V| <= cv_sad t'
+    // VOI row interval: t', U and V of the centre of voxel (0, iy, iz), relative to S, are
+    // row_t[0] + iy row_t[1] + iz row_t[2] (likewise row_u, row_v); dx holds their change
+    // per column; the row's four conditions c0 + c1[c] x <= 0 have r1[c] = 1 / c1[c] (0 if
+    // c1[c] = 0)
+    double row_t[3], row_u[3], row_v[3];
+    double dx[3];
+    double c1[4], r1[4];
     float half_a, half_b;   // a/2, b/2 at the iso plane
     float tA_f, inv_step_f;
     float sad_f, tau_max_f;   // SAD; n_table - 1

@@ -648,6 +648,24 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
                 R.sad = B.sad;
                 R.cu_sad = cu / B.sad;
                 R.cv_sad = cv / B.sad;
+                {
+                    // VOI row interval coefficients, once per beamlet (the count and the fill
+                    // solve every grid row from them)
+                    const V3 w0 = V3{g->origin[0], g->origin[1], g->origin[2]} - S;
+                    const V3 axis[3] = {e, eu, ev};
+                    double *row[3] = {R.row_t, R.row_u, R.row_v};
+                    for (int k = 0; k < 3; ++k) {
+                        row[k][0] = dot(w0, axis[k]);
+                        row[k][1] = g->spacing[1] * axis[k].y;
+                        row[k][2] = g->spacing[2] * axis[k].z;
+                        R.dx[k] = g->spacing[0] * axis[k].x;
+                    }
+                    R.c1[0] = R.dx[1] - R.cu_sad * R.dx[0];
+                    R.c1[1] = -R.dx[1] - R.cu_sad * R.dx[0];
+                    R.c1[2] = R.dx[2] - R.cv_sad * R.dx[0];
+                    R.c1[3] = -R.dx[2] - R.cv_sad * R.dx[0];
+                    for (int c = 0; c < 4; ++c) R.r1[c] = R.c1[c] != 0.0 ? 1.0 / R.c1[c] : 0.0;
+                }
                 R.half_a = (float)(0.5 * B.beamlet_a);
                 R.half_b = (float)(0.5 * B.beamlet_b);
                 double tA, tB;

@@ -59,6 +59,27 @@ __device__ inline T wave_sum(T x)
     return x;
 }
 
+/*
+ * 32-bit integers: the inclusive scan by DPP, without LDS round trips.  Row
+ * shifts by 1, 2, 4 and 8 lanes scan each row of 16 lanes (lanes shifted in
+ * from outside the row read 0); then rows 1 and 3 add the last lane of the
+ * row below (row_bcast:15) and rows 2 and 3 add lane 31 (row_bcast:31).
+ * Every lane of the wave must be active.
+ */
+__device__ inline int wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+/* Wave total of 32-bit integers (every lane active), the same on every lane. */
+__device__ inline int wave_sum(int x) { return __builtin_amdgcn_readlane(wave_incl_scan(x), kWave - 1); }
+
 /* ---------------------------------------------------------------- prep */
 
 /* Mask bits and member extent of grid row `row` (= iz * ny + iy); one wave. */
@@ -277,55 +298,44 @@ __global__ __launch_bounds__(kBlock) void k_raytrace(const PlanDev *__restrict__
 struct RowAffine { double t0, U0, V0; };
 
 /*
- * The FP64 beamlet and grid quantities the VOI row interval needs, read once
- * per beamlet (or tile) into registers, and the four inequalities
- * c0 + c1 x <= 0 in the column x of a grid row: c1 (and 1/c1) are the same for
- * every row of the beamlet.
+ * The FP64 quantities the VOI row interval needs, taken from the beamlet
+ * record (built once per beamlet on the host, so that no division is left per
+ * tile): t', U, V at column 0 of a grid row as affine functions of (iy, iz),
+ * the cutoff slopes, and the four inequalities c0 + c1 x <= 0 in the column x
+ * of a row, whose c1 (and 1/c1) are the same for every row of the beamlet.
  */
 struct RowGeom {
-    double wx, oy, oz, sy, sz, Sy, Sz;    // org0 - S0; org1, org2; spacing y, z; S1, S2
-    double e[3], eu[3], ev[3], cu, cv;
+    double t[3], u[3], v[3];
+    double cu, cv;
     double c1[4], r1[4];
 };
 
-__device__ inline RowGeom row_geom(const PlanDev &P, const BeamletRec &R)
+__device__ inline RowGeom row_geom(const BeamletRec &R)
 {
     RowGeom G;
-    G.wx = P.org[0] - R.S[0];
-    G.oy = P.org[1];
-    G.oz = P.org[2];
-    G.sy = P.sp[1];
-    G.sz = P.sp[2];
-    G.Sy = R.S[1];
-    G.Sz = R.S[2];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        G.e[k] = R.e[k];
-        G.eu[k] = R.eu[k];
-        G.ev[k] = R.ev[k];
+        G.t[k] = R.row_t[k];
+        G.u[k] = R.row_u[k];
+        G.v[k] = R.row_v[k];
     }
     G.cu = R.cu_sad;
     G.cv = R.cv_sad;
-    const double t1 = P.sp[0] * R.e[0];
-    const double U1 = P.sp[0] * R.eu[0];
-    const double V1 = P.sp[0] * R.ev[0];
-    G.c1[0] = U1 - G.cu * t1;
-    G.c1[1] = -U1 - G.cu * t1;
-    G.c1[2] = V1 - G.cv * t1;
-    G.c1[3] = -V1 - G.cv * t1;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) G.r1[c] = G.c1[c] != 0.0 ? 1.0 / G.c1[c] : 0.0;
+    for (int c = 0; c < 4; ++c) {
+        G.c1[c] = R.c1[c];
+        G.r1[c] = R.r1[c];
+    }
     return G;
 }
 
 __device__ inline RowAffine row_affine(const RowGeom &G, int iy, int iz)
 {
-    const double wx = G.wx;
-    const double wy = fma((double)iy, G.sy, G.oy) - G.Sy;
-    const double wz = fma((double)iz, G.sz, G.oz) - G.Sz;
+    const double y = (double)iy, z = (double)iz;
     RowAffine a;
-    a.t0 = wx * G.e[0] + wy * G.e[1] + wz * G.e[2];
-    a.U0 = wx * G.eu[0] + wy * G.eu[1] + wz * G.eu[2];
-    a.V0 = wx * G.ev[0] + wy * G.ev[1] + wz * G.ev[2];
+    a.t0 = fma(z, G.t[2], fma(y, G.t[1], G.t[0]));
+    a.U0 = fma(z, G.u[2], fma(y, G.u[1], G.u[0]));
+    a.V0 = fma(z, G.v[2], fma(y, G.v[1], G.v[0]));
     return a;
 }
 
@@ -411,7 +421,7 @@ __device__ void count_beamlet(const PlanDev &P, int j)
 {
     const int lane = lane_id();
     const BeamletRec &R = P.rec[j];
-    const RowGeom G = row_geom(P, R);
+    const RowGeom G = row_geom(R);
     const int n_iy = R.n_iy, iy0 = R.iy0, iz0 = R.iz0, tile0 = R.tile0, n_tiles = R.n_tiles;
     const int n_rows = n_iy * R.n_iz;
     const int nx = P.nx, ny = P.ny, wpr = P.wpr;
@@ -796,8 +806,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     const float sad_f = R.sad_f;
     const double tA = R.tA, sad = R.sad;
     // per voxel step along x: t' in float, U and V scaled by SAD (rounded once from FP64)
-    const double t1 = P.sp[0] * R.e[0], u1 = P.sp[0] * R.eu[0] * sad, v1 = P.sp[0] * R.ev[0] * sad;
-    const float t1f = R.t1_f, U1f = (float)u1, V1f = (float)v1;
+    const float t1f = R.t1_f, U1f = (float)(R.dx[1] * sad), V1f = (float)(R.dx[2] * sad);
     const gptr<const uint32_t> bits = as_global<const uint32_t>(P.bits);
     const gptr<const int32_t> tile_count = as_global<const int32_t>(P.tile_count);
     const gptr<int32_t> out_idx = as_global<int32_t>(O.indices);
@@ -898,16 +907,16 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         if (r < n_rows) {
             const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
             RowAffine a;
-            const RowGeom G = row_geom(P, R);
+            const RowGeom G = row_geom(R);
             bool holes;
             if (row_span(G, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
                 const int grow = iz * ny + iy;
                 cb = grow * nx + lo;
                 wb = grow * wpr;
                 const double x = (double)lo;
-                s_lo = (float)(a.t0 + x * t1 - tA);
-                U_lo = (float)(fma(x, P.sp[0] * R.eu[0], a.U0) * sad);
-                V_lo = (float)(fma(x, P.sp[0] * R.ev[0], a.V0) * sad);
+                s_lo = (float)(a.t0 + x * R.dx[0] - tA);
+                U_lo = (float)(fma(x, R.dx[1], a.U0) * sad);
+                V_lo = (float)(fma(x, R.dx[2], a.V0) * sad);
             } else {
                 lo = 0;
                 hi = -1;
