@@ -36,14 +36,15 @@ struct alignas(16) BeamletRec {
     double tA, tB;        // entry / exit distances from S
     double step;          // spacing of the table points on AB
     double sad;
-    double cu_sad, cv_sad;  // cutoff / SAD: |U| <= cu_sad t', |V| <= cv_sad t'
-    // VOI row interval: t', U and V of the centre of voxel (0, iy, iz), relative to S, are
-    // row_t[0] + iy row_t[1] + iz row_t[2] (likewise row_u, row_v); dx holds their change
-    // per column; the row's four conditions c0 + c1[c] x <= 0 have r1[c] = 1 / c1[c] (0 if
-    // c1[c] = 0)
+    // VOI row interval (one block, copied as a whole by the fill): the cutoffs over SAD
+    // (|U| <= cu_sad t', |V| <= cv_sad t'); t', U and V of the centre of voxel (0, iy, iz),
+    // relative to S, as row_t[0] + iy row_t[1] + iz row_t[2] (likewise row_u, row_v); the
+    // row's four conditions c0 + c1[c] x <= 0 as r1[c] = 1 / c1[c] (0 if c1[c] = 0) and the
+    // signs of c1 (c1_pos, c1_neg below); dx: the change of t', U, V per column
+    double cu_sad, cv_sad;
     double row_t[3], row_u[3], row_v[3];
+    double r1[4];
     double dx[3];
-    double c1[4], r1[4];
     float half_a, half_b;   // a/2, b/2 at the iso plane
     float tA_f, inv_step_f;
     float sad_f, tau_max_f;   // SAD; n_table - 1
@@ -60,6 +61,7 @@ struct alignas(16) BeamletRec {
     int32_t iz0, n_iz;
     int32_t tile0;        // first tile (plan-local)
     int32_t n_tiles;
+    int32_t c1_pos, c1_neg;   // bit c set where c1[c] > 0, where c1[c] < 0
 };
 
 /* Everything a kernel needs about one plan; lives in device memory. */

@@ -660,11 +660,13 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
                         row[k][2] = g->spacing[2] * axis[k].z;
                         R.dx[k] = g->spacing[0] * axis[k].x;
                     }
-                    R.c1[0] = R.dx[1] - R.cu_sad * R.dx[0];
-                    R.c1[1] = -R.dx[1] - R.cu_sad * R.dx[0];
-                    R.c1[2] = R.dx[2] - R.cv_sad * R.dx[0];
-                    R.c1[3] = -R.dx[2] - R.cv_sad * R.dx[0];
-                    for (int c = 0; c < 4; ++c) R.r1[c] = R.c1[c] != 0.0 ? 1.0 / R.c1[c] : 0.0;
+                    const double c1[4] = {R.dx[1] - R.cu_sad * R.dx[0], -R.dx[1] - R.cu_sad * R.dx[0],
+                                          R.dx[2] - R.cv_sad * R.dx[0], -R.dx[2] - R.cv_sad * R.dx[0]};
+                    for (int c = 0; c < 4; ++c) {
+                        R.r1[c] = c1[c] != 0.0 ? 1.0 / c1[c] : 0.0;
+                        if (c1[c] > 0.0) R.c1_pos |= 1 << c;
+                        if (c1[c] < 0.0) R.c1_neg |= 1 << c;
+                    }
                 }
                 R.half_a = (float)(0.5 * B.beamlet_a);
                 R.half_b = (float)(0.5 * B.beamlet_b);

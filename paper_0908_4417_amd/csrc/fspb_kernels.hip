@@ -298,36 +298,34 @@ __global__ __launch_bounds__(kBlock) void k_raytrace(const PlanDev *__restrict__
 struct RowAffine { double t0, U0, V0; };
 
 /*
- * The FP64 quantities the VOI row interval needs, taken from the beamlet
- * record (built once per beamlet on the host, so that no division is left per
- * tile): t', U, V at column 0 of a grid row as affine functions of (iy, iz),
- * the cutoff slopes, and the four inequalities c0 + c1 x <= 0 in the column x
- * of a row, whose c1 (and 1/c1) are the same for every row of the beamlet.
+ * The FP64 quantities the VOI row interval needs: the beamlet record's block
+ * from cu_sad to dx (built once per beamlet on the host, so that no division
+ * is left per row): the cutoff slopes, t', U, V at column 0 of a grid row as
+ * affine functions of (iy, iz), 1/c1 of the four inequalities c0 + c1 x <= 0
+ * in the column x of a row (c1 is the same for every row of the beamlet; its
+ * signs come with the record as bit masks), and the change of t', U, V per
+ * column.
  */
 struct RowGeom {
-    double t[3], u[3], v[3];
     double cu, cv;
-    double c1[4], r1[4];
+    double t[3], u[3], v[3];
+    double r1[4];
+    double dx[3];
 };
+constexpr int kGeomWords = sizeof(RowGeom) / sizeof(double);
+static_assert(offsetof(BeamletRec, dx) + 3 * sizeof(double) - offsetof(BeamletRec, cu_sad) == sizeof(RowGeom),
+              "RowGeom mirrors the record's block from cu_sad to dx");
 
-__device__ inline RowGeom row_geom(const BeamletRec &R)
+/* The block from the record, or from a copy of it. */
+__device__ inline RowGeom row_geom(const double *src)
 {
     RowGeom G;
+    double *dst = reinterpret_cast<double *>(&G);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        G.t[k] = R.row_t[k];
-        G.u[k] = R.row_u[k];
-        G.v[k] = R.row_v[k];
-    }
-    G.cu = R.cu_sad;
-    G.cv = R.cv_sad;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        G.c1[c] = R.c1[c];
-        G.r1[c] = R.r1[c];
-    }
+    for (int k = 0; k < kGeomWords; ++k) dst[k] = src[k];
     return G;
 }
+__device__ inline RowGeom row_geom(const BeamletRec &R) { return row_geom(&R.cu_sad); }
 
 __device__ inline RowAffine row_affine(const RowGeom &G, int iy, int iz)
 {
@@ -345,8 +343,8 @@ __device__ inline RowAffine row_affine(const RowGeom &G, int iy, int iz)
  * interval), intersected with the row's extent of voxels above rho_min.
  * Solved in FP64 from the four linear inequalities.  Returns false if empty.
  */
-__device__ inline bool row_span(const RowGeom &G, const int2 *__restrict__ ext_rows, int nx, int ny, int iy,
-                                int iz, int &lo, int &hi, RowAffine &a, bool &holes)
+__device__ inline bool row_span(const RowGeom &G, int c1_pos, int c1_neg, const int2 *__restrict__ ext_rows,
+                                int nx, int ny, int iy, int iz, int &lo, int &hi, RowAffine &a, bool &holes)
 {
     a = row_affine(G, iy, iz);
     const double c0[4] = {a.U0 - G.cu * a.t0, -a.U0 - G.cu * a.t0,
@@ -354,9 +352,9 @@ __device__ inline bool row_span(const RowGeom &G, const int2 *__restrict__ ext_r
     double xlo = -1.0, xhi = (double)nx;            // already clipped to the grid
     bool ok = true;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {                   // c0 + c1 x <= 0
-        if (G.c1[c] > 0.0) xhi = fmin(xhi, -c0[c] * G.r1[c]);
-        else if (G.c1[c] < 0.0) xlo = fmax(xlo, -c0[c] * G.r1[c]);
+    for (int c = 0; c < 4; ++c) {                   // c0 + c1 x <= 0; the sign of c1 from the flags
+        if (c1_pos & (1 << c)) xhi = fmin(xhi, -c0[c] * G.r1[c]);
+        else if (c1_neg & (1 << c)) xlo = fmax(xlo, -c0[c] * G.r1[c]);
         else ok = ok && !(c0[c] > 0.0);
     }
     const int2 ext = ext_rows[iz * ny + iy];
@@ -396,7 +394,7 @@ struct RowCursor {
 };
 
 /* VOI members of grid row (iy0 + c.iy, iz0 + c.iz), or 0 when r >= n_rows: lane work of count_beamlet. */
-__device__ inline int count_row(const RowGeom &G, const uint32_t *__restrict__ bits,
+__device__ inline int count_row(const RowGeom &G, int c1_pos, int c1_neg, const uint32_t *__restrict__ bits,
                                 const int2 *__restrict__ ext, int nx, int ny, int wpr, int iy0, int iz0,
                                 const RowCursor &c, bool in)
 {
@@ -405,7 +403,7 @@ __device__ inline int count_row(const RowGeom &G, const uint32_t *__restrict__ b
     int lo, hi;
     RowAffine a;
     bool holes;
-    if (!row_span(G, ext, nx, ny, iy, iz, lo, hi, a, holes)) return 0;
+    if (!row_span(G, c1_pos, c1_neg, ext, nx, ny, iy, iz, lo, hi, a, holes)) return 0;
     // every voxel between the row's first and last member is one: no mask words needed
     if (!holes) return hi - lo + 1;
     return popcount_range(bits + (size_t)(iz * ny + iy) * wpr, lo, hi);
@@ -422,6 +420,7 @@ __device__ void count_beamlet(const PlanDev &P, int j)
     const int lane = lane_id();
     const BeamletRec &R = P.rec[j];
     const RowGeom G = row_geom(R);
+    const int c1_pos = __builtin_amdgcn_readfirstlane(R.c1_pos), c1_neg = __builtin_amdgcn_readfirstlane(R.c1_neg);
     const int n_iy = R.n_iy, iy0 = R.iy0, iz0 = R.iz0, tile0 = R.tile0, n_tiles = R.n_tiles;
     const int n_rows = n_iy * R.n_iz;
     const int nx = P.nx, ny = P.ny, wpr = P.wpr;
@@ -435,8 +434,8 @@ __device__ void count_beamlet(const PlanDev &P, int j)
     int64_t total = 0;
     for (int t = 0; t < n_tiles; t += 2) {
         const int r = t * kRowsPerTile + lane;
-        const int x0 = count_row(G, bits, ext, nx, ny, wpr, iy0, iz0, ca, r < n_rows);
-        const int x1 = count_row(G, bits, ext, nx, ny, wpr, iy0, iz0, cb, r + kRowsPerTile < n_rows);
+        const int x0 = count_row(G, c1_pos, c1_neg, bits, ext, nx, ny, wpr, iy0, iz0, ca, r < n_rows);
+        const int x1 = count_row(G, c1_pos, c1_neg, bits, ext, nx, ny, wpr, iy0, iz0, cb, r + kRowsPerTile < n_rows);
         const int c0 = wave_sum(x0), c1 = wave_sum(x1);
         if (lane == 0) {
             tile_count[tile0 + t] = c0;
@@ -823,6 +822,9 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     float2 *s_pdd = s_tab + P.max_table;
     int *s_tpre = reinterpret_cast<int *>(s_pdd + n_pdd);
     __shared__ int wsum[W];
+    // the beamlet's VOI row coefficients, read by every tile (LDS keeps them out of registers)
+    __shared__ RowGeom s_geom;
+    const int c1_pos = __builtin_amdgcn_readfirstlane(R.c1_pos), c1_neg = __builtin_amdgcn_readfirstlane(R.c1_neg);
     // surrogate: per-wave h1 tile after the tile prefix, and W2 fragments in registers
     uint16_t *s_h1 = reinterpret_cast<uint16_t *>(
         smem + ((sizeof(float2) * ((size_t)kErfPairs + P.max_table + n_pdd) +
@@ -841,6 +843,7 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         const float4 *__restrict__ et = reinterpret_cast<const float4 *>(P.erf_tab + (SE ? kErfIntervals : 0));
         float4 *se4 = reinterpret_cast<float4 *>(s_erf);
         for (int i = tid; i < kErfPairs / 2; i += kB) se4[i] = et[i];
+        if (tid < kGeomWords) reinterpret_cast<double *>(&s_geom)[tid] = (&R.cu_sad)[tid];
         const gptr<const float> tab = as_global<const float>(P.tables + R.table_off);
         for (int i = tid; i < n_table; i += kB) {
             const float d0 = tab[i];
@@ -907,16 +910,20 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         if (r < n_rows) {
             const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
             RowAffine a;
-            const RowGeom G = row_geom(R);
+            // the block is read from LDS here, tile by tile (an offset the compiler cannot see
+            // through keeps it from being held in registers across the tile loop)
+            uint32_t goff = 0;
+            asm volatile("" : "+s"(goff));
+            const RowGeom G = row_geom(reinterpret_cast<const double *>(reinterpret_cast<const char *>(&s_geom) + goff));
             bool holes;
-            if (row_span(G, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
+            if (row_span(G, c1_pos, c1_neg, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
                 const int grow = iz * ny + iy;
                 cb = grow * nx + lo;
                 wb = grow * wpr;
                 const double x = (double)lo;
-                s_lo = (float)(a.t0 + x * R.dx[0] - tA);
-                U_lo = (float)(fma(x, R.dx[1], a.U0) * sad);
-                V_lo = (float)(fma(x, R.dx[2], a.V0) * sad);
+                s_lo = (float)(a.t0 + x * G.dx[0] - tA);
+                U_lo = (float)(fma(x, G.dx[1], a.U0) * sad);
+                V_lo = (float)(fma(x, G.dx[2], a.V0) * sad);
             } else {
                 lo = 0;
                 hi = -1;
