@@ -3,7 +3,7 @@
  *
  *   beamlet-row CSR (what the fill writes: row j = beamlet, columns = voxels)
  *     k_fluence_dose      dose_i += w_j D_ij with FP32 atomics   -- one wave per row
- *     k_fluence_gradient  g_j = sum_i D_ij r_i, fixed order      -- one wave per row
+ *     k_fluence_gradient  g_j = sum_i D_ij r_i, fixed order      -- one workgroup per row
  *   voxel-row CSR (row i = voxel, columns = beamlets): the transpose, a stable
  *   sort of the row-major entries by column
  *     k_run_count, scan, k_run_sizes   runs of each row (stretches within one
@@ -163,46 +163,83 @@ __device__ inline float dot4(int4 i, float4 v, const float *__restrict__ x, uint
     return acc;
 }
 
-/* g_j = sum_i D_ij r_i; one wave per row: 16-byte loads of four consecutive
- * entries per lane, two steps in flight, lane partial sums then a fixed
- * butterfly.  Columns outside [0, n_voxels) are skipped. */
+/*
+ * g_j = sum_i D_ij r_i; one workgroup per row.  The row's middle goes in steps
+ * of 4 kBlock entries: lane l of wave w takes entries 256 w + l + 64 k
+ * (k < 4) of a step, so that each gather of r reads 64 consecutive columns;
+ * the next step's indices and values are loaded (non-temporal: streamed once,
+ * kept from displacing r in the caches) after this step's gathers are issued,
+ * so they are in flight while the gathered values are awaited.  The tail is
+ * lane-strided; lane partial sums, a fixed butterfly per wave and the wave
+ * totals added in wave order.  Columns outside [0, n_voxels) are skipped.
+ */
 __global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__restrict__ indptr,
                                                              const int32_t *__restrict__ indices,
                                                              const float *__restrict__ values, int n_rows,
                                                              int n_voxels, const float *__restrict__ r,
                                                              float *__restrict__ g)
 {
-    const int j = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    if (j >= n_rows) return;
-    const int lane = lane_id();
+    constexpr int kStep = 4 * kBlock;
+    __shared__ float s_w[kWavesPerBlock];
+    const int j = blockIdx.x;
+    const int t = threadIdx.x;
     const uint32_t n = (uint32_t)n_voxels;
     const int64_t e0 = indptr[j], e1 = indptr[j + 1];
-    const RowSplit sp = row_split(indices, values, e0, e1, 4 * kWave);
+    // whole steps from the row's start (4-byte loads need no alignment), then the tail
+    const int64_t b = e0 + (e1 - e0) / kStep * kStep;
     float acc0 = 0.0f, acc1 = 0.0f;
-    if (e0 + lane < sp.a) {
-        const uint32_t i = (uint32_t)indices[e0 + lane];
-        if (i < n) acc0 = fmaf(values[e0 + lane], r[i], acc0);
+    if (e0 < b) {   // the same for the whole workgroup, as is every step test below
+        int64_t e = e0 + 4 * kWave * (t >> 6) + (t & (kWave - 1));
+        uint32_t i0[4];
+        float v0[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            i0[k] = (uint32_t)__builtin_nontemporal_load(indices + e + kWave * k);
+            v0[k] = __builtin_nontemporal_load(values + e + kWave * k);
+        }
+        for (;;) {
+            const int64_t en = e + kStep;
+            float x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = i0[k] < n ? r[i0[k]] : 0.0f;
+            uint32_t i1[4];
+            float v1[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                i1[k] = i0[k];
+                v1[k] = v0[k];
+            }
+            if (en < b) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    i1[k] = (uint32_t)__builtin_nontemporal_load(indices + en + kWave * k);
+                    v1[k] = __builtin_nontemporal_load(values + en + kWave * k);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i0[k] < n) acc0 = fmaf(v0[k], x[k], acc0);
+            if (en >= b) break;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                i0[k] = i1[k];
+                v0[k] = v1[k];
+            }
+            e = en;
+        }
     }
-    int64_t e = sp.a + 4 * lane;
-    for (; e + 4 * kWave < sp.b; e += 8 * kWave) {
-        const int4 i0 = *reinterpret_cast<const int4 *>(indices + e);
-        const float4 v0 = *reinterpret_cast<const float4 *>(values + e);
-        const int4 i1 = *reinterpret_cast<const int4 *>(indices + e + 4 * kWave);
-        const float4 v1 = *reinterpret_cast<const float4 *>(values + e + 4 * kWave);
-        acc0 = dot4(i0, v0, r, n, acc0);
-        acc1 = dot4(i1, v1, r, n, acc1);
+    for (int64_t q = b + t; q < e1; q += kBlock) {
+        const uint32_t i = (uint32_t)indices[q];
+        if (i < n) acc1 = fmaf(values[q], r[i], acc1);
     }
-    if (e < sp.b) {
-        const int4 i0 = *reinterpret_cast<const int4 *>(indices + e);
-        const float4 v0 = *reinterpret_cast<const float4 *>(values + e);
-        acc0 = dot4(i0, v0, r, n, acc0);
+    const float s = wave_sum(acc0 + acc1);
+    if (lane_id() == 0) s_w[t >> 6] = s;
+    __syncthreads();
+    if (t == 0) {
+        float tot = s_w[0];
+        for (int k = 1; k < kWavesPerBlock; ++k) tot += s_w[k];
+        g[j] = tot;
     }
-    for (int64_t t = sp.b + lane; t < e1; t += kWave) {
-        const uint32_t i = (uint32_t)indices[t];
-        if (i < n) acc1 = fmaf(values[t], r[i], acc1);
-    }
-    float s = wave_sum(acc0 + acc1);
-    if (lane == 0) g[j] = s;
 }
 
 /* dose_i = sum_j D_ij w_j over voxel row i: 16 lanes per row, lane-strided
@@ -529,7 +566,7 @@ hipError_t launch_fluence_gradient(const int64_t *indptr, const int32_t *indices
                                    int n_voxels, const float *r, float *g, hipStream_t s)
 {
     if (n_rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fluence_gradient, dim3(blocks_of(n_rows, kWavesPerBlock)), dim3(kBlock), 0, s, indptr,
+    hipLaunchKernelGGL(k_fluence_gradient, dim3(n_rows), dim3(kBlock), 0, s, indptr,
                        indices, values, n_rows, n_voxels, r, g);
     return hipGetLastError();
 }
