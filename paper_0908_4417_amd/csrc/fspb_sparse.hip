@@ -154,14 +154,8 @@ __device__ inline RowSplit row_split(const int32_t *indices, const float *values
     return {a, a + (e1 - a) / step * step};
 }
 
-__device__ inline float dot4(int4 i, float4 v, const float *__restrict__ x, uint32_t n, float acc)
-{
-    if ((uint32_t)i.x < n) acc = fmaf(v.x, x[(uint32_t)i.x], acc);
-    if ((uint32_t)i.y < n) acc = fmaf(v.y, x[(uint32_t)i.y], acc);
-    if ((uint32_t)i.z < n) acc = fmaf(v.z, x[(uint32_t)i.z], acc);
-    if ((uint32_t)i.w < n) acc = fmaf(v.w, x[(uint32_t)i.w], acc);
-    return acc;
-}
+typedef int vi4 __attribute__((ext_vector_type(4)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
 
 /*
  * g_j = sum_i D_ij r_i; one workgroup per row.  The row's middle goes in steps
@@ -242,9 +236,10 @@ __global__ __launch_bounds__(kBlock) void k_fluence_gradient(const int64_t *__re
     }
 }
 
-/* dose_i = sum_j D_ij w_j over voxel row i: 16 lanes per row, lane-strided
- * partial sums and a fixed 16-lane butterfly.  Beamlets outside [0, n_w) are
- * skipped. */
+/* dose_i = sum_j D_ij w_j over voxel row i: 16 lanes per row, 16-byte loads of
+ * four consecutive entries per lane, the next step's loads in flight while
+ * this step's gathers of w are awaited; lane-strided partial sums and a fixed
+ * 16-lane butterfly.  Beamlets outside [0, n_w) are skipped. */
 __global__ __launch_bounds__(kBlock) void k_voxel_dose(const int64_t *__restrict__ t_indptr,
                                                        const int32_t *__restrict__ t_indices,
                                                        const float *__restrict__ t_values, int n_voxels, int n_w,
@@ -262,10 +257,34 @@ __global__ __launch_bounds__(kBlock) void k_voxel_dose(const int64_t *__restrict
             const uint32_t j = (uint32_t)t_indices[e0 + l];
             if (j < n) acc0 = fmaf(t_values[e0 + l], w[j], acc0);
         }
-        for (int64_t e = sp.a + 4 * l; e < sp.b; e += 64) {
-            const int4 j4 = *reinterpret_cast<const int4 *>(t_indices + e);
-            const float4 v4 = *reinterpret_cast<const float4 *>(t_values + e);
-            acc1 = dot4(j4, v4, w, n, acc1);
+        // the next step's indices and values are loaded after this step's gathers of w are
+        // issued (non-temporal: streamed once), so they are in flight while those are awaited
+        int64_t e = sp.a + 4 * l;
+        if (e < sp.b) {
+            vi4 a = __builtin_nontemporal_load(reinterpret_cast<const vi4 *>(t_indices + e));
+            vf4 c = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(t_values + e));
+            for (;;) {
+                const int64_t en = e + 64;
+                float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f, x3 = 0.0f;
+                if ((uint32_t)a.x < n) x0 = w[(uint32_t)a.x];
+                if ((uint32_t)a.y < n) x1 = w[(uint32_t)a.y];
+                if ((uint32_t)a.z < n) x2 = w[(uint32_t)a.z];
+                if ((uint32_t)a.w < n) x3 = w[(uint32_t)a.w];
+                vi4 a1 = a;
+                vf4 c1 = c;
+                if (en < sp.b) {
+                    a1 = __builtin_nontemporal_load(reinterpret_cast<const vi4 *>(t_indices + en));
+                    c1 = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(t_values + en));
+                }
+                if ((uint32_t)a.x < n) acc1 = fmaf(c.x, x0, acc1);
+                if ((uint32_t)a.y < n) acc1 = fmaf(c.y, x1, acc1);
+                if ((uint32_t)a.z < n) acc1 = fmaf(c.z, x2, acc1);
+                if ((uint32_t)a.w < n) acc1 = fmaf(c.w, x3, acc1);
+                if (en >= sp.b) break;
+                a = a1;
+                c = c1;
+                e = en;
+            }
         }
         for (int64_t e = sp.b + l; e < e1; e += 16) {
             const uint32_t j = (uint32_t)t_indices[e];
