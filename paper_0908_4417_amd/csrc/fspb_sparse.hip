@@ -65,16 +65,36 @@ __device__ inline T wave_sum(T x)
     return x;
 }
 
+/*
+ * Inclusive scan of a wave's 32-bit integers by DPP: row shifts by 1, 2, 4 and
+ * 8 lanes scan each row of 16 lanes (lanes shifted in from outside the row read
+ * 0); rows 1 and 3 then add the last lane of the row below (row_bcast:15) and
+ * rows 2 and 3 add lane 31 (row_bcast:31).  Every lane of the wave must be
+ * active.
+ */
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return (uint32_t)x;
+}
+
+/* Wave total of 32-bit integers (every lane active), the same on every lane. */
+__device__ inline uint32_t wave_sum(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(x), kWave - 1);
+}
+
 /* Exclusive scan of one value per thread over the block; *total gets the sum. */
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, uint32_t *total)
 {
     const int l = lane_id(), w = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, kWave);
-        if (l >= d) x += y;
-    }
+    uint32_t x = wave_incl_scan(v);
     if (l == kWave - 1) s_w[w] = x;
     __syncthreads();
     uint32_t off = 0, tot = 0;
@@ -373,12 +393,7 @@ __global__ __launch_bounds__(kScanTop) void k_scan_top(uint32_t *__restrict__ pa
     for (int64_t b0 = 0; b0 < nb; b0 += kScanTop) {
         const int64_t i = b0 + threadIdx.x;
         const uint32_t v = i < nb ? partial[i] : 0u;
-        uint32_t x = v;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t y = __shfl_up(x, d, kWave);
-            if (l >= d) x += y;
-        }
+        uint32_t x = wave_incl_scan(v);
         if (l == kWave - 1) s_w[w] = x;
         __syncthreads();
         uint32_t off = 0, tot = 0;
@@ -886,12 +901,7 @@ __global__ __launch_bounds__(kWave) void k_place_sorted(
             acc += lane == c ? n : 0u;
         }
     }
-    uint32_t incl = acc;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += y;
-    }
+    uint32_t incl = wave_incl_scan(acc);
     if (lane < kBucketCols) {
         const uint32_t pos = base + incl - acc;
         s_pos[lane] = pos;
@@ -908,12 +918,7 @@ __global__ __launch_bounds__(kWave) void k_place_sorted(
         const uint32_t src = have ? __float_as_uint(b_src[q]) : 0u;
         uint32_t mask = have ? b_mask[q] : 0u;   // 0 for an invalid run
         uint32_t len = (uint32_t)__popc(mask);
-        uint32_t end = len;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t y = __shfl_up(end, d, kWave);
-            if (lane >= d) end += y;
-        }
+        uint32_t end = wave_incl_scan(len);
         // the batch: the leading runs whose entries fit (at least one: a run holds <= 32)
         const bool fit = have && end <= (uint32_t)kPlaceCap;
         const int take = __popcll(__ballot(fit));
@@ -931,12 +936,7 @@ __global__ __launch_bounds__(kWave) void k_place_sorted(
             cm = lane == c ? m : cm;
         }
         const uint32_t cnt = (uint32_t)__popcll(cm);
-        uint32_t cinc = cnt;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t y = __shfl_up(cinc, d, kWave);
-            if (lane >= d) cinc += y;
-        }
+        uint32_t cinc = wave_incl_scan(cnt);
         const uint32_t cst = cinc - cnt;
         if (lane < kBucketCols) {
             s_cm[lane] = cm;
@@ -1019,12 +1019,7 @@ __device__ inline RunBatch load_runs(int64_t qb, int64_t q1, const int32_t *__re
         B.src = __float_as_uint(b_src[q]);
         B.len = b_len[q];   // 0 for an invalid run
     }
-    uint32_t incl = B.len;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += y;
-    }
+    uint32_t incl = wave_incl_scan(B.len);
     B.excl = incl - B.len;
     B.total = __shfl(incl, kWave - 1, kWave);
     return B;
