@@ -97,8 +97,13 @@ struct alignas(16) PlanDev {
     int32_t depth_mode;          // 0: exact path integral; 1: trilinear samples + trapezoids
     const BeamletRec *rec;
     float *tables;
-    const int32_t *tile_beamlet; // [n_tiles]
-    int32_t *tile_count;         // [n_tiles]
+    // Fill tiles, from the count pass: either the beamlet's row block in runs of kRowsPerTile
+    // grid rows, or, where most of the block's rows hold no VOI member, its list of the rows
+    // that do (row index in the block, ascending) in runs of kRowsPerTile list entries
+    int32_t *tile_count;         // [n_tiles] members of each block tile
+    int32_t *row_list;           // [n_tiles kRowsPerTile]: beamlet j's list at tile0 kRowsPerTile
+    int32_t *list_count;         // [n_tiles] members of each list tile (first ceil(row_ne / 64) of a beamlet's)
+    int32_t *row_ne;             // [n_beamlets] length of beamlet j's list, -1: block tiles
     int64_t *row_nnz;            // [n_beamlets]
     int64_t *nnz;                // [1]
     // attached kernel surrogate (use_mlp = 0: analytic fill)

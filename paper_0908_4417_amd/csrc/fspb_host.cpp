@@ -75,8 +75,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 /* Workspace carve: offsets of every device array.  The arrays the host
  * writes come first, so that one copy of [0, upload) uploads all of them. */
 struct Layout {
-    size_t plan, scal, rec, tile_beamlet, pdd, erf, ctab, atab, upload;
-    size_t out, tile_count, row_nnz, tables, bits, ext, total;
+    size_t plan, scal, rec, pdd, erf, ctab, atab, upload;
+    size_t out, tile_count, row_list, list_count, row_ne, row_nnz, tables, bits, ext, total;
 };
 
 /*
@@ -159,7 +159,6 @@ struct fspb_plan {
     int64_t *d_nnz = nullptr;
     int32_t *d_overflow = nullptr;
     std::vector<BeamletRec> recs;
-    std::vector<int32_t> tile_beamlet;
     int64_t table_entries = 0;
     int32_t n_voxels = 0;
     bool traced = false;
@@ -724,13 +723,6 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     if (table_off >= (int64_t)1 << 31 || tile_off >= (int64_t)1 << 31)
         return fail(FSPB_ERR_INVALID, "plan too large (%lld table entries, %lld tiles)", (long long)table_off,
                     (long long)tile_off);
-    try {
-        p->tile_beamlet.resize((size_t)tile_off);
-    } catch (...) {
-        return fail(FSPB_ERR_NOMEM, "cannot allocate the tile map");
-    }
-    for (size_t k = 0; k < p->recs.size(); ++k)
-        for (int32_t t = 0; t < p->recs[k].n_tiles; ++t) p->tile_beamlet[(size_t)p->recs[k].tile0 + t] = (int32_t)k;
     h.n_beamlets = (int32_t)nbl;
     h.max_table = max_table;
     h.n_tiles = (int32_t)tile_off;
@@ -755,7 +747,6 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     L.plan = take(sizeof(PlanDev));
     L.scal = take(64);
     L.rec = take(sizeof(BeamletRec) * (size_t)nbl);
-    L.tile_beamlet = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
     L.pdd = take(sizeof(float) * (size_t)K->n_pdd);
     L.erf = take(sizeof(float2) * 3 * fspb::kErfIntervals);
     if (K->tables) {
@@ -765,6 +756,9 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     L.upload = off;
     L.out = take(sizeof(OutDev));
     L.tile_count = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
+    L.row_list = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off * fspb::kRowsPerTile, 1));
+    L.list_count = take(sizeof(int32_t) * (size_t)std::max<int64_t>(tile_off, 1));
+    L.row_ne = take(sizeof(int32_t) * (size_t)std::max<int64_t>(nbl, 1));
     L.row_nnz = take(sizeof(int64_t) * (size_t)nbl);
     L.tables = take(sizeof(float) * (size_t)std::max<int64_t>(table_off, 1));
     L.bits = take(sizeof(uint32_t) * (size_t)grow * h.wpr);
@@ -795,7 +789,9 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     p->d_nnz = reinterpret_cast<int64_t *>(ws + L.scal);
     p->d_overflow = reinterpret_cast<int32_t *>(ws + L.scal + 16);
     h.rec = reinterpret_cast<BeamletRec *>(ws + L.rec);
-    h.tile_beamlet = reinterpret_cast<int32_t *>(ws + L.tile_beamlet);
+    h.row_list = reinterpret_cast<int32_t *>(ws + L.row_list);
+    h.list_count = reinterpret_cast<int32_t *>(ws + L.list_count);
+    h.row_ne = reinterpret_cast<int32_t *>(ws + L.row_ne);
     h.tile_count = reinterpret_cast<int32_t *>(ws + L.tile_count);
     h.row_nnz = reinterpret_cast<int64_t *>(ws + L.row_nnz);
     h.tables = reinterpret_cast<float *>(ws + L.tables);
@@ -840,8 +836,6 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
         std::memcpy(img + L.plan, &h, sizeof(PlanDev));
         std::memset(img + L.scal, 0, 64);   // nonzero count and overflow flag start at zero
         if (nbl > 0) std::memcpy(img + L.rec, p->recs.data(), sizeof(BeamletRec) * (size_t)nbl);
-        if (tile_off > 0)
-            std::memcpy(img + L.tile_beamlet, p->tile_beamlet.data(), sizeof(int32_t) * (size_t)tile_off);
         std::memcpy(img + L.pdd, K->pdd, sizeof(float) * (size_t)K->n_pdd);
         const std::vector<float2> &et = fill_erf_table();
         std::memcpy(img + L.erf, et.data(), sizeof(float2) * et.size());

@@ -410,11 +410,51 @@ __device__ inline int count_row(const RowGeom &G, int c1_pos, int c1_neg, const 
 }
 
 /*
- * VOI members of every tile of beamlet j (64 grid rows each, lane = row) and
- * of its whole row of D; one wave, two tiles per step so that the loads of
- * both are in flight together.  Everything the loop reads from the plan and
- * the beamlet record is taken into registers first.
+ * Tiles of beamlet j and its row of D's length; one wave.  The beamlet's row
+ * block is walked 64 grid rows at a time (lane = row), two such groups per step
+ * so that the loads of both are in flight together; each group's members are a
+ * block tile's count.  Rows with VOI members are also appended to the
+ * beamlet's row list (ascending), whose runs of 64 entries are list tiles with
+ * their own counts.  Where fewer than half of the block's rows hold members
+ * (a beam crossing air around a body), the fill takes the list tiles, so that
+ * no tile set-up is spent on empty rows; otherwise the block tiles, whose rows
+ * need no list read.  Everything the loop reads from the plan and the beamlet
+ * record is taken into registers first.
  */
+struct RowListBuilder {
+    int32_t *list;       // the beamlet's row list
+    int32_t *tiles;      // its list tiles' member counts
+    int n = 0;           // rows in the list so far
+    int acc = 0;         // members of the list tile being filled (tile n / 64)
+
+    /* rows of one group of 64: row r (this lane's) with x members; returns the group's members */
+    __device__ int append(int x, int r)
+    {
+        const uint64_t ne = __ballot(x > 0);
+        const int pos = n + mbcnt64(ne);
+        if (x > 0) list[pos] = r;
+        const int t0 = n >> 6;
+        const bool same = (pos >> 6) == t0;
+        const int sa = wave_sum(x > 0 && same ? x : 0);    // members joining tile t0
+        const int sb = wave_sum(x > 0 && !same ? x : 0);   // and the next tile (<= 64 rows: at most two)
+        const int cnt = __popcll(ne);
+        if (((n + cnt) >> 6) != t0) {                       // tile t0 is complete
+            if (lane_id() == 0) tiles[t0] = acc + sa;
+            acc = sb;
+        } else {
+            acc += sa;
+        }
+        n += cnt;
+        return sa + sb;
+    }
+    /* the last, partial tile */
+    __device__ void finish()
+    {
+        if ((n & (kRowsPerTile - 1)) != 0 && lane_id() == 0) tiles[n >> 6] = acc;
+    }
+};
+static_assert(kRowsPerTile == kWave, "one list tile per wave of rows");
+
 __device__ void count_beamlet(const PlanDev &P, int j)
 {
     const int lane = lane_id();
@@ -427,6 +467,7 @@ __device__ void count_beamlet(const PlanDev &P, int j)
     const uint32_t *__restrict__ bits = P.bits;
     const int2 *__restrict__ ext = P.ext;
     int32_t *__restrict__ tile_count = P.tile_count;
+    RowListBuilder L{P.row_list + (int64_t)tile0 * kRowsPerTile, P.list_count + tile0};
     // rows r and r + 64 of this lane, stepped by 128 rows per iteration
     RowCursor ca{lane % n_iy, lane / n_iy};
     RowCursor cb{(lane + kRowsPerTile) % n_iy, (lane + kRowsPerTile) / n_iy};
@@ -436,7 +477,7 @@ __device__ void count_beamlet(const PlanDev &P, int j)
         const int r = t * kRowsPerTile + lane;
         const int x0 = count_row(G, c1_pos, c1_neg, bits, ext, nx, ny, wpr, iy0, iz0, ca, r < n_rows);
         const int x1 = count_row(G, c1_pos, c1_neg, bits, ext, nx, ny, wpr, iy0, iz0, cb, r + kRowsPerTile < n_rows);
-        const int c0 = wave_sum(x0), c1 = wave_sum(x1);
+        const int c0 = L.append(x0, r), c1 = L.append(x1, r + kRowsPerTile);
         if (lane == 0) {
             tile_count[tile0 + t] = c0;
             if (t + 1 < n_tiles) tile_count[tile0 + t + 1] = c1;
@@ -445,7 +486,11 @@ __device__ void count_beamlet(const PlanDev &P, int j)
         ca.step(dy, dz, n_iy);
         cb.step(dy, dz, n_iy);
     }
-    if (lane == 0) P.row_nnz[j] = total;
+    L.finish();
+    if (lane == 0) {
+        P.row_nnz[j] = total;
+        P.row_ne[j] = 2 * L.n < n_rows ? L.n : -1;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_count(const PlanDev *__restrict__ plans)
@@ -755,18 +800,19 @@ __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readla
 
 /*
  * D_ij of beamlet j (one CSR row) by a workgroup of W waves: LDS-staged
- * tables, then each wave takes tiles of 64 grid rows; a tile's VOI candidates
- * are flattened across its rows, 64 per chunk, members compacted by ballot.
+ * tables, then each wave takes tiles of 64 grid rows (runs of the row list the
+ * count pass built: rows with members only); a tile's VOI candidates are
+ * flattened across its rows, 64 per chunk, members compacted by ballot.
  * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K);
  * EM: how erf is read (erf_mirrored_mode).
  */
 /* tile_group: consecutive 64-row tiles a wave takes per step (the batched fill's tuned shape). */
 template <int K, int W, bool GUARD, bool SURR, bool GEN = false, int EM = 0>
-__device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem, int tile_group = 1)
+__device__ __attribute__((always_inline)) inline void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned char *smem,
+                                                             int tile_group = 1)
 {
     const BeamletRec &R = P.rec[j];
-    const int n_tiles = R.n_tiles;
-    if (n_tiles == 0) return;
+    if (R.n_tiles == 0) return;   // the axis misses the grid
     constexpr int kB = W * kWave;
     const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = lane_id();
     constexpr bool SE = erf_mirrored_mode(EM);
@@ -775,7 +821,8 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
 
     // ---- constants into registers
     const int n_table = R.n_table, n_pdd = lds_pdd_pairs(P), tile0 = R.tile0;
-    const int iy0 = R.iy0, n_iy = R.n_iy, iz0 = R.iz0, n_rows = R.n_iy * R.n_iz;
+    const int iy0 = R.iy0, n_iy = R.n_iy, iz0 = R.iz0;
+    const gptr<const int32_t> row_list = as_global<const int32_t>(P.row_list + (int64_t)R.tile0 * kRowsPerTile);
     const int nx = P.nx, ny = P.ny, wpr = P.wpr;
     FillConst<K> c;
     c.tA = R.tA_f;
@@ -807,7 +854,6 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
     // per voxel step along x: t' in float, U and V scaled by SAD (rounded once from FP64)
     const float t1f = R.t1_f, U1f = (float)(R.dx[1] * sad), V1f = (float)(R.dx[2] * sad);
     const gptr<const uint32_t> bits = as_global<const uint32_t>(P.bits);
-    const gptr<const int32_t> tile_count = as_global<const int32_t>(P.tile_count);
     const gptr<int32_t> out_idx = as_global<int32_t>(O.indices);
     const gptr<float> out_val = as_global<float>(O.values);
     const int64_t capacity = O.capacity;
@@ -880,6 +926,14 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
             }
         }
     }
+    // the tiles the count pass chose (read here, after the table loads have been issued): the
+    // row list's (64 rows with members each, the last one partial; its length clamped to the
+    // row block's capacity, so that no index can leave it) or the row block's
+    const int ne = __builtin_amdgcn_readfirstlane(P.row_ne[j]);
+    const bool use_list = ne >= 0;
+    const int n_list = use_list ? min(ne, R.n_tiles * kRowsPerTile) : R.n_iy * R.n_iz;
+    const int n_tiles = use_list ? (n_list + kRowsPerTile - 1) / kRowsPerTile : R.n_tiles;
+    const gptr<const int32_t> tile_count = as_global<const int32_t>(use_list ? P.list_count : P.tile_count);
     // exclusive scan of this beamlet's tile counts
     int carry = 0;
     for (int base = 0; base < n_tiles; base += kB) {
@@ -897,260 +951,289 @@ __device__ void fill_beamlet(const PlanDev &P, const OutDev &O, int j, unsigned 
         __syncthreads();
     }
 
-    for (int tg = wave * tile_group; tg < n_tiles; tg += W * tile_group)
-    for (int tl = tg; tl < tg + tile_group && tl < n_tiles; ++tl) {
+    // the wave's tiles: runs of tile_group consecutive tiles, every W-th run.  Lane = an entry
+    // of the row list, a grid row r of the beamlet's row block; the next tile's entries are
+    // loaded while this tile is walked (the list, written by the count pass, is not in L2)
+    auto next_tile = [&](int t) { return (t + 1) % tile_group != 0 ? t + 1 : t + 1 + (W - 1) * tile_group; };
+    auto list_entry = [&](int t) {
+        const int li = t * kRowsPerTile + lane;
+        return t < n_tiles && li < n_list ? row_list[li] : -1;
+    };
+    // one tile: row r (this lane's; -1 for none) of tile tl; after_span runs once the rows'
+    // extents have been read
+    auto tile = [&](const int tl, const int r, auto &&after_span) {
+        // row r's VOI interval and FP32 start values; the column of candidate k of the row is
+        // cb + k, its mask word wb + ((lo + k) >> 5)
         const int members = __builtin_amdgcn_readfirstlane(tile_count[tile0 + tl]);
-        if (members == 0) continue;
-        const int64_t out0 = row_base + __builtin_amdgcn_readfirstlane(s_tpre[tl]);
-        // lane = grid row of this tile: its VOI interval and FP32 start values; the column
-        // of candidate k of the row is cb + k, its mask word wb + ((lo + k) >> 5)
-        const int r = tl * kRowsPerTile + lane;
-        int lo = 0, hi = -1, cb = 0, wb = 0;
-        float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
-        if (r < n_rows) {
-            const int iy = iy0 + r % n_iy, iz = iz0 + r / n_iy;
-            RowAffine a;
-            // the block is read from LDS here, tile by tile (an offset the compiler cannot see
-            // through keeps it from being held in registers across the tile loop)
-            uint32_t goff = 0;
-            asm volatile("" : "+s"(goff));
-            const RowGeom G = row_geom(reinterpret_cast<const double *>(reinterpret_cast<const char *>(&s_geom) + goff));
-            bool holes;
-            if (row_span(G, c1_pos, c1_neg, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
-                const int grow = iz * ny + iy;
-                cb = grow * nx + lo;
-                wb = grow * wpr;
-                const double x = (double)lo;
-                s_lo = (float)(a.t0 + x * G.dx[0] - tA);
-                U_lo = (float)(fma(x, G.dx[1], a.U0) * sad);
-                V_lo = (float)(fma(x, G.dx[2], a.V0) * sad);
-            } else {
-                lo = 0;
-                hi = -1;
-            }
+        if (members == 0) {           // an empty block tile (list tiles always have members)
+            after_span();
+            return;
         }
-        int cnt = hi - lo + 1;
-        {
-            // rows with candidates move to the low lanes, in order, empty rows after them
-            // (a permutation of the wave), so that row starts are distinct candidates
-            const uint64_t ne = __ballot(cnt > 0);
-            const int dst = cnt > 0 ? mbcnt64(ne) : __popcll(ne) + mbcnt64(~ne);
-            const int a = dst << 2;
-            lo = __builtin_amdgcn_ds_permute(a, lo);
-            cnt = __builtin_amdgcn_ds_permute(a, cnt);
-            cb = __builtin_amdgcn_ds_permute(a, cb);
-            wb = __builtin_amdgcn_ds_permute(a, wb);
-            s_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(s_lo)));
-            U_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(U_lo)));
-            V_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(V_lo)));
-        }
-        const int n_ne = __popcll(__ballot(cnt > 0));
-        const int incl = wave_incl_scan(cnt);
-        const int excl = incl - cnt;
-        const int total = readlane(incl, kWave - 1);   // wave-uniform: the chunk loop stays scalar
-        // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
-        // rows are walked once, wave-uniformly, as the chunks advance (rcur: row of
-        // the first candidate of the next chunk)
-        int rcur = 0;
-        int64_t written = out0;
-        // a tile whose counted members equal its candidates (no masked voxel inside its rows)
-        // takes every candidate: no mask read, and member lanes are the low ones of the chunk
-        const bool dense = members == total;
-        // the tile's entries fit the caller's arrays: no per-chunk capacity test, and they are
-        // written through buffer descriptors over exactly the tile's entries (32-bit offsets:
-        // the lane's slot in a VGPR, the chunk's start in an SGPR)
-        const bool fits = out0 + members <= capacity;
-        const __amdgpu_buffer_rsrc_t rs_idx =
-            __builtin_amdgcn_make_buffer_rsrc(O.indices + out0, 0, members * 4, kRawBufferWord3);
-        const __amdgpu_buffer_rsrc_t rs_val =
-            __builtin_amdgcn_make_buffer_rsrc(O.values + out0, 0, members * 4, kRawBufferWord3);
-        // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
-        auto chunk = [&](const int p, const int rr, auto dense_tag, auto fits_tag) {
-            constexpr bool DENSE = decltype(dense_tag)::value;
-            constexpr bool FITS = decltype(fits_tag)::value;
-            // row rr's values, fetched by lane (rr < 64: the byte address needs no wrap)
-            const int ra = rr << 2;
-            auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
-            auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
-            const int k = p - from_row(excl);
-            const int col = from_row(cb) + k;
-            bool member = false;
-            if (DENSE) {
-                member = p < total;
-            } else {
-                const int wr = from_row(wb), ix = from_row(lo) + k;
-                if (p < total) {
-                    const uint32_t wo = ((uint32_t)wr + ((uint32_t)ix >> 5)) << 2;   // byte offset
-                    member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
+            const int64_t out0 = row_base + __builtin_amdgcn_readfirstlane(s_tpre[tl]);
+            int lo = 0, hi = -1, cb = 0, wb = 0;
+            float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
+            if (r >= 0) {
+                const int iy = iy0 + (int)((uint32_t)r % (uint32_t)n_iy), iz = iz0 + (int)((uint32_t)r / (uint32_t)n_iy);
+                RowAffine a;
+                // the block is read from LDS here, tile by tile (an offset the compiler cannot see
+                // through keeps it from being held in registers across the tile loop)
+                uint32_t goff = 0;
+                asm volatile("" : "+s"(goff));
+                const RowGeom G = row_geom(reinterpret_cast<const double *>(reinterpret_cast<const char *>(&s_geom) + goff));
+                bool holes;
+                if (row_span(G, c1_pos, c1_neg, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
+                    const int grow = iz * ny + iy;
+                    cb = grow * nx + lo;
+                    wb = grow * wpr;
+                    const double x = (double)lo;
+                    s_lo = (float)(a.t0 + x * G.dx[0] - tA);
+                    U_lo = (float)(fma(x, G.dx[1], a.U0) * sad);
+                    V_lo = (float)(fma(x, G.dx[2], a.V0) * sad);
+                } else {
+                    lo = 0;
+                    hi = -1;
                 }
             }
-            const uint64_t mask = __ballot(member);
-            const uint32_t slot = DENSE ? (uint32_t)lane : (uint32_t)mbcnt64(mask);
-            const float sl = from_row_f(s_lo);
-            const float ul = from_row_f(U_lo);
-            const float vl = from_row_f(V_lo);
-            // this chunk's entries go to [written, written + popcount); the bases are wave-uniform
-            const gptr<char> ip = (gptr<char>)(out_idx + written);
-            const gptr<char> vp = (gptr<char>)(out_val + written);
-            float D = 0.0f;
-            if (SURR) {
-                // the network runs on all 64 lanes (matrix cores need the whole wave)
-                const float kf = (float)k;
-                const float sv = fmaf(kf, t1f, sl), Uv = fmaf(kf, U1f, ul), Vv = fmaf(kf, V1f, vl);
-                const float rr_ = __builtin_amdgcn_rcpf(sv + c.tA);
-                const float g = sad_f * rr_;
-                const float au = fabsf(Uv * rr_), av = fabsf(Vv * rr_);
-                const float tau = __builtin_amdgcn_fmed3f(sv * c.inv_step, 0.0f, c.tau_max);
-                const float2 q = s_tab[(int)tau];
-                const float d = fmaf(tau, q.y, q.x);
-                const bool in_box = member && mlp_ok && d <= kMlpDMax && au <= kMlpUVMax &&
-                                    av <= kMlpUVMax;
-                float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                if (in_box) mlp::features(d, au, av, a_f, x);
-                // the network only for chunks with a sample inside the training box
-                float y = 0.0f;
-                if (__ballot(in_box)) y = mlp::forward_wave<true>(P.mlp_p, s_b1x, wf, x, s_h1);
-                if (in_box) D = y * g * g;
-                else if (member) D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
+            // the next tile's list entries, loaded once this tile's row extents have arrived: the
+            // vector memory counter retires in order, so an earlier issue would make the wait for
+            // those extents wait for this load as well
+            after_span();
+            int cnt = hi - lo + 1;
+            {
+                // rows with candidates move to the low lanes, in order, empty rows after them
+                // (a permutation of the wave), so that row starts are distinct candidates
+                const uint64_t ne = __ballot(cnt > 0);
+                const int dst = cnt > 0 ? mbcnt64(ne) : __popcll(ne) + mbcnt64(~ne);
+                const int a = dst << 2;
+                lo = __builtin_amdgcn_ds_permute(a, lo);
+                cnt = __builtin_amdgcn_ds_permute(a, cnt);
+                cb = __builtin_amdgcn_ds_permute(a, cb);
+                wb = __builtin_amdgcn_ds_permute(a, wb);
+                s_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(s_lo)));
+                U_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(U_lo)));
+                V_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(V_lo)));
             }
-            if (member) {
-                const float kf = (float)k;
-                if (GEN)
-                    D = dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
-                                                  fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
-                else if (!SURR)
-                    D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
-                                                     fmaf(kf, V1f, vl));
-                if (FITS) {
-                    const int so = (int)(written - out0) << 2;
-                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, (int)(slot << 2), so, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D), rs_val, (int)(slot << 2), so, 0);
+            const int n_ne = __popcll(__ballot(cnt > 0));
+            const int incl = wave_incl_scan(cnt);
+            const int excl = incl - cnt;
+            const int total = readlane(incl, kWave - 1);   // wave-uniform: the chunk loop stays scalar
+            // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
+            // rows are walked once, wave-uniformly, as the chunks advance (rcur: row of
+            // the first candidate of the next chunk)
+            int rcur = 0;
+            int64_t written = out0;
+            // a tile whose counted members equal its candidates (no masked voxel inside its rows)
+            // takes every candidate: no mask read, and member lanes are the low ones of the chunk
+            const bool dense = members == total;
+            // the tile's entries fit the caller's arrays: no per-chunk capacity test, and they are
+            // written through buffer descriptors over exactly the tile's entries (32-bit offsets:
+            // the lane's slot in a VGPR, the chunk's start in an SGPR)
+            const bool fits = out0 + members <= capacity;
+            const __amdgpu_buffer_rsrc_t rs_idx =
+                __builtin_amdgcn_make_buffer_rsrc(O.indices + out0, 0, members * 4, kRawBufferWord3);
+            const __amdgpu_buffer_rsrc_t rs_val =
+                __builtin_amdgcn_make_buffer_rsrc(O.values + out0, 0, members * 4, kRawBufferWord3);
+            // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
+            auto chunk = [&](const int p, const int rr, auto dense_tag, auto fits_tag) {
+                constexpr bool DENSE = decltype(dense_tag)::value;
+                constexpr bool FITS = decltype(fits_tag)::value;
+                // row rr's values, fetched by lane (rr < 64: the byte address needs no wrap)
+                const int ra = rr << 2;
+                auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
+                auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
+                const int k = p - from_row(excl);
+                const int col = from_row(cb) + k;
+                bool member = false;
+                if (DENSE) {
+                    member = p < total;
                 } else {
-                    // slots below `avail` fit in the caller's arrays
-                    const int64_t left = capacity - written;
-                    const uint32_t avail = left >= kWave ? (uint32_t)kWave : (left > 0 ? (uint32_t)left : 0u);
-                    if (slot < avail) {
-                        *(gptr<int32_t>)(ip + (slot << 2)) = col;
-                        *(gptr<float>)(vp + (slot << 2)) = D;
-                    } else {
-                        *O.overflow = 1;
+                    const int wr = from_row(wb), ix = from_row(lo) + k;
+                    if (p < total) {
+                        const uint32_t wo = ((uint32_t)wr + ((uint32_t)ix >> 5)) << 2;   // byte offset
+                        member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
                     }
                 }
-            }
-            written += __popcll(mask);
-        };
-        auto walk2 = [&](auto dense_tag, auto fits_tag) {
-            // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane.
-            // Bit b of (mhi:mlo) marks a row starting at candidate c0 + b (0 < b < 128);
-            // a lane's row is rcur plus the row starts at or below its candidate, a
-            // masked bit count of the mask shifted down by one
-            for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
-                uint64_t mlo = 0, mhi = 0;
-                int rnext = rcur;
-                for (int q = rcur + 1; q < n_ne; ++q) {
-                    const int b = readlane(excl, q) - c0;
-                    if (b > 2 * kWave) break;
-                    rnext = q;
-                    if (b == 2 * kWave) break;
-                    if (b < kWave) mlo |= 1ull << b;
-                    else mhi |= 1ull << (b - kWave);
+                const uint64_t mask = __ballot(member);
+                const uint32_t slot = DENSE ? (uint32_t)lane : (uint32_t)mbcnt64(mask);
+                const float sl = from_row_f(s_lo);
+                const float ul = from_row_f(U_lo);
+                const float vl = from_row_f(V_lo);
+                // this chunk's entries go to [written, written + popcount); the bases are wave-uniform
+                const gptr<char> ip = (gptr<char>)(out_idx + written);
+                const gptr<char> vp = (gptr<char>)(out_val + written);
+                float D = 0.0f;
+                if (SURR) {
+                    // the network runs on all 64 lanes (matrix cores need the whole wave)
+                    const float kf = (float)k;
+                    const float sv = fmaf(kf, t1f, sl), Uv = fmaf(kf, U1f, ul), Vv = fmaf(kf, V1f, vl);
+                    const float rr_ = __builtin_amdgcn_rcpf(sv + c.tA);
+                    const float g = sad_f * rr_;
+                    const float au = fabsf(Uv * rr_), av = fabsf(Vv * rr_);
+                    const float tau = __builtin_amdgcn_fmed3f(sv * c.inv_step, 0.0f, c.tau_max);
+                    const float2 q = s_tab[(int)tau];
+                    const float d = fmaf(tau, q.y, q.x);
+                    const bool in_box = member && mlp_ok && d <= kMlpDMax && au <= kMlpUVMax &&
+                                        av <= kMlpUVMax;
+                    float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (in_box) mlp::features(d, au, av, a_f, x);
+                    // the network only for chunks with a sample inside the training box
+                    float y = 0.0f;
+                    if (__ballot(in_box)) y = mlp::forward_wave<true>(P.mlp_p, s_b1x, wf, x, s_h1);
+                    if (in_box) D = y * g * g;
+                    else if (member) D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
                 }
-                const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
-                const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rcur));
-                const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rcur + __popcll(nlo))));
-                chunk(c0 + lane, r1, dense_tag, fits_tag);
-                chunk(c0 + kWave + lane, r2, dense_tag, fits_tag);
-                rcur = rnext;
-            }
-        };
-        // dense tiles whose entries fit: a lane takes two consecutive candidates of one row
-        // (pair slot q of a row holds its candidates 2q and 2q + 1), so that the row lookup,
-        // the row walk and the column arithmetic serve two entries; each entry's value is
-        // computed exactly as in a chunk of single candidates
-        auto pair_chunk = [&](const int q, const int rr, const int pexcl, const int ptotal) {
-            const int ra = rr << 2;
-            auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
-            auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
-            const int k0 = (q - from_row(pexcl)) << 1;
-            const int e0 = from_row(excl) + k0;            // tile-local entry of candidate k0
-            const int cn = from_row(cnt);
-            const int col = from_row(cb) + k0;
-            const float sl = from_row_f(s_lo), ul = from_row_f(U_lo), vl = from_row_f(V_lo);
-            if (q < ptotal) {
-                const bool two = k0 + 1 < cn;
-                auto value = [&](float kf) {
+                if (member) {
+                    const float kf = (float)k;
                     if (GEN)
-                        return dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
-                                                     fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
-                    return dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
-                                                    fmaf(kf, V1f, vl));
-                };
-                // the second candidate of a row's last, odd slot is evaluated at the first (and not stored)
-                const float D0 = value((float)k0), D1 = value((float)(two ? k0 + 1 : k0));
-                __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, e0 << 2, 0, 0);
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D0), rs_val, e0 << 2, 0, 0);
-                if (two) {
-                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(col + 1), rs_idx, (e0 + 1) << 2, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D1), rs_val, (e0 + 1) << 2, 0, 0);
+                        D = dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                                                      fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
+                    else if (!SURR)
+                        D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                                         fmaf(kf, V1f, vl));
+                    if (FITS) {
+                        const int so = (int)(written - out0) << 2;
+                        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, (int)(slot << 2), so, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D), rs_val, (int)(slot << 2), so, 0);
+                    } else {
+                        // slots below `avail` fit in the caller's arrays
+                        const int64_t left = capacity - written;
+                        const uint32_t avail = left >= kWave ? (uint32_t)kWave : (left > 0 ? (uint32_t)left : 0u);
+                        if (slot < avail) {
+                            *(gptr<int32_t>)(ip + (slot << 2)) = col;
+                            *(gptr<float>)(vp + (slot << 2)) = D;
+                        } else {
+                            *O.overflow = 1;
+                        }
+                    }
                 }
-            }
-        };
-        auto walk_pairs = [&]() {
-            // the row walk of walk2 over pair slots: bit b of (mhi:mlo) marks a row whose
-            // first pair slot is c0 + b
-            const int np = (cnt + 1) >> 1;
-            const int pincl = wave_incl_scan(np);
-            const int pexcl = pincl - np;
-            const int ptotal = readlane(pincl, kWave - 1);
-            int rc = 0;
-            for (int c0 = 0; c0 < ptotal; c0 += 2 * kWave) {
-                uint64_t mlo = 0, mhi = 0;
-                int rnext = rc;
-                for (int q = rc + 1; q < n_ne; ++q) {
-                    const int b = readlane(pexcl, q) - c0;
-                    if (b > 2 * kWave) break;
-                    rnext = q;
-                    if (b == 2 * kWave) break;
-                    if (b < kWave) mlo |= 1ull << b;
-                    else mhi |= 1ull << (b - kWave);
+                written += __popcll(mask);
+            };
+            auto walk2 = [&](auto dense_tag, auto fits_tag) {
+                // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane.
+                // Bit b of (mhi:mlo) marks a row starting at candidate c0 + b (0 < b < 128);
+                // a lane's row is rcur plus the row starts at or below its candidate, a
+                // masked bit count of the mask shifted down by one
+                for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
+                    uint64_t mlo = 0, mhi = 0;
+                    int rnext = rcur;
+                    for (int q = rcur + 1; q < n_ne; ++q) {
+                        const int b = readlane(excl, q) - c0;
+                        if (b > 2 * kWave) break;
+                        rnext = q;
+                        if (b == 2 * kWave) break;
+                        if (b < kWave) mlo |= 1ull << b;
+                        else mhi |= 1ull << (b - kWave);
+                    }
+                    const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
+                    const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rcur));
+                    const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rcur + __popcll(nlo))));
+                    chunk(c0 + lane, r1, dense_tag, fits_tag);
+                    chunk(c0 + kWave + lane, r2, dense_tag, fits_tag);
+                    rcur = rnext;
                 }
-                const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
-                const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rc));
-                const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rc + __popcll(nlo))));
-                pair_chunk(c0 + lane, r1, pexcl, ptotal);
-                pair_chunk(c0 + kWave + lane, r2, pexcl, ptotal);
-                rc = rnext;
-            }
-        };
-        if (!SURR) {
-            if (fits) {
-                if (dense) walk_pairs();
-                else walk2(std::false_type{}, std::true_type{});
+            };
+            // dense tiles whose entries fit: a lane takes two consecutive candidates of one row
+            // (pair slot q of a row holds its candidates 2q and 2q + 1), so that the row lookup,
+            // the row walk and the column arithmetic serve two entries; each entry's value is
+            // computed exactly as in a chunk of single candidates
+            auto pair_chunk = [&](const int q, const int rr, const int pexcl, const int ptotal) {
+                const int ra = rr << 2;
+                auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
+                auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
+                const int k0 = (q - from_row(pexcl)) << 1;
+                const int e0 = from_row(excl) + k0;            // tile-local entry of candidate k0
+                const int cn = from_row(cnt);
+                const int col = from_row(cb) + k0;
+                const float sl = from_row_f(s_lo), ul = from_row_f(U_lo), vl = from_row_f(V_lo);
+                if (q < ptotal) {
+                    const bool two = k0 + 1 < cn;
+                    auto value = [&](float kf) {
+                        if (GEN)
+                            return dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                                                         fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
+                        return dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                                        fmaf(kf, V1f, vl));
+                    };
+                    // the second candidate of a row's last, odd slot is evaluated at the first (and not stored)
+                    const float D0 = value((float)k0), D1 = value((float)(two ? k0 + 1 : k0));
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, e0 << 2, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D0), rs_val, e0 << 2, 0, 0);
+                    if (two) {
+                        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(col + 1), rs_idx, (e0 + 1) << 2, 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D1), rs_val, (e0 + 1) << 2, 0, 0);
+                    }
+                }
+            };
+            auto walk_pairs = [&]() {
+                // the row walk of walk2 over pair slots: bit b of (mhi:mlo) marks a row whose
+                // first pair slot is c0 + b
+                const int np = (cnt + 1) >> 1;
+                const int pincl = wave_incl_scan(np);
+                const int pexcl = pincl - np;
+                const int ptotal = readlane(pincl, kWave - 1);
+                int rc = 0;
+                for (int c0 = 0; c0 < ptotal; c0 += 2 * kWave) {
+                    uint64_t mlo = 0, mhi = 0;
+                    int rnext = rc;
+                    for (int q = rc + 1; q < n_ne; ++q) {
+                        const int b = readlane(pexcl, q) - c0;
+                        if (b > 2 * kWave) break;
+                        rnext = q;
+                        if (b == 2 * kWave) break;
+                        if (b < kWave) mlo |= 1ull << b;
+                        else mhi |= 1ull << (b - kWave);
+                    }
+                    const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
+                    const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rc));
+                    const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rc + __popcll(nlo))));
+                    pair_chunk(c0 + lane, r1, pexcl, ptotal);
+                    pair_chunk(c0 + kWave + lane, r2, pexcl, ptotal);
+                    rc = rnext;
+                }
+            };
+            if (!SURR) {
+                if (fits) {
+                    if (dense) walk_pairs();
+                    else walk2(std::false_type{}, std::true_type{});
+                } else {
+                    walk2(std::false_type{}, std::false_type{});
+                }
             } else {
-                walk2(std::false_type{}, std::false_type{});
-            }
-        } else {
-            for (int c0 = 0; c0 < total; c0 += kWave) {
-                while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
-                const int p = c0 + lane;
-                int rr = rcur;
-                for (int q = rcur + 1; q < kWave; ++q) {
-                    const int eq = readlane(excl, q);
-                    if (eq > c0 + kWave - 1) break;
-                    if (p >= eq) rr = q;
+                for (int c0 = 0; c0 < total; c0 += kWave) {
+                    while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
+                    const int p = c0 + lane;
+                    int rr = rcur;
+                    for (int q = rcur + 1; q < kWave; ++q) {
+                        const int eq = readlane(excl, q);
+                        if (eq > c0 + kWave - 1) break;
+                        if (p >= eq) rr = q;
+                    }
+                    chunk(p, rr, std::false_type{}, std::false_type{});
                 }
-                chunk(p, rr, std::false_type{}, std::false_type{});
             }
+    };
+    if (!use_list) {
+        for (int tg = wave * tile_group; tg < n_tiles; tg += W * tile_group)
+            for (int tl = tg; tl < tg + tile_group && tl < n_tiles; ++tl) {
+                const int r = tl * kRowsPerTile + lane;
+                tile(tl, r < n_list ? r : -1, [] {});
+            }
+    } else {
+        int r_next = list_entry(wave * tile_group);
+        for (int tl = wave * tile_group; tl < n_tiles; tl = next_tile(tl)) {
+            const int r = r_next;
+            tile(tl, r, [&] { r_next = list_entry(next_tile(tl)); });
         }
     }
 }
 
+// the analytic form's register budget at one or two terms: six waves per SIMD (80 VGPRs)
 template <int K, bool SURR, bool GEN, int EM>
-__global__ __launch_bounds__(kBlock) void k_fill(const PlanDev *__restrict__ plans,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SURR || GEN || K > 2 ? 1 : 6))) void k_fill(const PlanDev *__restrict__ plans,
                                                   const OutDev *__restrict__ outs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
