@@ -427,25 +427,27 @@ struct RowListBuilder {
     int n = 0;           // rows in the list so far
     int acc = 0;         // members of the list tile being filled (tile n / 64)
 
-    /* rows of one group of 64: row r (this lane's) with x members; returns the group's members */
+    /* rows of one group of 64: row r (this lane's) with x >= 0 members; returns the group's
+     * members.  The group's rows fill tile n / 64 and perhaps start the next (64 rows at most). */
     __device__ int append(int x, int r)
     {
         const uint64_t ne = __ballot(x > 0);
         const int pos = n + mbcnt64(ne);
         if (x > 0) list[pos] = r;
-        const int t0 = n >> 6;
-        const bool same = (pos >> 6) == t0;
-        const int sa = wave_sum(x > 0 && same ? x : 0);    // members joining tile t0
-        const int sb = wave_sum(x > 0 && !same ? x : 0);   // and the next tile (<= 64 rows: at most two)
-        const int cnt = __popcll(ne);
-        if (((n + cnt) >> 6) != t0) {                       // tile t0 is complete
+        const int incl = wave_incl_scan(x);                 // members of this lane's row and those below
+        const int sum = __builtin_amdgcn_readlane(incl, kWave - 1);
+        const int cnt = __popcll(ne), t0 = n >> 6, room = 64 * (t0 + 1) - n;
+        if (cnt >= room) {
+            // tile t0 is complete: its last row is the one at list position n + room - 1
+            const uint64_t last = __ballot(x > 0 && pos == n + room - 1);
+            const int sa = __builtin_amdgcn_readlane(incl, (int)__builtin_ctzll(last));
             if (lane_id() == 0) tiles[t0] = acc + sa;
-            acc = sb;
+            acc = sum - sa;
         } else {
-            acc += sa;
+            acc += sum;
         }
         n += cnt;
-        return sa + sb;
+        return sum;
     }
     /* the last, partial tile */
     __device__ void finish()
