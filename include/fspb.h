@@ -131,8 +131,9 @@ typedef struct {
     double table_step;           /* nominal depth-table element; <= 0 selects half the
                                     smallest voxel spacing (Sec. 3.2) */
     float rho_min;               /* voxels with density <= rho_min are in no VOI */
-    uint32_t flags;              /* 0, or FSPB_DEPTH_TRILINEAR and at most one of
-                                    FSPB_ERF_COMPACT, FSPB_ERF_MIRRORED */
+    uint32_t flags;              /* 0, or FSPB_DEPTH_TRILINEAR, at most one of
+                                    FSPB_ERF_COMPACT, FSPB_ERF_MIRRORED, and at most
+                                    one of FSPB_TILES_BLOCK, FSPB_TILES_LIST */
     const fspb_kernel_tables *tables;   /* NULL: the analytic form above (weight, sigma0,
                                            sigma_slope, width_scale, pdd); else these tables
                                            replace them (pdd is still validated, unused) */
@@ -160,6 +161,17 @@ typedef struct {
  */
 #define FSPB_ERF_COMPACT  2u
 #define FSPB_ERF_MIRRORED 4u
+
+/*
+ * kernel.flags: how the fill walks a beamlet's VOI rows (the coefficients are
+ * the same either way, bit for bit).  By default the count pass chooses per
+ * beamlet: tiles of 64 consecutive grid rows of the beamlet's bounding row
+ * block, or, where fewer than half of those rows hold a VOI member, tiles of
+ * 64 entries of the list of rows that do.  These flags force one kind for
+ * every beamlet of the plan (for testing both; the default is the faster).
+ */
+#define FSPB_TILES_BLOCK  8u
+#define FSPB_TILES_LIST  16u
 
 /* Static description of a created plan. */
 typedef struct {

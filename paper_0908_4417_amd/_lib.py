@@ -21,6 +21,8 @@ FSPB_ERR_OVERFLOW = -6
 FSPB_DEPTH_TRILINEAR = 1       # fspb_kernel.flags: trilinear-sampled depth table
 FSPB_ERF_COMPACT = 2           # fspb_kernel.flags: force the 8 KB erf table on [0, 4]
 FSPB_ERF_MIRRORED = 4          # fspb_kernel.flags: force the 16 KB erf table mirrored onto [-4, 4]
+FSPB_TILES_BLOCK = 8           # fspb_kernel.flags: fill every beamlet in tiles of its row block
+FSPB_TILES_LIST = 16           # fspb_kernel.flags: fill every beamlet in tiles of its member-row list
 
 
 class FspbError(RuntimeError):

@@ -95,6 +95,7 @@ struct alignas(16) PlanDev {
     int32_t n_tiles;
     int32_t max_tiles;           // most tiles of any beamlet
     int32_t depth_mode;          // 0: exact path integral; 1: trilinear samples + trapezoids
+    int32_t tiles_mode;          // fill tiles: 0 chosen per beamlet, 1 row block, 2 row list
     const BeamletRec *rec;
     float *tables;
     // Fill tiles, from the count pass: either the beamlet's row block in runs of kRowsPerTile

@@ -260,10 +260,12 @@ fspb_status validate(const fspb_grid *g, const fspb_beam *beams, int32_t n_beams
     if (!finite(K->cutoff_u) || !finite(K->cutoff_v) || !finite(K->table_step))
         return fail(FSPB_ERR_INVALID, "kernel cutoffs and table_step must be finite");
     if (!std::isfinite(K->rho_min)) return fail(FSPB_ERR_INVALID, "kernel.rho_min must be finite");
-    if (K->flags & ~(FSPB_DEPTH_TRILINEAR | FSPB_ERF_COMPACT | FSPB_ERF_MIRRORED))
+    if (K->flags & ~(FSPB_DEPTH_TRILINEAR | FSPB_ERF_COMPACT | FSPB_ERF_MIRRORED | FSPB_TILES_BLOCK | FSPB_TILES_LIST))
         return fail(FSPB_ERR_INVALID, "kernel.flags has unknown bits");
     if ((K->flags & FSPB_ERF_COMPACT) && (K->flags & FSPB_ERF_MIRRORED))
         return fail(FSPB_ERR_INVALID, "kernel.flags: FSPB_ERF_COMPACT and FSPB_ERF_MIRRORED exclude each other");
+    if ((K->flags & FSPB_TILES_BLOCK) && (K->flags & FSPB_TILES_LIST))
+        return fail(FSPB_ERR_INVALID, "kernel.flags: FSPB_TILES_BLOCK and FSPB_TILES_LIST exclude each other");
     if (const fspb_kernel_tables *T = K->tables) {
         if (T->n_depth < 2 || T->n_adepth < 2 || T->n_theta < 1 || T->reserved != 0)
             return fail(FSPB_ERR_INVALID, "kernel.tables: n_depth, n_adepth must be >= 2, n_theta >= 1, reserved 0");
@@ -577,6 +579,7 @@ fspb_status fspb_plan_create(const fspb_grid *g, const fspb_beam *beams, int32_t
     h.density = g->density;
     h.rho_min = K->rho_min;
     h.depth_mode = (K->flags & FSPB_DEPTH_TRILINEAR) ? 1 : 0;
+    h.tiles_mode = (K->flags & FSPB_TILES_BLOCK) ? 1 : ((K->flags & FSPB_TILES_LIST) ? 2 : 0);
     h.n_terms = K->n_terms;
     h.n_pdd = K->n_pdd;
     for (int i = 0; i < fspb::kMaxTerms; ++i) {

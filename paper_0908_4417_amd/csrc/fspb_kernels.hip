@@ -491,7 +491,8 @@ __device__ void count_beamlet(const PlanDev &P, int j)
     L.finish();
     if (lane == 0) {
         P.row_nnz[j] = total;
-        P.row_ne[j] = 2 * L.n < n_rows ? L.n : -1;
+        const bool list = P.tiles_mode == 0 ? 2 * L.n < n_rows : P.tiles_mode == 2;
+        P.row_ne[j] = list ? L.n : -1;
     }
 }
 

@@ -84,9 +84,10 @@ class VoxelCSR:
 
 
 _ERF_FORMS = {None: 0, "compact": L.FSPB_ERF_COMPACT, "mirrored": L.FSPB_ERF_MIRRORED}
+_TILES = {None: 0, "block": L.FSPB_TILES_BLOCK, "list": L.FSPB_TILES_LIST}
 
 
-def _structs(problem, density_ptr, erf_form=None):
+def _structs(problem, density_ptr, erf_form=None, tiles=None):
     g = problem.grid
     nz, ny, nx = g.density.shape
     grid = L.FspbGrid(nx, ny, nz, 0, (C.c_double * 3)(*g.spacing), (C.c_double * 3)(*g.origin),
@@ -101,7 +102,8 @@ def _structs(problem, density_ptr, erf_form=None):
     kern = L.FspbKernel(kp.n_terms, len(pdd), pad(kp.weight), pad(kp.sigma0), pad(kp.sigma_slope),
                         pad(kp.width_scale), pdd.ctypes.data_as(C.POINTER(C.c_float)), kp.pdd_step,
                         kp.cutoff_u, kp.cutoff_v, kp.table_step, kp.rho_min,
-                        (L.FSPB_DEPTH_TRILINEAR if kp.depth == "trilinear" else 0) | _ERF_FORMS[erf_form])
+                        (L.FSPB_DEPTH_TRILINEAR if kp.depth == "trilinear" else 0) | _ERF_FORMS[erf_form]
+                        | _TILES[tiles])
     kt = getattr(kp, "tables", None)
     if kt is not None:
         arrs = [np.ascontiguousarray(x, dtype=np.float32) for x in (kt.c1, kt.c2, kt.c3, kt.A)]
@@ -131,17 +133,19 @@ class Plan:
     fields).  The density is copied to the device once; the plan borrows that
     tensor, and ``set_density`` may overwrite it in place (same shape) before
     the next ``raytrace``.  ``erf_form`` ("compact", "mirrored") forces the
-    fill's erf table form; None lets plan creation choose it.
+    fill's erf table form; None lets plan creation choose it.  ``tiles``
+    ("block", "list") forces how the fill walks every beamlet's VOI rows; None
+    lets the count pass choose per beamlet.
     """
 
-    def __init__(self, problem, device="cuda:0", density=None, erf_form=None):
+    def __init__(self, problem, device="cuda:0", density=None, erf_form=None, tiles=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         if density is None:
             density = torch.from_numpy(np.ascontiguousarray(problem.grid.density, dtype=np.float32))
         self.density = density.to(self.device, dtype=torch.float32).contiguous()
-        grid, beams, kern, self._pdd = _structs(problem, self.density.data_ptr(), erf_form)
+        grid, beams, kern, self._pdd = _structs(problem, self.density.data_ptr(), erf_form, tiles)
         st, _, need = L.fspb_plan_create(grid, beams, len(problem.beams), kern, None, 0)
         assert st == L.FSPB_ERR_CAPACITY
         self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=self.device)

@@ -84,8 +84,9 @@ def test_workspace_query(fspb):
     (lambda g, b, k: k.width_scale.__setitem__(0, 0.0), "width_scale"),
     (lambda g, b, k: setattr(k, "n_pdd", 1), "n_pdd"),
     (lambda g, b, k: setattr(k, "pdd_step", 0.0), "pdd_step"),
-    (lambda g, b, k: setattr(k, "flags", 8), "flags"),
+    (lambda g, b, k: setattr(k, "flags", 32), "flags"),
     (lambda g, b, k: setattr(k, "flags", 6), "exclude each other"),
+    (lambda g, b, k: setattr(k, "flags", 24), "FSPB_TILES_BLOCK and FSPB_TILES_LIST"),
     (lambda g, b, k: setattr(k, "rho_min", float("inf")), "rho_min"),
 ])
 def test_invalid_arguments_rejected_before_device_work(fspb, mutate, msg):

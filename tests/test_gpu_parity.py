@@ -209,6 +209,40 @@ def test_pelvis_like_small_full_parity(torch_gpu, oracle_lib):
     _say(f"  nnz={csr.nnz} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e} band={r['band_mismatches']}")
 
 
+@pytest.mark.parametrize("grid", ["pelvis", "slab"])
+def test_fill_tiles_forced(torch_gpu, oracle_lib, grid):
+    """The fill's two ways of walking a beamlet's VOI rows, forced on the same
+    plan (FSPB_TILES_BLOCK: tiles of its row block; FSPB_TILES_LIST: tiles of
+    the list of rows with members, taken by default where most block rows are
+    empty, as around a body): each against the oracle in full, and the two
+    CSRs and the default's identical bit for bit (the tiling changes which
+    wave computes an entry, not how)."""
+    from paper_0908_4417_amd import Plan
+    if grid == "pelvis":
+        g = fi.pelvis_phantom(9, n=(96, 80, 20), spacing=(0.4, 0.4, 0.6))
+        beams = fi.coplanar_beams(9, (0.0, 0.0, 0.0), 100.0, 0.5, 0.5, 8, 6, step_deg=40.0)
+    else:
+        g = fi.slab_phantom(45, n=(41, 37, 29), spacing=(0.45, 0.5, 0.55), lung_side=(2, 8), bone_side=(1, 3))
+        beams = fi.coplanar_beams(5, (0.2, 0.1, -0.1), 90.0, 0.6, 0.6, 7, 5, step_deg=72.0)
+    prob = fi.Problem("tiles_" + grid, g, beams, fi.default_kernel(9))
+    ora = oracle_lib.OraclePlan(prob)
+    out = {}
+    for tiles in ("block", "list", None):
+        plan = Plan(prob, "cuda:0", tiles=tiles)
+        csr = plan.compute()
+        torch_gpu.cuda.synchronize()
+        out[tiles] = (csr.indptr.cpu().numpy(), csr.indices.cpu().numpy(), csr.values.cpu().numpy())
+        if tiles is not None:
+            r = compare_plan(ora, csr)
+            _say(f"  {grid} tiles={tiles}: nnz={csr.nnz} max_rel={r['max_rel']:.2e} eps={r['eps']:.2e} "
+                 f"band={r['band_mismatches']}")
+        del csr, plan
+    for tiles in ("list", None):
+        for a, b in zip(out["block"], out[tiles]):
+            np.testing.assert_array_equal(a.view(np.int32) if a.dtype == np.float32 else a,
+                                          b.view(np.int32) if b.dtype == np.float32 else b)
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_full_size_workloads_sampled(torch_gpu, oracle_lib, k):
     """The 128^3 slab and 256 x 256 x 100 pelvis at full size; 24 seeded rows each."""
