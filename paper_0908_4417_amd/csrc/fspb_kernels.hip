@@ -803,9 +803,10 @@ __device__ inline int readlane(int v, int lane) { return __builtin_amdgcn_readla
 
 /*
  * D_ij of beamlet j (one CSR row) by a workgroup of W waves: LDS-staged
- * tables, then each wave takes tiles of 64 grid rows (runs of the row list the
- * count pass built: rows with members only); a tile's VOI candidates are
- * flattened across its rows, 64 per chunk, members compacted by ballot.
+ * tables, then each wave takes tiles of 64 grid rows (64 consecutive rows of
+ * the beamlet's row block, or 64 entries of the list of its rows with members,
+ * as the count pass chose); a tile's VOI candidates are flattened across its
+ * rows, 64 per chunk, members compacted by ballot.
  * K = unrolled term count; GUARD: stop at P.n_terms (plans of mixed K);
  * EM: how erf is read (erf_mirrored_mode).
  */
@@ -954,9 +955,9 @@ __device__ __attribute__((always_inline)) inline void fill_beamlet(const PlanDev
         __syncthreads();
     }
 
-    // the wave's tiles: runs of tile_group consecutive tiles, every W-th run.  Lane = an entry
-    // of the row list, a grid row r of the beamlet's row block; the next tile's entries are
-    // loaded while this tile is walked (the list, written by the count pass, is not in L2)
+    // the wave's tiles: runs of tile_group consecutive tiles, every W-th run.  Lane = a grid
+    // row r of the beamlet's row block (of a block tile, or an entry of the row list); with the
+    // list, the next tile's entries are loaded while this tile is walked
     auto next_tile = [&](int t) { return (t + 1) % tile_group != 0 ? t + 1 : t + 1 + (W - 1) * tile_group; };
     auto list_entry = [&](int t) {
         const int li = t * kRowsPerTile + lane;
@@ -972,252 +973,252 @@ __device__ __attribute__((always_inline)) inline void fill_beamlet(const PlanDev
             after_span();
             return;
         }
-            const int64_t out0 = row_base + __builtin_amdgcn_readfirstlane(s_tpre[tl]);
-            int lo = 0, hi = -1, cb = 0, wb = 0;
-            float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
-            if (r >= 0) {
-                const int iy = iy0 + (int)((uint32_t)r % (uint32_t)n_iy), iz = iz0 + (int)((uint32_t)r / (uint32_t)n_iy);
-                RowAffine a;
-                // the block is read from LDS here, tile by tile (an offset the compiler cannot see
-                // through keeps it from being held in registers across the tile loop)
-                uint32_t goff = 0;
-                asm volatile("" : "+s"(goff));
-                const RowGeom G = row_geom(reinterpret_cast<const double *>(reinterpret_cast<const char *>(&s_geom) + goff));
-                bool holes;
-                if (row_span(G, c1_pos, c1_neg, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
-                    const int grow = iz * ny + iy;
-                    cb = grow * nx + lo;
-                    wb = grow * wpr;
-                    const double x = (double)lo;
-                    s_lo = (float)(a.t0 + x * G.dx[0] - tA);
-                    U_lo = (float)(fma(x, G.dx[1], a.U0) * sad);
-                    V_lo = (float)(fma(x, G.dx[2], a.V0) * sad);
-                } else {
-                    lo = 0;
-                    hi = -1;
-                }
-            }
-            // the next tile's list entries, loaded once this tile's row extents have arrived: the
-            // vector memory counter retires in order, so an earlier issue would make the wait for
-            // those extents wait for this load as well
-            after_span();
-            int cnt = hi - lo + 1;
-            {
-                // rows with candidates move to the low lanes, in order, empty rows after them
-                // (a permutation of the wave), so that row starts are distinct candidates
-                const uint64_t ne = __ballot(cnt > 0);
-                const int dst = cnt > 0 ? mbcnt64(ne) : __popcll(ne) + mbcnt64(~ne);
-                const int a = dst << 2;
-                lo = __builtin_amdgcn_ds_permute(a, lo);
-                cnt = __builtin_amdgcn_ds_permute(a, cnt);
-                cb = __builtin_amdgcn_ds_permute(a, cb);
-                wb = __builtin_amdgcn_ds_permute(a, wb);
-                s_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(s_lo)));
-                U_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(U_lo)));
-                V_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(V_lo)));
-            }
-            const int n_ne = __popcll(__ballot(cnt > 0));
-            const int incl = wave_incl_scan(cnt);
-            const int excl = incl - cnt;
-            const int total = readlane(incl, kWave - 1);   // wave-uniform: the chunk loop stays scalar
-            // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
-            // rows are walked once, wave-uniformly, as the chunks advance (rcur: row of
-            // the first candidate of the next chunk)
-            int rcur = 0;
-            int64_t written = out0;
-            // a tile whose counted members equal its candidates (no masked voxel inside its rows)
-            // takes every candidate: no mask read, and member lanes are the low ones of the chunk
-            const bool dense = members == total;
-            // the tile's entries fit the caller's arrays: no per-chunk capacity test, and they are
-            // written through buffer descriptors over exactly the tile's entries (32-bit offsets:
-            // the lane's slot in a VGPR, the chunk's start in an SGPR)
-            const bool fits = out0 + members <= capacity;
-            const __amdgpu_buffer_rsrc_t rs_idx =
-                __builtin_amdgcn_make_buffer_rsrc(O.indices + out0, 0, members * 4, kRawBufferWord3);
-            const __amdgpu_buffer_rsrc_t rs_val =
-                __builtin_amdgcn_make_buffer_rsrc(O.values + out0, 0, members * 4, kRawBufferWord3);
-            // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
-            auto chunk = [&](const int p, const int rr, auto dense_tag, auto fits_tag) {
-                constexpr bool DENSE = decltype(dense_tag)::value;
-                constexpr bool FITS = decltype(fits_tag)::value;
-                // row rr's values, fetched by lane (rr < 64: the byte address needs no wrap)
-                const int ra = rr << 2;
-                auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
-                auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
-                const int k = p - from_row(excl);
-                const int col = from_row(cb) + k;
-                bool member = false;
-                if (DENSE) {
-                    member = p < total;
-                } else {
-                    const int wr = from_row(wb), ix = from_row(lo) + k;
-                    if (p < total) {
-                        const uint32_t wo = ((uint32_t)wr + ((uint32_t)ix >> 5)) << 2;   // byte offset
-                        member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
-                    }
-                }
-                const uint64_t mask = __ballot(member);
-                const uint32_t slot = DENSE ? (uint32_t)lane : (uint32_t)mbcnt64(mask);
-                const float sl = from_row_f(s_lo);
-                const float ul = from_row_f(U_lo);
-                const float vl = from_row_f(V_lo);
-                // this chunk's entries go to [written, written + popcount); the bases are wave-uniform
-                const gptr<char> ip = (gptr<char>)(out_idx + written);
-                const gptr<char> vp = (gptr<char>)(out_val + written);
-                float D = 0.0f;
-                if (SURR) {
-                    // the network runs on all 64 lanes (matrix cores need the whole wave)
-                    const float kf = (float)k;
-                    const float sv = fmaf(kf, t1f, sl), Uv = fmaf(kf, U1f, ul), Vv = fmaf(kf, V1f, vl);
-                    const float rr_ = __builtin_amdgcn_rcpf(sv + c.tA);
-                    const float g = sad_f * rr_;
-                    const float au = fabsf(Uv * rr_), av = fabsf(Vv * rr_);
-                    const float tau = __builtin_amdgcn_fmed3f(sv * c.inv_step, 0.0f, c.tau_max);
-                    const float2 q = s_tab[(int)tau];
-                    const float d = fmaf(tau, q.y, q.x);
-                    const bool in_box = member && mlp_ok && d <= kMlpDMax && au <= kMlpUVMax &&
-                                        av <= kMlpUVMax;
-                    float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                    if (in_box) mlp::features(d, au, av, a_f, x);
-                    // the network only for chunks with a sample inside the training box
-                    float y = 0.0f;
-                    if (__ballot(in_box)) y = mlp::forward_wave<true>(P.mlp_p, s_b1x, wf, x, s_h1);
-                    if (in_box) D = y * g * g;
-                    else if (member) D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
-                }
-                if (member) {
-                    const float kf = (float)k;
-                    if (GEN)
-                        D = dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
-                                                      fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
-                    else if (!SURR)
-                        D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
-                                                         fmaf(kf, V1f, vl));
-                    if (FITS) {
-                        const int so = (int)(written - out0) << 2;
-                        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, (int)(slot << 2), so, 0);
-                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D), rs_val, (int)(slot << 2), so, 0);
-                    } else {
-                        // slots below `avail` fit in the caller's arrays
-                        const int64_t left = capacity - written;
-                        const uint32_t avail = left >= kWave ? (uint32_t)kWave : (left > 0 ? (uint32_t)left : 0u);
-                        if (slot < avail) {
-                            *(gptr<int32_t>)(ip + (slot << 2)) = col;
-                            *(gptr<float>)(vp + (slot << 2)) = D;
-                        } else {
-                            *O.overflow = 1;
-                        }
-                    }
-                }
-                written += __popcll(mask);
-            };
-            auto walk2 = [&](auto dense_tag, auto fits_tag) {
-                // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane.
-                // Bit b of (mhi:mlo) marks a row starting at candidate c0 + b (0 < b < 128);
-                // a lane's row is rcur plus the row starts at or below its candidate, a
-                // masked bit count of the mask shifted down by one
-                for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
-                    uint64_t mlo = 0, mhi = 0;
-                    int rnext = rcur;
-                    for (int q = rcur + 1; q < n_ne; ++q) {
-                        const int b = readlane(excl, q) - c0;
-                        if (b > 2 * kWave) break;
-                        rnext = q;
-                        if (b == 2 * kWave) break;
-                        if (b < kWave) mlo |= 1ull << b;
-                        else mhi |= 1ull << (b - kWave);
-                    }
-                    const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
-                    const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rcur));
-                    const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rcur + __popcll(nlo))));
-                    chunk(c0 + lane, r1, dense_tag, fits_tag);
-                    chunk(c0 + kWave + lane, r2, dense_tag, fits_tag);
-                    rcur = rnext;
-                }
-            };
-            // dense tiles whose entries fit: a lane takes two consecutive candidates of one row
-            // (pair slot q of a row holds its candidates 2q and 2q + 1), so that the row lookup,
-            // the row walk and the column arithmetic serve two entries; each entry's value is
-            // computed exactly as in a chunk of single candidates
-            auto pair_chunk = [&](const int q, const int rr, const int pexcl, const int ptotal) {
-                const int ra = rr << 2;
-                auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
-                auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
-                const int k0 = (q - from_row(pexcl)) << 1;
-                const int e0 = from_row(excl) + k0;            // tile-local entry of candidate k0
-                const int cn = from_row(cnt);
-                const int col = from_row(cb) + k0;
-                const float sl = from_row_f(s_lo), ul = from_row_f(U_lo), vl = from_row_f(V_lo);
-                if (q < ptotal) {
-                    const bool two = k0 + 1 < cn;
-                    auto value = [&](float kf) {
-                        if (GEN)
-                            return dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
-                                                         fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
-                        return dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
-                                                        fmaf(kf, V1f, vl));
-                    };
-                    // the second candidate of a row's last, odd slot is evaluated at the first (and not stored)
-                    const float D0 = value((float)k0), D1 = value((float)(two ? k0 + 1 : k0));
-                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, e0 << 2, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D0), rs_val, e0 << 2, 0, 0);
-                    if (two) {
-                        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(col + 1), rs_idx, (e0 + 1) << 2, 0, 0);
-                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D1), rs_val, (e0 + 1) << 2, 0, 0);
-                    }
-                }
-            };
-            auto walk_pairs = [&]() {
-                // the row walk of walk2 over pair slots: bit b of (mhi:mlo) marks a row whose
-                // first pair slot is c0 + b
-                const int np = (cnt + 1) >> 1;
-                const int pincl = wave_incl_scan(np);
-                const int pexcl = pincl - np;
-                const int ptotal = readlane(pincl, kWave - 1);
-                int rc = 0;
-                for (int c0 = 0; c0 < ptotal; c0 += 2 * kWave) {
-                    uint64_t mlo = 0, mhi = 0;
-                    int rnext = rc;
-                    for (int q = rc + 1; q < n_ne; ++q) {
-                        const int b = readlane(pexcl, q) - c0;
-                        if (b > 2 * kWave) break;
-                        rnext = q;
-                        if (b == 2 * kWave) break;
-                        if (b < kWave) mlo |= 1ull << b;
-                        else mhi |= 1ull << (b - kWave);
-                    }
-                    const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
-                    const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rc));
-                    const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rc + __popcll(nlo))));
-                    pair_chunk(c0 + lane, r1, pexcl, ptotal);
-                    pair_chunk(c0 + kWave + lane, r2, pexcl, ptotal);
-                    rc = rnext;
-                }
-            };
-            if (!SURR) {
-                if (fits) {
-                    if (dense) walk_pairs();
-                    else walk2(std::false_type{}, std::true_type{});
-                } else {
-                    walk2(std::false_type{}, std::false_type{});
-                }
+        const int64_t out0 = row_base + __builtin_amdgcn_readfirstlane(s_tpre[tl]);
+        int lo = 0, hi = -1, cb = 0, wb = 0;
+        float s_lo = 0.0f, U_lo = 0.0f, V_lo = 0.0f;
+        if (r >= 0) {
+            const int iy = iy0 + (int)((uint32_t)r % (uint32_t)n_iy), iz = iz0 + (int)((uint32_t)r / (uint32_t)n_iy);
+            RowAffine a;
+            // the block is read from LDS here, tile by tile (an offset the compiler cannot see
+            // through keeps it from being held in registers across the tile loop)
+            uint32_t goff = 0;
+            asm volatile("" : "+s"(goff));
+            const RowGeom G = row_geom(reinterpret_cast<const double *>(reinterpret_cast<const char *>(&s_geom) + goff));
+            bool holes;
+            if (row_span(G, c1_pos, c1_neg, P.ext, P.nx, P.ny, iy, iz, lo, hi, a, holes)) {
+                const int grow = iz * ny + iy;
+                cb = grow * nx + lo;
+                wb = grow * wpr;
+                const double x = (double)lo;
+                s_lo = (float)(a.t0 + x * G.dx[0] - tA);
+                U_lo = (float)(fma(x, G.dx[1], a.U0) * sad);
+                V_lo = (float)(fma(x, G.dx[2], a.V0) * sad);
             } else {
-                for (int c0 = 0; c0 < total; c0 += kWave) {
-                    while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
-                    const int p = c0 + lane;
-                    int rr = rcur;
-                    for (int q = rcur + 1; q < kWave; ++q) {
-                        const int eq = readlane(excl, q);
-                        if (eq > c0 + kWave - 1) break;
-                        if (p >= eq) rr = q;
-                    }
-                    chunk(p, rr, std::false_type{}, std::false_type{});
+                lo = 0;
+                hi = -1;
+            }
+        }
+        // the next tile's list entries, loaded once this tile's row extents have arrived: the
+        // vector memory counter retires in order, so an earlier issue would make the wait for
+        // those extents wait for this load as well
+        after_span();
+        int cnt = hi - lo + 1;
+        {
+            // rows with candidates move to the low lanes, in order, empty rows after them
+            // (a permutation of the wave), so that row starts are distinct candidates
+            const uint64_t ne = __ballot(cnt > 0);
+            const int dst = cnt > 0 ? mbcnt64(ne) : __popcll(ne) + mbcnt64(~ne);
+            const int a = dst << 2;
+            lo = __builtin_amdgcn_ds_permute(a, lo);
+            cnt = __builtin_amdgcn_ds_permute(a, cnt);
+            cb = __builtin_amdgcn_ds_permute(a, cb);
+            wb = __builtin_amdgcn_ds_permute(a, wb);
+            s_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(s_lo)));
+            U_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(U_lo)));
+            V_lo = __int_as_float(__builtin_amdgcn_ds_permute(a, __float_as_int(V_lo)));
+        }
+        const int n_ne = __popcll(__ballot(cnt > 0));
+        const int incl = wave_incl_scan(cnt);
+        const int excl = incl - cnt;
+        const int total = readlane(incl, kWave - 1);   // wave-uniform: the chunk loop stays scalar
+        // candidate p of the tile lies on the last row whose exclusive prefix is <= p;
+        // rows are walked once, wave-uniformly, as the chunks advance (rcur: row of
+        // the first candidate of the next chunk)
+        int rcur = 0;
+        int64_t written = out0;
+        // a tile whose counted members equal its candidates (no masked voxel inside its rows)
+        // takes every candidate: no mask read, and member lanes are the low ones of the chunk
+        const bool dense = members == total;
+        // the tile's entries fit the caller's arrays: no per-chunk capacity test, and they are
+        // written through buffer descriptors over exactly the tile's entries (32-bit offsets:
+        // the lane's slot in a VGPR, the chunk's start in an SGPR)
+        const bool fits = out0 + members <= capacity;
+        const __amdgpu_buffer_rsrc_t rs_idx =
+            __builtin_amdgcn_make_buffer_rsrc(O.indices + out0, 0, members * 4, kRawBufferWord3);
+        const __amdgpu_buffer_rsrc_t rs_val =
+            __builtin_amdgcn_make_buffer_rsrc(O.values + out0, 0, members * 4, kRawBufferWord3);
+        // one chunk: candidate p of the tile, on row rr of the tile; every lane of the wave calls it
+        auto chunk = [&](const int p, const int rr, auto dense_tag, auto fits_tag) {
+            constexpr bool DENSE = decltype(dense_tag)::value;
+            constexpr bool FITS = decltype(fits_tag)::value;
+            // row rr's values, fetched by lane (rr < 64: the byte address needs no wrap)
+            const int ra = rr << 2;
+            auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
+            auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
+            const int k = p - from_row(excl);
+            const int col = from_row(cb) + k;
+            bool member = false;
+            if (DENSE) {
+                member = p < total;
+            } else {
+                const int wr = from_row(wb), ix = from_row(lo) + k;
+                if (p < total) {
+                    const uint32_t wo = ((uint32_t)wr + ((uint32_t)ix >> 5)) << 2;   // byte offset
+                    member = (*(const gptr<const uint32_t>)((gptr<const char>)bits + wo) >> (ix & 31)) & 1u;
                 }
             }
+            const uint64_t mask = __ballot(member);
+            const uint32_t slot = DENSE ? (uint32_t)lane : (uint32_t)mbcnt64(mask);
+            const float sl = from_row_f(s_lo);
+            const float ul = from_row_f(U_lo);
+            const float vl = from_row_f(V_lo);
+            // this chunk's entries go to [written, written + popcount); the bases are wave-uniform
+            const gptr<char> ip = (gptr<char>)(out_idx + written);
+            const gptr<char> vp = (gptr<char>)(out_val + written);
+            float D = 0.0f;
+            if (SURR) {
+                // the network runs on all 64 lanes (matrix cores need the whole wave)
+                const float kf = (float)k;
+                const float sv = fmaf(kf, t1f, sl), Uv = fmaf(kf, U1f, ul), Vv = fmaf(kf, V1f, vl);
+                const float rr_ = __builtin_amdgcn_rcpf(sv + c.tA);
+                const float g = sad_f * rr_;
+                const float au = fabsf(Uv * rr_), av = fabsf(Vv * rr_);
+                const float tau = __builtin_amdgcn_fmed3f(sv * c.inv_step, 0.0f, c.tau_max);
+                const float2 q = s_tab[(int)tau];
+                const float d = fmaf(tau, q.y, q.x);
+                const bool in_box = member && mlp_ok && d <= kMlpDMax && au <= kMlpUVMax &&
+                                    av <= kMlpUVMax;
+                float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (in_box) mlp::features(d, au, av, a_f, x);
+                // the network only for chunks with a sample inside the training box
+                float y = 0.0f;
+                if (__ballot(in_box)) y = mlp::forward_wave<true>(P.mlp_p, s_b1x, wf, x, s_h1);
+                if (in_box) D = y * g * g;
+                else if (member) D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, sv, Uv, Vv);
+            }
+            if (member) {
+                const float kf = (float)k;
+                if (GEN)
+                    D = dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                                                  fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
+                else if (!SURR)
+                    D = dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                                     fmaf(kf, V1f, vl));
+                if (FITS) {
+                    const int so = (int)(written - out0) << 2;
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, (int)(slot << 2), so, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D), rs_val, (int)(slot << 2), so, 0);
+                } else {
+                    // slots below `avail` fit in the caller's arrays
+                    const int64_t left = capacity - written;
+                    const uint32_t avail = left >= kWave ? (uint32_t)kWave : (left > 0 ? (uint32_t)left : 0u);
+                    if (slot < avail) {
+                        *(gptr<int32_t>)(ip + (slot << 2)) = col;
+                        *(gptr<float>)(vp + (slot << 2)) = D;
+                    } else {
+                        *O.overflow = 1;
+                    }
+                }
+            }
+            written += __popcll(mask);
+        };
+        auto walk2 = [&](auto dense_tag, auto fits_tag) {
+            // two chunks per row walk: lane takes candidates c0 + lane and c0 + 64 + lane.
+            // Bit b of (mhi:mlo) marks a row starting at candidate c0 + b (0 < b < 128);
+            // a lane's row is rcur plus the row starts at or below its candidate, a
+            // masked bit count of the mask shifted down by one
+            for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
+                uint64_t mlo = 0, mhi = 0;
+                int rnext = rcur;
+                for (int q = rcur + 1; q < n_ne; ++q) {
+                    const int b = readlane(excl, q) - c0;
+                    if (b > 2 * kWave) break;
+                    rnext = q;
+                    if (b == 2 * kWave) break;
+                    if (b < kWave) mlo |= 1ull << b;
+                    else mhi |= 1ull << (b - kWave);
+                }
+                const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
+                const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rcur));
+                const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rcur + __popcll(nlo))));
+                chunk(c0 + lane, r1, dense_tag, fits_tag);
+                chunk(c0 + kWave + lane, r2, dense_tag, fits_tag);
+                rcur = rnext;
+            }
+        };
+        // dense tiles whose entries fit: a lane takes two consecutive candidates of one row
+        // (pair slot q of a row holds its candidates 2q and 2q + 1), so that the row lookup,
+        // the row walk and the column arithmetic serve two entries; each entry's value is
+        // computed exactly as in a chunk of single candidates
+        auto pair_chunk = [&](const int q, const int rr, const int pexcl, const int ptotal) {
+            const int ra = rr << 2;
+            auto from_row = [&](int v) { return __builtin_amdgcn_ds_bpermute(ra, v); };
+            auto from_row_f = [&](float v) { return __int_as_float(__builtin_amdgcn_ds_bpermute(ra, __float_as_int(v))); };
+            const int k0 = (q - from_row(pexcl)) << 1;
+            const int e0 = from_row(excl) + k0;            // tile-local entry of candidate k0
+            const int cn = from_row(cnt);
+            const int col = from_row(cb) + k0;
+            const float sl = from_row_f(s_lo), ul = from_row_f(U_lo), vl = from_row_f(V_lo);
+            if (q < ptotal) {
+                const bool two = k0 + 1 < cn;
+                auto value = [&](float kf) {
+                    if (GEN)
+                        return dose_value_gen<K, EM>(c, s_tab, s_pdd, s_pdd + P.n_adepth, s_erf, fmaf(kf, t1f, sl),
+                                                     fmaf(kf, U1f, ul), fmaf(kf, V1f, vl));
+                    return dose_value<K, GUARD, EM>(c, s_tab, s_pdd, s_erf, fmaf(kf, t1f, sl), fmaf(kf, U1f, ul),
+                                                    fmaf(kf, V1f, vl));
+                };
+                // the second candidate of a row's last, odd slot is evaluated at the first (and not stored)
+                const float D0 = value((float)k0), D1 = value((float)(two ? k0 + 1 : k0));
+                __builtin_amdgcn_raw_buffer_store_b32((uint32_t)col, rs_idx, e0 << 2, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D0), rs_val, e0 << 2, 0, 0);
+                if (two) {
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(col + 1), rs_idx, (e0 + 1) << 2, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(D1), rs_val, (e0 + 1) << 2, 0, 0);
+                }
+            }
+        };
+        auto walk_pairs = [&]() {
+            // the row walk of walk2 over pair slots: bit b of (mhi:mlo) marks a row whose
+            // first pair slot is c0 + b
+            const int np = (cnt + 1) >> 1;
+            const int pincl = wave_incl_scan(np);
+            const int pexcl = pincl - np;
+            const int ptotal = readlane(pincl, kWave - 1);
+            int rc = 0;
+            for (int c0 = 0; c0 < ptotal; c0 += 2 * kWave) {
+                uint64_t mlo = 0, mhi = 0;
+                int rnext = rc;
+                for (int q = rc + 1; q < n_ne; ++q) {
+                    const int b = readlane(pexcl, q) - c0;
+                    if (b > 2 * kWave) break;
+                    rnext = q;
+                    if (b == 2 * kWave) break;
+                    if (b < kWave) mlo |= 1ull << b;
+                    else mhi |= 1ull << (b - kWave);
+                }
+                const uint64_t nlo = (mlo >> 1) | (mhi << 63), nhi = mhi >> 1;
+                const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nlo >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)nlo, (uint32_t)rc));
+                const int r2 = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(nhi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nhi, (uint32_t)(rc + __popcll(nlo))));
+                pair_chunk(c0 + lane, r1, pexcl, ptotal);
+                pair_chunk(c0 + kWave + lane, r2, pexcl, ptotal);
+                rc = rnext;
+            }
+        };
+        if (!SURR) {
+            if (fits) {
+                if (dense) walk_pairs();
+                else walk2(std::false_type{}, std::true_type{});
+            } else {
+                walk2(std::false_type{}, std::false_type{});
+            }
+        } else {
+            for (int c0 = 0; c0 < total; c0 += kWave) {
+                while (rcur + 1 < kWave && readlane(excl, rcur + 1) <= c0) ++rcur;
+                const int p = c0 + lane;
+                int rr = rcur;
+                for (int q = rcur + 1; q < kWave; ++q) {
+                    const int eq = readlane(excl, q);
+                    if (eq > c0 + kWave - 1) break;
+                    if (p >= eq) rr = q;
+                }
+                chunk(p, rr, std::false_type{}, std::false_type{});
+            }
+        }
     };
     if (!use_list) {
         for (int tg = wave * tile_group; tg < n_tiles; tg += W * tile_group)
