@@ -26,7 +26,7 @@ bounded sample of the same workload, on this host's cores),
 sample, and its depth tables against the oracle's), per-kernel times, and
 beside the default workload the pelvis (`pelvis`, with its own error against
 the oracle over every row), the 32-plan batch (`batch32`), Eq. 1 (`eq1`),
-the rows beyond the plain path (`next_rows`) and the learned surrogate judged
+the rows beyond the plain path (`next_rows`) and the learned surrogate checked
 against the oracle (`surrogate`).
 """
 from __future__ import annotations
@@ -140,7 +140,7 @@ def _gpu_rows(indptr_h, indices, values, sel):
 
 class OracleError:
     """Error of the GPU rows against the oracle's, accumulated chunk by chunk: the 1e-4
-    relative bar is judged on entries above 1 % of the largest entry (taken as 0.99 % of
+    relative bar is applied to entries above 1 % of the largest entry (taken as 0.99 % of
     the GPU's largest, which is the larger set once the two maxima agree to 1e-4), eps is
     the mean absolute difference over common entries (the paper's measure, Sec. 3.1)."""
 
@@ -267,7 +267,7 @@ def surrogate_comparison(epochs, cpu=True):
     uniformly in the square-root feature coordinates, beamlet side
     log-uniform, 10 % at zero depth); both fills are timed with HIP events.
     With ``cpu`` the oracle computes every row of the plan (FP64), and both
-    fills are judged against it: the dose of a uniform fluence (Eq. 1; the
+    fills are compared with it: the dose of a uniform fluence (Eq. 1; the
     surrogate's target is a maximum dose error of 0.5 % of the maximum dose)
     and every coefficient (maximum and RMS error over entries above 1 % of the
     maximum, relative to the largest coefficient).

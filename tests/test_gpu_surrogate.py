@@ -114,7 +114,7 @@ def test_training_is_deterministic(torch_gpu):
 
 def test_fallback_outside_the_training_box(torch_gpu, oracle_lib):
     """Beamlets narrower than the box (a = 0.2) never use the network: the analytic
-    kernel's pattern and values, judged against the FP64 oracle at the 1e-4 bar on
+    kernel's pattern and values, checked against the FP64 oracle at the 1e-4 bar on
     every row.  The surrogate fill keeps the 8 KB erf table while the plain fill of
     a plan this small stages the mirrored one, so the two fills agree to the
     rounding of the two table forms (the network's own error is 1e-3 of the maximum)."""
@@ -143,7 +143,7 @@ def test_fallback_outside_the_training_box(torch_gpu, oracle_lib):
 
 
 def test_trained_surrogate_dose_on_pelvis(torch_gpu, oracle_lib):
-    """The surrogate trained with the shipped recipe, judged against the FP64 oracle.
+    """The surrogate trained with the shipped recipe, checked against the FP64 oracle.
 
     Pelvis, 9 beams, uniform fluence (Eq. 1): max dose error <= 0.5 % and RMS
     <= 0.1 % of the maximum dose; held-out kernel error <= 0.5 % of max K on
