@@ -23,6 +23,11 @@
  *
  * Everything is double precision; densities and the depth-dose table are read
  * as float and promoted.  Library routines used: erf, erfc, floor, sqrt, qsort.
+ *
+ * Parity unpinned: absolute coefficient values against the paper, which prints
+ * no D_ij, no fitted kernel parameters and no worked example.  The functions
+ * here are pinned instead by closed forms, symmetries, limits and brute force
+ * (tests/test_oracle_*.py).
  */
 #include <math.h>
 #include <stdint.h>
